@@ -93,19 +93,15 @@ def tr_subproblem(g, H, delta):
                 p = V @ pt
                 pred = g @ p + 0.5 * p @ H @ p
                 return p, pred, s, lam
+        # root of |p(s)| = delta on (s_lo, hi]; just above the pole the norm may already be
+        # inside (g nearly orthogonal to the bottom space): then that point is taken
+        s_a = s_lo + 1e-12 * scale if s_lo > 0 else 0.0
         f = lambda t: pnorm(t) - delta
-        a = s_lo + 1e-300
-        while f(a) < 0:   # g (numerically) lies off the bottom space only weakly
-            a = s_lo + (a - s_lo) * 0.5 if a > s_lo else s_lo
-            if a == s_lo:
-                break
-        b = max(s_lo, 0.0) + np.linalg.norm(g) / delta + 1.0
-        while f(b) > 0:
-            b *= 2.0
-        if f(a) <= 0:
-            s = a
+        if f(s_a) <= 0:
+            s = s_a
         else:
-            s = brentq(f, a, b, xtol=1e-15, rtol=1e-15, maxiter=500)
+            b = s_lo + np.linalg.norm(g) / delta + 1.0
+            s = brentq(f, s_a, b, xtol=1e-15, rtol=1e-15, maxiter=500)
         pt = gt / (lam + s)
     p = V @ pt
     pred = g @ p + 0.5 * p @ H @ p
