@@ -1,0 +1,210 @@
+/*
+ * celeste.h — C ABI of the MI355X (gfx950) Celeste ELBO / trust-region Newton library.
+ *
+ * Celeste (Regier et al., "Learning an Astronomical Catalog of the Visible Universe
+ * through Scalable Bayesian Inference", IPDPS 2017) infers a catalog of stars and
+ * galaxies from multi-band images.  Section III-A defines the model (Poisson pixel
+ * counts whose rates are a deterministic function of the catalog and each image's
+ * metadata), section III-B the variational objective (the ELBO of Eq. 1 under a
+ * mean-field q), its per-source decomposition with neighbours held fixed, and its
+ * optimisation by trust-region Newton with a hand-derived gradient and dense Hessian.
+ * Section III-C lists what one source needs: the images containing it, its initial
+ * estimate and its neighbours' estimates.  This header exports exactly that work.
+ *
+ * Conventions (all entry points):
+ *   - Return codes: CELESTE_OK (0) or a negative CELESTE_E_* code; the message of the
+ *     last failing call on the calling host thread is returned by celeste_last_error().
+ *     Non-convergence of a fit is a per-source status, not a call error.
+ *   - Ownership: every buffer is owned by the caller.  The library keeps no pointer
+ *     after a call returns.  Device scratch lives in the context and is reused.
+ *   - Memory kinds: celeste_batch.mem_kind says where the pixel arrays (and the theta /
+ *     output arrays passed with that batch) live: CELESTE_MEM_HOST or CELESTE_MEM_DEVICE
+ *     (device pointers of the context's device).  The metadata structs themselves
+ *     (images, offsets, prior, profiles, options, results) are always host memory.
+ *   - Threading: a context is not thread-safe; use one context per host thread.
+ *   - Precision: per-pixel arithmetic is FP32; pixel-sum accumulation, the ELBO, the
+ *     gradient, the Hessian and the 27x27 trust-region subproblem are FP64.
+ *
+ * Parameter vector (27 natural coordinates per source; derivatives are reported in
+ * these coordinates):
+ *   0,1   u: source-frame position (px)            2   a = q(source is a star)
+ *   3     e_dev: weight of the de Vaucouleurs profile   4 e_axis: minor/major ratio
+ *   5     e_angle: major-axis angle (rad, CCW from +x)   6 e_scale: half-light radius (px)
+ *   7,8   r1[star, galaxy]: mean of log reference-band (r) brightness (ln nMgy)
+ *   9,10  r2[star, galaxy]: variance of log reference-band brightness
+ *   11-14 c1[star][0..3], 15-18 c1[galaxy][0..3]: colour means (log ratios u/g.. of
+ *         adjacent bands: c_j = log(l_{j+1} / l_j), bands u,g,r,i,z = 0..4)
+ *   19-22 c2[star][0..3], 23-26 c2[galaxy][0..3]: colour variances (diagonal q)
+ * Hessians are row-major 27x27.
+ */
+#ifndef CELESTE_H
+#define CELESTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CELESTE_NP 27
+#define CELESTE_MAX_PSF 4
+#define CELESTE_MAX_PROTO 8
+
+enum {
+  CELESTE_OK = 0,
+  CELESTE_E_INVALID = -1,      /* bad shape, range, NaN, band, or count */
+  CELESTE_E_NOMEM = -2,        /* device or host allocation failed */
+  CELESTE_E_DEVICE = -3,       /* a HIP runtime call failed */
+  CELESTE_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+};
+
+enum { CELESTE_MEM_HOST = 0, CELESTE_MEM_DEVICE = 1 };
+
+enum {                          /* per-source fit status */
+  CELESTE_CONVERGED = 0,        /* predicted gain below tolerance at a concave point */
+  CELESTE_MAX_ITER = 1,         /* iteration cap reached */
+  CELESTE_TR_COLLAPSED = 2,     /* trust radius fell below delta_min */
+  CELESTE_NONFINITE = 3         /* the starting point has a non-finite ELBO */
+};
+
+enum { CELESTE_INIT_AS_GIVEN = 0, CELESTE_INIT_PLAIN = 1 };
+
+enum {                          /* context options (celeste_ctx_set_option) */
+  CELESTE_OPT_CHUNK_PX = 1,     /* pixels per work item (64 .. 2^24; default 4096) */
+  CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
+  CELESTE_OPT_USE_GRAPH = 3     /* batched fit replays a captured HIP graph per iteration (default 1) */
+};
+
+typedef struct celeste_ctx celeste_ctx;
+
+/* One band image cut-out ("patch") seen by one source (section III-A: image n has
+ * metadata Lambda_n and pixels x_nm ~ Poisson(F_nm)).  Pixel element (r, c) is centred
+ * at image-frame coordinates origin + (c, r); the model density is sampled there. */
+typedef struct celeste_image {
+  int32_t band;                 /* 0..4 = u,g,r,i,z (reference band r = 2) */
+  int32_t h, w;                 /* patch rows and columns, >= 1 */
+  int32_t pitch;                /* elements between rows of pixels/nbr arrays, >= w */
+  int32_t n_psf;                /* PSF mixture components, 1..CELESTE_MAX_PSF */
+  int32_t reserved;             /* must be 0 */
+  double origin[2];             /* image-frame (x, y) of element (0,0)'s centre */
+  double wcs[6];                /* p = A u + b: A row-major 2x2 (wcs[0..3]), b (wcs[4..5]) */
+  double sky;                   /* sky level epsilon_n, counts per pixel, > 0 */
+  double calib;                 /* iota_n, counts per nMgy, > 0 */
+  double psf[CELESTE_MAX_PSF][6]; /* weight, mean_x, mean_y, cov_xx, cov_xy, cov_yy (px) */
+  const float* pixels;          /* counts x_nm, h rows of `pitch` floats */
+  const float* nbr_mean;        /* optional fixed E[F] of other sources (counts/px), or NULL */
+  const float* nbr_var;         /* optional fixed Var[F] of other sources, or NULL */
+} celeste_image;
+
+/* Prior parameters Phi (P(star)), Upsilon (lognormal brightness) and Xi (colours),
+ * section III-A; index 0 = star, 1 = galaxy. */
+typedef struct celeste_prior {
+  double p_star;
+  double r_mean[2], r_var[2];   /* normal prior on log r-band brightness */
+  double c_mean[2][4];
+  double c_cov[2][4][4];        /* full colour covariance, symmetric positive definite */
+} celeste_prior;
+
+/* Galaxy prototype profiles: exponential and de Vaucouleurs, each a mixture of
+ * isotropic zero-mean Gaussians with amplitude amp[j] and variance var[j] in units
+ * of the half-light radius squared.  Amplitudes of each mixture sum to 1. */
+typedef struct celeste_profiles {
+  int32_t n_exp, n_dev;         /* 1..CELESTE_MAX_PROTO each */
+  double exp_amp[CELESTE_MAX_PROTO], exp_var[CELESTE_MAX_PROTO];
+  double dev_amp[CELESTE_MAX_PROTO], dev_var[CELESTE_MAX_PROTO];
+} celeste_profiles;
+
+/* A batch of independent sources (section III-B: each source is optimised with the
+ * others held fixed).  Source s owns images[image_offsets[s] .. image_offsets[s+1]). */
+typedef struct celeste_batch {
+  int32_t n_sources;            /* >= 1 */
+  int32_t mem_kind;             /* CELESTE_MEM_HOST or CELESTE_MEM_DEVICE */
+  const int64_t* image_offsets; /* host, n_sources + 1 entries, non-decreasing, [0] = 0 */
+  const celeste_image* images;  /* host array of image_offsets[n_sources] entries */
+  const celeste_prior* prior;   /* host */
+  const celeste_profiles* profiles; /* host */
+} celeste_batch;
+
+typedef struct celeste_fit_opts {
+  int32_t max_iter;             /* trust-region iterations, >= 1 (default 50) */
+  int32_t init_mode;            /* CELESTE_INIT_AS_GIVEN or CELESTE_INIT_PLAIN */
+  double pred_rtol;             /* converged when predicted gain <= pred_rtol * max(1,|L|) (1e-8) */
+  double curv_tol;              /* ... and lambda_min(-H) >= -curv_tol * max(1, |lambda|max) (1e-8) */
+  double delta0, delta_max, delta_min;  /* trust radius: start 1, cap 100, collapse 1e-10 */
+  double eta;                   /* acceptance threshold on rho (0.1) */
+  double u_box;                 /* half-width (px) of the position box around the start (3) */
+  int32_t poll_every;           /* batched fit: iterations between host reads of the active count */
+  int32_t reserved;
+} celeste_fit_opts;
+
+typedef struct celeste_fit_result {
+  double elbo;                  /* ELBO at the returned parameters */
+  double pred_gain;             /* last predicted gain of the trust-region model */
+  double delta;                 /* final trust radius */
+  int32_t iters;                /* trust-region iterations taken */
+  int32_t status;               /* CELESTE_CONVERGED, ... */
+  int32_t n_full_evals;         /* value+gradient+Hessian evaluations */
+  int32_t flags;                /* reserved, 0 */
+} celeste_fit_result;
+
+/* Create a context on HIP device `hip_device` (makes it current).  *out receives the
+ * context; destroy it with celeste_ctx_destroy.  Errors: E_INVALID (bad device),
+ * E_DEVICE, E_NOMEM. */
+int celeste_ctx_create(int hip_device, celeste_ctx** out);
+void celeste_ctx_destroy(celeste_ctx* ctx);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* celeste_last_error(void);
+
+/* Set a tuning option of the context (CELESTE_OPT_*).  Results do not depend on the
+ * block size; the chunk size changes only the FP64 summation grouping.  Errors:
+ * E_INVALID (unknown option or value out of range). */
+int celeste_ctx_set_option(celeste_ctx* ctx, int option, int64_t value);
+
+/* sizeof of the ABI structs, for bindings to check their layouts: 0 celeste_image,
+ * 1 celeste_prior, 2 celeste_profiles, 3 celeste_batch, 4 celeste_fit_opts,
+ * 5 celeste_fit_result; 0 for any other value. */
+size_t celeste_struct_size(int which);
+
+/* Defaults for celeste_fit_opts (values in the comments above). */
+void celeste_fit_opts_default(celeste_fit_opts* opts);
+
+/* ELBO, gradient and dense Hessian of every source of the batch at theta
+ * (sections III-A/B: L = sum over the source's images and pixels of the expected
+ * Poisson log-likelihood, with E[log F] by the second-order delta method, minus the
+ * Kullback-Leibler terms of q(a), q(r|a), q(c|a) from their priors).
+ *   theta : n_sources x 27 (natural coordinates)
+ *   elbo  : n_sources
+ *   grad  : n_sources x 27, or NULL
+ *   hess  : n_sources x 27 x 27 row-major, or NULL (requires grad)
+ *   stream: hipStream_t to run on, or NULL for the context's stream.  The call
+ *           returns after the results are written (host or device memory).
+ * Pixel arrays are checked on the device first: any negative or non-finite pixel or
+ * neighbour value makes the call fail with E_INVALID before any evaluation.
+ * Errors: E_INVALID (validation; nothing is launched), E_DEVICE, E_NOMEM. */
+int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                      double* elbo, double* grad, double* hess, void* stream);
+
+/* Trust-region Newton fit of ONE source (batch->n_sources must be 1), host-driven:
+ * one host/device round trip per iteration (section III-B).  theta_inout: 27 natural
+ * coordinates in (start) and out (result), in batch->mem_kind memory.  Returns the
+ * per-source status in *result.  Errors as for celeste_elbo_eval. */
+int celeste_newton_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
+                       const celeste_fit_opts* opts, celeste_fit_result* result);
+
+/* Trust-region Newton fit of all sources of the batch at once: every iteration is one
+ * launch per step over all still-active sources (ragged images and patch sizes),
+ * per-source trust-region state stays on the device, and iterations are replayed from
+ * a captured HIP graph.  theta_inout: n_sources x 27 (batch->mem_kind memory);
+ * results: host array of n_sources.  With init_mode CELESTE_INIT_PLAIN the start is
+ * computed on the device from the data (theta_inout's u entries give the catalog
+ * position).  Errors as for celeste_elbo_eval. */
+int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
+                      const celeste_fit_opts* opts, celeste_fit_result* results, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELESTE_H */

@@ -1,0 +1,263 @@
+"""Python binding of libceleste (argument marshalling only).
+
+Every step of the ELBO evaluation and of the trust-region fits runs in the HIP
+library; this module only builds the C structs, passes pointers and reads back
+results.  It raises if the library is missing: there is no other code path.
+
+Batches are given as structure-of-arrays (one entry per image, CSR offsets per
+source).  Pixels given as a NumPy array make a host-memory batch (the library
+stages them to the device); a torch tensor on a GPU makes a device-memory batch,
+and theta / outputs are then torch tensors on the same device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libceleste.so")
+
+NP = 27
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4
+MEM_HOST, MEM_DEVICE = 0, 1
+CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE = 0, 1, 2, 3
+INIT_AS_GIVEN, INIT_PLAIN = 0, 1
+OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH = 1, 2, 3
+
+IMAGE_DT = np.dtype([
+    ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("reserved", "<i4"),
+    ("origin", "<f8", (2,)), ("wcs", "<f8", (6,)), ("sky", "<f8"), ("calib", "<f8"), ("psf", "<f8", (4, 6)),
+    ("pixels", "<u8"), ("nbr_mean", "<u8"), ("nbr_var", "<u8"),
+])
+PRIOR_DT = np.dtype([("p_star", "<f8"), ("r_mean", "<f8", (2,)), ("r_var", "<f8", (2,)),
+                     ("c_mean", "<f8", (2, 4)), ("c_cov", "<f8", (2, 4, 4))])
+PROF_DT = np.dtype([("n_exp", "<i4"), ("n_dev", "<i4"), ("exp_amp", "<f8", (8,)), ("exp_var", "<f8", (8,)),
+                    ("dev_amp", "<f8", (8,)), ("dev_var", "<f8", (8,))])
+RESULT_DT = np.dtype([("elbo", "<f8"), ("pred_gain", "<f8"), ("delta", "<f8"), ("iters", "<i4"),
+                      ("status", "<i4"), ("n_full_evals", "<i4"), ("flags", "<i4")])
+
+
+class CBatch(ctypes.Structure):
+    _fields_ = [("n_sources", ctypes.c_int32), ("mem_kind", ctypes.c_int32), ("image_offsets", ctypes.c_void_p),
+                ("images", ctypes.c_void_p), ("prior", ctypes.c_void_p), ("profiles", ctypes.c_void_p)]
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("pred_rtol", ctypes.c_double),
+                ("curv_tol", ctypes.c_double), ("delta0", ctypes.c_double), ("delta_max", ctypes.c_double),
+                ("delta_min", ctypes.c_double), ("eta", ctypes.c_double), ("u_box", ctypes.c_double),
+                ("poll_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CelesteError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libceleste error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libceleste.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1611_03404_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.celeste_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.celeste_ctx_destroy.argtypes = [vp]
+    lib.celeste_ctx_destroy.restype = None
+    lib.celeste_last_error.restype = ctypes.c_char_p
+    lib.celeste_ctx_set_option.argtypes = [vp, ctypes.c_int, i64]
+    lib.celeste_struct_size.argtypes = [ctypes.c_int]
+    lib.celeste_struct_size.restype = ctypes.c_size_t
+    lib.celeste_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
+    lib.celeste_fit_opts_default.restype = None
+    lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
+    lib.celeste_newton_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
+    lib.celeste_batch_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp, vp]
+    for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
+                 "celeste_batch_fit"):
+        getattr(lib, name).restype = ctypes.c_int
+    sizes = [lib.celeste_struct_size(k) for k in range(6)]
+    expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
+              ctypes.sizeof(FitOpts), RESULT_DT.itemsize]
+    if sizes != expect:
+        raise RuntimeError(f"ABI struct sizes differ: library {sizes}, binding {expect}")
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != OK:
+        raise CelesteError(code, load().celeste_last_error().decode())
+
+
+def default_opts(**kw):
+    o = FitOpts()
+    load().celeste_fit_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if _is_torch(x):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+class Batch:
+    """ABI batch from structure-of-arrays image metadata (keeps its arrays alive)."""
+
+    def __init__(self, src_img_off, band, h, w, pitch, origin, wcs, sky, calib, psf, npsf, pixels, pix_off,
+                 prior, profiles, nbr_mean=None, nbr_var=None, nbr_off=None):
+        n_img = int(len(band))
+        self.device = _is_torch(pixels) and pixels.is_cuda
+        if self.device:
+            if pixels.dtype.__repr__() != "torch.float32" or not pixels.is_contiguous():
+                raise ValueError("device pixels must be a contiguous float32 tensor")
+        else:
+            pixels = np.ascontiguousarray(pixels, dtype=np.float32)
+        self._keep = [pixels]
+        img = np.zeros(n_img, dtype=IMAGE_DT)
+        img["band"] = band
+        img["h"] = h
+        img["w"] = w
+        img["pitch"] = pitch
+        img["n_psf"] = npsf
+        img["origin"] = origin
+        img["wcs"] = wcs
+        img["sky"] = sky
+        img["calib"] = calib
+        K = psf.shape[1]
+        img["psf"][:, :K, :] = psf
+        base = _ptr(pixels)
+        img["pixels"] = base + 4 * np.asarray(pix_off, dtype=np.uint64)
+        for name, arr in (("nbr_mean", nbr_mean), ("nbr_var", nbr_var)):
+            if arr is not None:
+                if not self.device:
+                    arr = np.ascontiguousarray(arr, dtype=np.float32)
+                self._keep.append(arr)
+                off = pix_off if nbr_off is None else nbr_off
+                img[name] = _ptr(arr) + 4 * np.asarray(off, dtype=np.uint64)
+        pr = np.zeros(1, dtype=PRIOR_DT)
+        pr["p_star"] = prior["p_star"]
+        pr["r_mean"] = prior["r_mean"]
+        pr["r_var"] = prior["r_var"]
+        pr["c_mean"] = prior["c_mean"]
+        pr["c_cov"] = prior["c_cov"]
+        pf = np.zeros(1, dtype=PROF_DT)
+        ea, ev = profiles["exp"]
+        da, dv = profiles["dev"]
+        pf["n_exp"], pf["n_dev"] = len(ea), len(da)
+        pf["exp_amp"][0, :len(ea)] = ea
+        pf["exp_var"][0, :len(ev)] = ev
+        pf["dev_amp"][0, :len(da)] = da
+        pf["dev_var"][0, :len(dv)] = dv
+        self.offsets = np.ascontiguousarray(src_img_off, dtype=np.int64)
+        self.images, self.prior, self.profiles = img, pr, pf
+        self.n_sources = len(self.offsets) - 1
+        self.c = CBatch(self.n_sources, MEM_DEVICE if self.device else MEM_HOST, self.offsets.ctypes.data,
+                        img.ctypes.data, pr.ctypes.data, pf.ctypes.data)
+        self.torch_device = pixels.device if self.device else None
+
+    @classmethod
+    def from_synth(cls, sb, nbr=None):
+        """From a synth.SynthBatch (pixels host ndarray or device tensor)."""
+        kw = {}
+        if nbr is not None:
+            kw = dict(nbr_mean=nbr[0], nbr_var=nbr[1], nbr_off=nbr[2] if len(nbr) > 2 else None)
+        return cls(sb.src_img_off, sb.img_band, sb.img_h, sb.img_w, sb.img_pitch, sb.img_origin, sb.img_wcs,
+                   sb.img_sky, sb.img_calib, sb.img_psf, sb.img_npsf, sb.pixels, sb.img_pix_off, sb.prior,
+                   sb.profiles, **kw)
+
+    def array(self, shape):
+        """An output array of the batch's memory kind."""
+        if self.device:
+            import torch
+            return torch.empty(shape, dtype=torch.float64, device=self.torch_device)
+        return np.empty(shape, dtype=np.float64)
+
+    def as_input(self, x):
+        if self.device:
+            import torch
+            return torch.as_tensor(np.asarray(x) if not _is_torch(x) else x, dtype=torch.float64,
+                                   device=self.torch_device).contiguous()
+        return np.ascontiguousarray(x.cpu().numpy() if _is_torch(x) else x, dtype=np.float64)
+
+
+class Context:
+    def __init__(self, device=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.celeste_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            load().celeste_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option, value):
+        _check(load().celeste_ctx_set_option(self._h, int(option), int(value)))
+
+    def _stream(self, batch):
+        # Work on device tensors queued by torch must be complete before the library's
+        # own (non-blocking) stream reads them; the library synchronises before returning.
+        if batch.device:
+            import torch
+            torch.cuda.synchronize(batch.torch_device)
+        return None
+
+    def elbo_eval(self, batch: Batch, theta, want="hess"):
+        """ELBO (S,), gradient (S,27) and Hessian (S,27,27) at theta (S,27); want in {value, grad, hess}."""
+        S = batch.n_sources
+        th = batch.as_input(theta)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta must have shape ({S}, {NP})")
+        elbo = batch.array((S,))
+        grad = batch.array((S, NP)) if want in ("grad", "hess") else None
+        hess = batch.array((S, NP, NP)) if want == "hess" else None
+        _check(load().celeste_elbo_eval(self._h, ctypes.byref(batch.c), _ptr(th), _ptr(elbo),
+                                        _ptr(grad) if grad is not None else None,
+                                        _ptr(hess) if hess is not None else None, self._stream(batch)))
+        return elbo, grad, hess
+
+    def newton_fit(self, batch: Batch, theta0, opts=None):
+        if batch.n_sources != 1:
+            raise ValueError("newton_fit takes one source")
+        th = batch.as_input(np.asarray(theta0).reshape(1, NP) if not _is_torch(theta0) else theta0.reshape(1, NP))
+        res = np.zeros(1, dtype=RESULT_DT)
+        o = opts if opts is not None else default_opts()
+        self._stream(batch)
+        _check(load().celeste_newton_fit(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o),
+                                         res.ctypes.data))
+        return th, res[0]
+
+    def batch_fit(self, batch: Batch, theta0, opts=None):
+        S = batch.n_sources
+        th = batch.as_input(theta0)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta0 must have shape ({S}, {NP})")
+        res = np.zeros(S, dtype=RESULT_DT)
+        o = opts if opts is not None else default_opts()
+        _check(load().celeste_batch_fit(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o),
+                                        res.ctypes.data, self._stream(batch)))
+        return th, res

@@ -1,0 +1,704 @@
+// Host side of libceleste: the C ABI, argument validation, packing of ragged
+// batches into device metadata (sources -> images -> work items), and the
+// drivers of the evaluation and of the trust-region fits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "celeste_internal.h"
+
+using namespace celeste;
+
+namespace celeste {
+hipError_t launch_fit_start(FitDev st, int n_src, hipStream_t s);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail(CELESTE_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(x)                 \
+  do {                         \
+    int r_ = (x);              \
+    if (r_ != CELESTE_OK) return r_; \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct celeste_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int chunk_px = 4096;
+  int block = 256;
+  int use_graph = 1;
+  DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
+  DevBuf st_buf;   // all trust-region state in one allocation
+};
+
+namespace {
+
+int ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (bytes <= b.cap) return CELESTE_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CELESTE_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  b.cap = bytes;
+  return CELESTE_OK;
+}
+
+template <class T>
+T* as(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Cholesky of a symmetric 4x4; false if not positive definite.
+bool chol4(const double A[4][4], double L[4][4]) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) L[i][j] = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    double d = A[j][j];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) return false;
+    L[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < 4; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  return true;
+}
+
+int make_prior(const celeste_prior* p, PriorDev* d) {
+  if (!p) return fail(CELESTE_E_INVALID, "prior is NULL");
+  if (!(p->p_star > 0.0 && p->p_star < 1.0)) return fail(CELESTE_E_INVALID, "prior p_star must lie in (0,1)");
+  std::memset(d, 0, sizeof(*d));
+  d->p_star = p->p_star;
+  for (int t = 0; t < 2; ++t) {
+    if (!finite(p->r_mean[t]) || !(p->r_var[t] > 0.0) || !finite(p->r_var[t]))
+      return fail(CELESTE_E_INVALID, "prior r_mean/r_var[%d] invalid", t);
+    d->r_mean[t] = p->r_mean[t];
+    d->r_var[t] = p->r_var[t];
+    for (int j = 0; j < 4; ++j) {
+      if (!finite(p->c_mean[t][j])) return fail(CELESTE_E_INVALID, "prior c_mean not finite");
+      d->c_mean[t][j] = p->c_mean[t][j];
+      d->c_diag[t][j] = p->c_cov[t][j][j];
+      for (int k = 0; k < 4; ++k)
+        if (!finite(p->c_cov[t][j][k]) || p->c_cov[t][j][k] != p->c_cov[t][k][j])
+          return fail(CELESTE_E_INVALID, "prior c_cov[%d] must be finite and symmetric", t);
+    }
+    double L[4][4];
+    if (!chol4(p->c_cov[t], L)) return fail(CELESTE_E_INVALID, "prior c_cov[%d] not positive definite", t);
+    double ld = 0.0;
+    for (int j = 0; j < 4; ++j) ld += 2.0 * std::log(L[j][j]);
+    d->c_logdet[t] = ld;
+    // inverse from the Cholesky factor: solve L L^T X = I
+    for (int c = 0; c < 4; ++c) {
+      double y[4], x[4];
+      for (int i = 0; i < 4; ++i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+      }
+      for (int i = 3; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < 4; ++k) v -= L[k][i] * x[k];
+        x[i] = v / L[i][i];
+      }
+      for (int i = 0; i < 4; ++i) d->c_inv[t][i][c] = x[i];
+    }
+  }
+  return CELESTE_OK;
+}
+
+int make_profiles(const celeste_profiles* p, ProfDev* d) {
+  if (!p) return fail(CELESTE_E_INVALID, "profiles is NULL");
+  if (p->n_exp < 1 || p->n_exp > CELESTE_MAX_PROTO || p->n_dev < 1 || p->n_dev > CELESTE_MAX_PROTO)
+    return fail(CELESTE_E_INVALID, "profile component counts must be in 1..%d", CELESTE_MAX_PROTO);
+  std::memset(d, 0, sizeof(*d));
+  d->n_exp = p->n_exp;
+  d->n_dev = p->n_dev;
+  for (int j = 0; j < p->n_exp; ++j) {
+    if (!(p->exp_amp[j] >= 0.0) || !finite(p->exp_amp[j]) || !(p->exp_var[j] > 0.0) || !finite(p->exp_var[j]))
+      return fail(CELESTE_E_INVALID, "exp profile component %d invalid", j);
+    d->amp[j] = p->exp_amp[j];
+    d->var[j] = p->exp_var[j];
+  }
+  for (int j = 0; j < p->n_dev; ++j) {
+    if (!(p->dev_amp[j] >= 0.0) || !finite(p->dev_amp[j]) || !(p->dev_var[j] > 0.0) || !finite(p->dev_var[j]))
+      return fail(CELESTE_E_INVALID, "dev profile component %d invalid", j);
+    d->amp[p->n_exp + j] = p->dev_amp[j];
+    d->var[p->n_exp + j] = p->dev_var[j];
+  }
+  return CELESTE_OK;
+}
+
+int check_image(const celeste_image& im, int64_t idx) {
+  if (im.band < 0 || im.band > 4) return fail(CELESTE_E_INVALID, "image %lld: band %d not in 0..4", (long long)idx, im.band);
+  if (im.h < 1 || im.w < 1 || im.pitch < im.w)
+    return fail(CELESTE_E_INVALID, "image %lld: bad shape h=%d w=%d pitch=%d", (long long)idx, im.h, im.w, im.pitch);
+  if ((int64_t)im.h * im.w > (int64_t)1 << 30) return fail(CELESTE_E_INVALID, "image %lld: patch too large", (long long)idx);
+  if (im.n_psf < 1 || im.n_psf > CELESTE_MAX_PSF)
+    return fail(CELESTE_E_INVALID, "image %lld: n_psf %d not in 1..%d", (long long)idx, im.n_psf, CELESTE_MAX_PSF);
+  if (im.reserved != 0) return fail(CELESTE_E_INVALID, "image %lld: reserved field must be 0", (long long)idx);
+  if (!im.pixels) return fail(CELESTE_E_INVALID, "image %lld: pixels is NULL", (long long)idx);
+  if (!(im.sky > 0.0) || !finite(im.sky) || !(im.calib > 0.0) || !finite(im.calib))
+    return fail(CELESTE_E_INVALID, "image %lld: sky and calib must be positive and finite", (long long)idx);
+  for (int k = 0; k < 2; ++k)
+    if (!finite(im.origin[k])) return fail(CELESTE_E_INVALID, "image %lld: origin not finite", (long long)idx);
+  for (int k = 0; k < 6; ++k)
+    if (!finite(im.wcs[k])) return fail(CELESTE_E_INVALID, "image %lld: wcs not finite", (long long)idx);
+  if (std::fabs(im.wcs[0] * im.wcs[3] - im.wcs[1] * im.wcs[2]) < 1e-12)
+    return fail(CELESTE_E_INVALID, "image %lld: singular WCS matrix", (long long)idx);
+  for (int k = 0; k < im.n_psf; ++k) {
+    const double* p = im.psf[k];
+    for (int j = 0; j < 6; ++j)
+      if (!finite(p[j])) return fail(CELESTE_E_INVALID, "image %lld: psf not finite", (long long)idx);
+    if (!(p[0] >= 0.0) || !(p[3] > 0.0) || !(p[5] > 0.0) || !(p[3] * p[5] - p[4] * p[4] > 0.0))
+      return fail(CELESTE_E_INVALID, "image %lld: psf component %d needs weight >= 0 and a PD covariance",
+                  (long long)idx, k);
+  }
+  return CELESTE_OK;
+}
+
+int check_theta(const double* th, int64_t s) {
+  for (int i = 0; i < NP; ++i)
+    if (!finite(th[i])) return fail(CELESTE_E_INVALID, "theta[%lld][%d] not finite", (long long)s, i);
+  if (!(th[2] > 0.0 && th[2] < 1.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: a must lie in (0,1)", (long long)s);
+  if (!(th[3] >= 0.0 && th[3] <= 1.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: e_dev must lie in [0,1]", (long long)s);
+  if (!(th[4] > 0.0 && th[4] <= 1.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: e_axis must lie in (0,1]", (long long)s);
+  if (!(th[6] > 0.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: e_scale must be > 0", (long long)s);
+  for (int i : {9, 10})
+    if (!(th[i] > 0.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: r2 must be > 0", (long long)s);
+  for (int i = 19; i < NP; ++i)
+    if (!(th[i] > 0.0)) return fail(CELESTE_E_INVALID, "theta[%lld]: c2 must be > 0", (long long)s);
+  return CELESTE_OK;
+}
+
+struct Packed {
+  std::vector<ImgDev> imgs;
+  std::vector<WorkItem> items;
+  std::vector<SrcDev> srcs;
+  PriorDev prior;
+  ProfDev prof;
+  int tstride = 0;
+  int n_src = 0, n_img = 0, n_items = 0;
+};
+
+int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  if (!b) return fail(CELESTE_E_INVALID, "batch is NULL");
+  if (b->n_sources < 1) return fail(CELESTE_E_INVALID, "n_sources must be >= 1");
+  if (b->mem_kind != CELESTE_MEM_HOST && b->mem_kind != CELESTE_MEM_DEVICE)
+    return fail(CELESTE_E_INVALID, "mem_kind must be CELESTE_MEM_HOST or CELESTE_MEM_DEVICE");
+  if (!b->image_offsets || !b->images) return fail(CELESTE_E_INVALID, "image_offsets/images is NULL");
+  if (b->image_offsets[0] != 0) return fail(CELESTE_E_INVALID, "image_offsets[0] must be 0");
+  for (int s = 0; s < b->n_sources; ++s) {
+    if (b->image_offsets[s + 1] < b->image_offsets[s])
+      return fail(CELESTE_E_INVALID, "image_offsets must be non-decreasing");
+    if (b->image_offsets[s + 1] == b->image_offsets[s])
+      return fail(CELESTE_E_INVALID, "source %d has no images", s);
+  }
+  const int64_t n_img = b->image_offsets[b->n_sources];
+  if (n_img > (int64_t)1 << 30) return fail(CELESTE_E_INVALID, "too many images");
+  CHK(make_prior(b->prior, &P->prior));
+  CHK(make_profiles(b->profiles, &P->prof));
+  int max_psf = 1;
+  for (int64_t i = 0; i < n_img; ++i) {
+    CHK(check_image(b->images[i], i));
+    max_psf = std::max(max_psf, b->images[i].n_psf);
+  }
+  P->tstride = table_stride(max_psf, P->prof.n_exp, P->prof.n_dev);
+  P->n_src = b->n_sources;
+  P->n_img = (int)n_img;
+  P->imgs.resize(n_img);
+  P->srcs.resize(b->n_sources);
+  P->items.clear();
+  const int chunk = std::max(64, ctx->chunk_px);
+  for (int s = 0; s < b->n_sources; ++s) {
+    SrcDev sd;
+    sd.img_begin = (int)b->image_offsets[s];
+    sd.img_end = (int)b->image_offsets[s + 1];
+    sd.item_begin = (int)P->items.size();
+    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) {
+      const celeste_image& im = b->images[i];
+      ImgDev& d = P->imgs[i];
+      std::memset(&d, 0, sizeof(d));
+      d.pix = im.pixels;
+      d.nbr_mean = im.nbr_mean;
+      d.nbr_var = im.nbr_var;
+      d.h = im.h;
+      d.w = im.w;
+      d.pitch = im.pitch;
+      d.band = im.band;
+      d.n_psf = im.n_psf;
+      d.src = s;
+      d.origin[0] = im.origin[0];
+      d.origin[1] = im.origin[1];
+      for (int k = 0; k < 6; ++k) d.wcs[k] = im.wcs[k];
+      d.sky = im.sky;
+      d.calib = im.calib;
+      for (int k = 0; k < CELESTE_MAX_PSF; ++k)
+        for (int j = 0; j < 6; ++j) d.psf[k][j] = k < im.n_psf ? im.psf[k][j] : 0.0;
+      d.item_begin = (int)P->items.size();
+      const int n = im.h * im.w;
+      for (int a = 0; a < n; a += chunk) P->items.push_back(WorkItem{(int)i, s, a, std::min(n, a + chunk)});
+      d.item_end = (int)P->items.size();
+    }
+    sd.item_end = (int)P->items.size();
+    P->srcs[s] = sd;
+  }
+  if (P->items.size() > (size_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
+  P->n_items = (int)P->items.size();
+  return CELESTE_OK;
+}
+
+// Copies host pixel arrays into one device staging buffer and repoints the images.
+int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st) {
+  size_t total = 0;
+  for (int i = 0; i < P->n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const size_t n = (size_t)im.h * im.w;
+    total += n * (1 + (im.nbr_mean ? 1 : 0) + (im.nbr_var ? 1 : 0));
+  }
+  std::vector<float> host(total);
+  size_t off = 0;
+  std::vector<size_t> offs(3 * P->n_img, (size_t)-1);
+  for (int i = 0; i < P->n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const float* srcs[3] = {im.pixels, im.nbr_mean, im.nbr_var};
+    for (int k = 0; k < 3; ++k) {
+      if (!srcs[k]) continue;
+      offs[3 * i + k] = off;
+      for (int r = 0; r < im.h; ++r) std::memcpy(&host[off + (size_t)r * im.w], srcs[k] + (size_t)r * im.pitch, sizeof(float) * im.w);
+      off += (size_t)im.h * im.w;
+    }
+  }
+  CHK(ensure(ctx->staging, total * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(ctx->staging.p, host.data(), total * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float* base = as<float>(ctx->staging);
+  for (int i = 0; i < P->n_img; ++i) {
+    ImgDev& d = P->imgs[i];
+    d.pitch = d.w;
+    d.pix = base + offs[3 * i];
+    d.nbr_mean = offs[3 * i + 1] != (size_t)-1 ? base + offs[3 * i + 1] : nullptr;
+    d.nbr_var = offs[3 * i + 2] != (size_t)-1 ? base + offs[3 * i + 2] : nullptr;
+  }
+  return CELESTE_OK;
+}
+
+// Metadata upload + pixel validation + per-image constants.  Synchronous.
+int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st) {
+  if (b->mem_kind == CELESTE_MEM_HOST) CHK(stage_host_pixels(ctx, b, P, st));
+  CHK(ensure(ctx->imgs, sizeof(ImgDev) * P->n_img));
+  CHK(ensure(ctx->items, sizeof(WorkItem) * P->n_items));
+  CHK(ensure(ctx->srcs, sizeof(SrcDev) * P->n_src));
+  CHK(ensure(ctx->img_const, sizeof(double) * P->n_img));
+  CHK(ensure(ctx->tables, sizeof(float) * (size_t)P->tstride * P->n_img));
+  CHK(ensure(ctx->partials, sizeof(double) * (size_t)NACC * P->n_items));
+  CHK(ensure(ctx->flag, sizeof(int) * 4));
+  HIPCHK(hipMemcpyAsync(ctx->imgs.p, P->imgs.data(), sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->items.p, P->items.data(), sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->srcs.p, P->srcs.data(), sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_zero_int(as<int>(ctx->flag), 4, st));
+  HIPCHK(launch_check_pixels(as<ImgDev>(ctx->imgs), P->n_img, as<int>(ctx->flag), st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(CELESTE_E_INVALID, "pixel or neighbour arrays hold negative or non-finite values");
+  HIPCHK(launch_const(as<ImgDev>(ctx->imgs), P->n_img, as<double>(ctx->img_const), st));
+  return CELESTE_OK;
+}
+
+hipStream_t pick(celeste_ctx* ctx, void* stream) { return stream ? (hipStream_t)stream : ctx->stream; }
+
+}  // namespace
+
+// =============================================================================== ABI
+
+extern "C" {
+
+const char* celeste_last_error(void) { return g_err.c_str(); }
+
+void celeste_fit_opts_default(celeste_fit_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iter = 50;
+  o->init_mode = CELESTE_INIT_AS_GIVEN;
+  o->pred_rtol = 1e-8;
+  o->curv_tol = 1e-8;
+  o->delta0 = 1.0;
+  o->delta_max = 100.0;
+  o->delta_min = 1e-10;
+  o->eta = 0.1;
+  o->u_box = 3.0;
+  o->poll_every = 4;
+}
+
+int celeste_ctx_create(int hip_device, celeste_ctx** out) {
+  if (!out) return fail(CELESTE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(CELESTE_E_INVALID, "device %d not in 0..%d", hip_device, n - 1);
+  HIPCHK(hipSetDevice(hip_device));
+  celeste_ctx* c = new (std::nothrow) celeste_ctx();
+  if (!c) return fail(CELESTE_E_NOMEM, "context allocation failed");
+  c->device = hip_device;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(CELESTE_E_DEVICE, "stream creation failed");
+  }
+  *out = c;
+  return CELESTE_OK;
+}
+
+void celeste_ctx_destroy(celeste_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
+                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
+  if (!c) return fail(CELESTE_E_INVALID, "context is NULL");
+  switch (option) {
+    case CELESTE_OPT_CHUNK_PX:
+      if (value < 64 || value > (1 << 24)) return fail(CELESTE_E_INVALID, "chunk_px must be in 64..2^24");
+      c->chunk_px = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_BLOCK:
+      if (value != 128 && value != 256) return fail(CELESTE_E_INVALID, "block must be 128 or 256");
+      c->block = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_USE_GRAPH:
+      c->use_graph = value ? 1 : 0;
+      return CELESTE_OK;
+    default:
+      return fail(CELESTE_E_INVALID, "unknown option %d", option);
+  }
+}
+
+size_t celeste_struct_size(int which) {
+  switch (which) {
+    case 0: return sizeof(celeste_image);
+    case 1: return sizeof(celeste_prior);
+    case 2: return sizeof(celeste_profiles);
+    case 3: return sizeof(celeste_batch);
+    case 4: return sizeof(celeste_fit_opts);
+    case 5: return sizeof(celeste_fit_result);
+    default: return 0;
+  }
+}
+
+int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
+                      double* hess, void* stream) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  if (!theta || !elbo) return fail(CELESTE_E_INVALID, "theta and elbo must not be NULL");
+  if (hess && !grad) return fail(CELESTE_E_INVALID, "hess requires grad");
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = pick(ctx, stream);
+  const size_t S = P.n_src;
+  std::vector<double> th_host;
+  const double* th_dev = theta;
+  if (b->mem_kind == CELESTE_MEM_HOST) {
+    for (size_t s = 0; s < S; ++s) CHK(check_theta(theta + s * NP, (int64_t)s));
+    CHK(ensure(ctx->theta, sizeof(double) * NP * S));
+    HIPCHK(hipMemcpyAsync(ctx->theta.p, theta, sizeof(double) * NP * S, hipMemcpyHostToDevice, st));
+    th_dev = as<double>(ctx->theta);
+  } else {
+    th_host.resize(NP * S);
+    HIPCHK(hipMemcpyAsync(th_host.data(), theta, sizeof(double) * NP * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t s = 0; s < S; ++s) CHK(check_theta(th_host.data() + s * NP, (int64_t)s));
+  }
+  CHK(prepare(ctx, b, &P, st));
+  double *d_elbo = elbo, *d_grad = grad, *d_hess = hess;
+  if (b->mem_kind == CELESTE_MEM_HOST) {
+    CHK(ensure(ctx->o_elbo, sizeof(double) * S));
+    d_elbo = as<double>(ctx->o_elbo);
+    if (grad) {
+      CHK(ensure(ctx->o_grad, sizeof(double) * NP * S));
+      d_grad = as<double>(ctx->o_grad);
+    }
+    if (hess) {
+      CHK(ensure(ctx->o_hess, sizeof(double) * NP * NP * S));
+      d_hess = as<double>(ctx->o_hess);
+    }
+  }
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  HIPCHK(launch_setup(imgs, P.n_img, th_dev, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  if (grad) {
+    HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+    HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
+                              as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess, st));
+  } else {
+    HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+    HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
+                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, st));
+  }
+  if (b->mem_kind == CELESTE_MEM_HOST) {
+    HIPCHK(hipMemcpyAsync(elbo, d_elbo, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, d_grad, sizeof(double) * NP * S, hipMemcpyDeviceToHost, st));
+    if (hess) HIPCHK(hipMemcpyAsync(hess, d_hess, sizeof(double) * NP * NP * S, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================== fits
+
+namespace {
+
+struct FitBufs {
+  FitDev d;
+};
+
+int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
+  const size_t nd = (size_t)S * (NP * 5 + NP * NP + 2 + 7);
+  const size_t ni = (size_t)S * 5 + 1;
+  CHK(ensure(ctx->st_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
+  double* d = as<double>(ctx->st_buf);
+  auto take = [&](size_t n) {
+    double* r = d;
+    d += n;
+    return r;
+  };
+  f->theta = take((size_t)S * NP);
+  f->psi = take((size_t)S * NP);
+  f->theta_trial = take((size_t)S * NP);
+  f->g = take((size_t)S * NP);
+  f->p = take((size_t)S * NP);
+  f->H = take((size_t)S * NP * NP);
+  f->u0 = take((size_t)S * 2);
+  f->f = take(S);
+  f->f_full = take(S);
+  f->f_trial = take(S);
+  f->pred = take(S);
+  f->delta = take(S);
+  f->pnorm = take(S);
+  take(S);
+  int* ip = reinterpret_cast<int*>(d);
+  f->iter = ip;
+  f->status = ip + S;
+  f->active = ip + 2 * S;
+  f->need_full = ip + 3 * S;
+  f->n_full = ip + 4 * S;
+  f->n_active = ip + 5 * S;
+  return CELESTE_OK;
+}
+
+int check_opts(const celeste_fit_opts* o) {
+  if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
+  if (o->max_iter < 1 || o->max_iter > 100000) return fail(CELESTE_E_INVALID, "max_iter must be in 1..100000");
+  if (o->init_mode != CELESTE_INIT_AS_GIVEN && o->init_mode != CELESTE_INIT_PLAIN)
+    return fail(CELESTE_E_UNSUPPORTED, "init_mode %d not supported", o->init_mode);
+  if (!(o->pred_rtol >= 0.0) || !(o->curv_tol >= 0.0) || !(o->delta0 > 0.0) || !(o->delta_max >= o->delta0) ||
+      !(o->delta_min >= 0.0) || !(o->eta >= 0.0 && o->eta < 1.0) || !(o->u_box > 0.0))
+    return fail(CELESTE_E_INVALID, "fit options out of range");
+  return CELESTE_OK;
+}
+
+// Enqueues one trust-region iteration over all sources (each kernel skips sources
+// whose flag is clear).
+int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const FitParams& fp, hipStream_t st) {
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  const WorkItem* items = as<WorkItem>(ctx->items);
+  const SrcDev* srcs = as<SrcDev>(ctx->srcs);
+  float* tables = as<float>(ctx->tables);
+  double* parts = as<double>(ctx->partials);
+  const double* ic = as<double>(ctx->img_const);
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
+  HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
+                          ctx->block, st));
+  HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H, st));
+  HIPCHK(launch_zero_int(F.n_active, 1, st));
+  HIPCHK(launch_tr_step(F, P.n_src, fp, st));
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, F.active, P.prof, tables, P.tstride, st));
+  HIPCHK(launch_eval_value(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.active, parts,
+                           ctx->block, st));
+  HIPCHK(launch_reduce_value(srcs, P.n_src, imgs, parts, ic, F.theta_trial, P.prior, F.active, F.f_trial, st));
+  HIPCHK(launch_accept(F, P.n_src, fp, st));
+  return CELESTE_OK;
+}
+
+int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
+            celeste_fit_result* res, hipStream_t st, bool batched) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_opts(o));
+  if (!theta_inout || !res) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int S = P.n_src;
+  std::vector<double> th(NP * (size_t)S);
+  if (b->mem_kind == CELESTE_MEM_HOST)
+    std::memcpy(th.data(), theta_inout, sizeof(double) * th.size());
+  else {
+    HIPCHK(hipMemcpyAsync(th.data(), theta_inout, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int s = 0; s < S; ++s) {
+    if (o->init_mode == CELESTE_INIT_PLAIN) {
+      if (!finite(th[(size_t)s * NP]) || !finite(th[(size_t)s * NP + 1]))
+        return fail(CELESTE_E_INVALID, "theta[%d]: position must be finite", s);
+    } else {
+      CHK(check_theta(th.data() + (size_t)s * NP, s));
+    }
+  }
+  CHK(prepare(ctx, b, &P, st));
+  FitDev F;
+  CHK(alloc_fit(ctx, S, &F));
+  FitParams fp;
+  fp.max_iter = o->max_iter;
+  fp.pred_rtol = o->pred_rtol;
+  fp.curv_tol = o->curv_tol;
+  fp.delta0 = o->delta0;
+  fp.delta_max = o->delta_max;
+  fp.delta_min = o->delta_min;
+  fp.eta = o->eta;
+  fp.u_box = o->u_box;
+  HIPCHK(hipMemcpyAsync(F.theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st));
+  if (o->init_mode == CELESTE_INIT_PLAIN)
+    HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, as<ImgDev>(ctx->imgs), P.prior, F.theta, st));
+  HIPCHK(launch_fit_init(F, S, fp, st));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                           P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+  HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs, as<double>(ctx->partials), as<double>(ctx->img_const),
+                             F.theta, P.prior, nullptr, F.f, st));
+  HIPCHK(launch_fit_start(F, S, st));
+
+  const int max_loops = o->max_iter + 1;
+  const int poll = batched ? std::max(1, o->poll_every) : 1;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (batched && ctx->use_graph) {
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_iteration(ctx, P, F, fp, st);
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (rc != CELESTE_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIPCHK(e2);
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  int rc = CELESTE_OK;
+  int n_active = 1;
+  for (int it = 0; it < max_loops && n_active > 0; ++it) {
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) {
+        rc = fail(CELESTE_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+        break;
+      }
+    } else {
+      rc = enqueue_iteration(ctx, P, F, fp, st);
+      if (rc != CELESTE_OK) break;
+    }
+    if ((it + 1) % poll == 0 || it + 1 == max_loops) {
+      hipError_t e = hipMemcpyAsync(&n_active, F.n_active, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        rc = fail(CELESTE_E_DEVICE, "active-count readback: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc != CELESTE_OK) return rc;
+  // results
+  std::vector<double> fv(S), pred(S), delta(S);
+  std::vector<int> iter(S), status(S), nfull(S);
+  HIPCHK(hipMemcpyAsync(th.data(), F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(fv.data(), F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pred.data(), F.pred, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(delta.data(), F.delta, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(iter.data(), F.iter, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(status.data(), F.status, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nfull.data(), F.n_full, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (b->mem_kind == CELESTE_MEM_HOST)
+    std::memcpy(theta_inout, th.data(), sizeof(double) * th.size());
+  else {
+    HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int s = 0; s < S; ++s) {
+    res[s].elbo = fv[s];
+    res[s].pred_gain = pred[s];
+    res[s].delta = delta[s];
+    res[s].iters = iter[s];
+    res[s].status = status[s];
+    res[s].n_full_evals = nfull[s];
+    res[s].flags = 0;
+  }
+  return CELESTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int celeste_newton_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* opts,
+                       celeste_fit_result* result) {
+  if (!b) return fail(CELESTE_E_INVALID, "batch is NULL");
+  if (b->n_sources != 1) return fail(CELESTE_E_INVALID, "celeste_newton_fit takes exactly one source");
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  return run_fit(ctx, b, theta_inout, opts, result, ctx->stream, false);
+}
+
+int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* opts,
+                      celeste_fit_result* results, void* stream) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  return run_fit(ctx, b, theta_inout, opts, results, pick(ctx, stream), true);
+}
+
+}  // extern "C"

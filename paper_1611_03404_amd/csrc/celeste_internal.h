@@ -1,0 +1,139 @@
+// Internal device-side layouts of libceleste (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/celeste.h"
+
+namespace celeste {
+
+constexpr int NP = 27;       // natural parameters per source
+constexpr int NZ = 11;       // per-image z-space: a, m_s, v_s, m_g, v_g, p_x, p_y, e_dev, e_axis, e_angle, e_scale
+constexpr int NACC = 1 + NZ + NZ * (NZ + 1) / 2;   // value, gradient, upper-triangle Hessian = 78
+
+// Per-image device metadata, packed from celeste_image by the host.
+struct ImgDev {
+  const float* pix;
+  const float* nbr_mean;
+  const float* nbr_var;
+  int32_t h, w, pitch, band;
+  int32_t n_psf, src;
+  int32_t item_begin, item_end;   // work items covering this image
+  double origin[2];
+  double wcs[6];
+  double sky, calib;
+  double psf[CELESTE_MAX_PSF][6];
+};
+
+// One unit of pixel work: a contiguous run of one image's pixels (row-major index).
+struct WorkItem {
+  int32_t img, src, px_begin, px_end;
+};
+
+// Source -> images / work items (CSR, contiguous).
+struct SrcDev {
+  int32_t img_begin, img_end, item_begin, item_end;
+};
+
+// Prior with the colour covariance inverse and log-determinant precomputed (FP64).
+struct PriorDev {
+  double p_star;
+  double r_mean[2], r_var[2];
+  double c_mean[2][4];
+  double c_inv[2][4][4];
+  double c_logdet[2];
+  double c_diag[2][4];       // diagonal of the colour covariance (plain start)
+};
+
+struct ProfDev {
+  int32_t n_exp, n_dev;
+  double amp[2 * CELESTE_MAX_PROTO];   // exp components first, then dev
+  double var[2 * CELESTE_MAX_PROTO];
+};
+
+// Per-image setup table (FP32, written by the setup kernel, read with wave-uniform loads).
+namespace tab {
+// header
+constexpr int PSX = 0, PSY = 1, CALIB = 2, SKY = 3, CS = 4, CG = 5, MU_S = 6, MU_G = 7;
+constexpr int KS = 8, KG = 9, KSG = 10, KA_S = 11, KA_G = 12, KA_SG = 13, KV_S = 14, KV_G = 15;
+constexpr int EDEV = 16;
+constexpr int KS_AA = 17, KS_AM = 18, KS_AV = 19, KS_MM = 20, KS_MV = 21, KS_VV = 22;
+constexpr int KG_AA = 23, KG_AM = 24, KG_AV = 25, KG_MM = 26, KG_MV = 27, KG_VV = 28;
+constexpr int KSG_AA = 29, KSG_AM = 30, KSG_AV = 31;
+constexpr int NPSF = 32;                 // stored as float
+// shape-derivative contraction coefficients
+constexpr int W1 = 64;                   // [3 eta][3]: (W_xx/2, W_xy, W_yy/2) of dW/deta
+constexpr int W4 = 73;                   // [6 pairs][5]: B4 contraction
+constexpr int W2 = 103;                  // [6 pairs][3]: (W_xx/2, W_xy, W_yy/2) of d2W/deta deta'
+constexpr int STAR = 128;                // [CELESTE_MAX_PSF][16]
+constexpr int STAR_REC = 16;
+constexpr int GAL = 192;                 // [n_psf][n_exp + n_dev][GAL_REC]
+constexpr int GAL_REC = 24;
+// galaxy record fields
+constexpr int R_C0 = 0, R_QXX = 1, R_QXY = 2, R_QYY = 3, R_PXX = 4, R_PXY = 5, R_PYY = 6, R_NU = 7;
+constexpr int R_3PXX = 8, R_3PYY = 9, R_2PXY = 10, R_6PXX = 11, R_6PYY = 12, R_3PXY = 13, R_4PXY = 14;
+constexpr int R_K4A = 15, R_K4B = 16, R_K4C = 17, R_K4D = 18, R_K4E = 19;
+// star record fields: c0, qxx, qxy, qyy, Pxx, Pxy, Pyy, xi_x, xi_y
+constexpr int S_XIX = 7, S_XIY = 8;
+}  // namespace tab
+
+inline int table_stride(int max_psf, int n_exp, int n_dev) {
+  int n = tab::GAL + max_psf * (n_exp + n_dev) * tab::GAL_REC;
+  return (n + 15) & ~15;
+}
+
+// ---------------------------------------------------------------- launch wrappers
+hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, const int* src_flag,
+                        ProfDev prof, float* tables, int tstride, hipStream_t st);
+hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStream_t st);
+hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st);
+hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
+                            int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
+                            int block, hipStream_t st);
+hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
+                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
+                             int block, hipStream_t st);
+hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
+                              const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
+                              double* elbo, double* grad, double* hess, hipStream_t st);
+hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
+                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
+                               double* elbo, hipStream_t st);
+
+// ---------------------------------------------------------------- trust-region state
+struct FitDev {
+  double* theta;        // S x 27 current (natural)
+  double* psi;          // S x 27 current (unconstrained)
+  double* u0;           // S x 2 box centre
+  double* theta_trial;  // S x 27
+  double* g;            // S x 27 natural gradient at current
+  double* H;            // S x 729 natural Hessian at current
+  double* p;            // S x 27 step (psi)
+  double* f;            // S current ELBO (value pass)
+  double* f_full;       // S ELBO from the full pass
+  double* f_trial;      // S
+  double* pred;         // S
+  double* delta;        // S
+  double* pnorm;        // S
+  int* iter;            // S
+  int* status;          // S
+  int* active;          // S  1 while the source is being fitted
+  int* need_full;       // S  1 when g/H must be recomputed at theta
+  int* n_full;          // S
+  int* n_active;        // 1 counter
+};
+
+struct FitParams {
+  int max_iter;
+  double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
+};
+
+hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);
+hipError_t launch_plain_init(const SrcDev* srcs, int n_src, const ImgDev* imgs, PriorDev prior, double* theta,
+                             hipStream_t s);
+hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s);
+hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+
+}  // namespace celeste

@@ -1,0 +1,434 @@
+// Pixel-sum kernels: the hot loop of the per-source ELBO (sections III-A/B).
+//
+// One work item = a contiguous run of one image's pixels; a 256-thread block
+// takes one work item, each lane one pixel at a time.  Per pixel the kernel
+// evaluates the PSF-convolved star mixture and the exp/dev galaxy mixtures with
+// all derivatives needed for the gradient and dense Hessian, forms the mean and
+// variance of the Poisson rate under q, applies the delta-method expected
+// log-likelihood, and accumulates value, z-gradient and z-Hessian in FP64.
+//
+// Galaxy shape derivatives are not taken component by component.  For a Gaussian
+// N(p; mu, C), dN/dC = (1/2) d2N/dmu2 (the heat equation), so derivatives with
+// respect to the covariance are position-space derivatives: per pixel the kernel
+// accumulates Hermite moments of orders 0-4 weighted by nu^k, and maps them onto
+// (e_axis, e_angle, e_scale) once per pixel with per-image coefficients of dW/deta.
+#include "celeste_internal.h"
+
+namespace celeste {
+
+namespace {
+
+using namespace tab;
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Hermite moments of one galaxy profile type (exp or dev), summed over components.
+struct GalAcc {
+  float a0, a1x, a1y;          // sum N, N b
+  float a2xx, a2xy, a2yy;      // sum N H2
+  float b2xx, b2xy, b2yy;      // sum nu N H2
+  float b3[4];                 // sum nu N H3: xxx, xxy, xyy, yyy
+  float b4[5];                 // sum nu^2 N H4: xxxx, xxxy, xxyy, xyyy, yyyy
+};
+
+__device__ __forceinline__ void zero(GalAcc& A) {
+  A.a0 = A.a1x = A.a1y = 0.f;
+  A.a2xx = A.a2xy = A.a2yy = 0.f;
+  A.b2xx = A.b2xy = A.b2yy = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) A.b3[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) A.b4[i] = 0.f;
+}
+
+// One galaxy component: N and the Hermite polynomials H1..H4 of b = P d,
+// i.e. the derivatives of N with respect to its mean up to order 4.
+__device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
+                                         float dyy, GalAcc& A) {
+  const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
+  const float N = ex2(e);
+  const float Pxx = r[R_PXX], Pxy = r[R_PXY], Pyy = r[R_PYY];
+  const float bx = fmaf(Pxx, dx, Pxy * dy);
+  const float by = fmaf(Pxy, dx, Pyy * dy);
+  const float bxx = bx * bx, bxy = bx * by, byy = by * by;
+  const float h2xx = bxx - Pxx, h2xy = bxy - Pxy, h2yy = byy - Pyy;
+  const float u3x = bxx - r[R_3PXX], u3y = byy - r[R_3PYY];
+  const float h3xxx = bx * u3x;
+  const float h3xxy = fmaf(by, h2xx, -r[R_2PXY] * bx);
+  const float h3xyy = fmaf(bx, h2yy, -r[R_2PXY] * by);
+  const float h3yyy = by * u3y;
+  const float h40 = fmaf(bxx, bxx - r[R_6PXX], r[R_K4A]);
+  const float h41 = fmaf(bxy, u3x, fmaf(-r[R_3PXY], bxx, r[R_K4B]));
+  const float h42 = fmaf(h2xx, h2yy, fmaf(-r[R_4PXY], bxy, r[R_K4C]));
+  const float h43 = fmaf(bxy, u3y, fmaf(-r[R_3PXY], byy, r[R_K4D]));
+  const float h44 = fmaf(byy, byy - r[R_6PYY], r[R_K4E]);
+  const float Nn = N * r[R_NU];
+  const float Nn2 = Nn * r[R_NU];
+  A.a0 += N;
+  A.a1x = fmaf(N, bx, A.a1x);
+  A.a1y = fmaf(N, by, A.a1y);
+  A.a2xx = fmaf(N, h2xx, A.a2xx);
+  A.a2xy = fmaf(N, h2xy, A.a2xy);
+  A.a2yy = fmaf(N, h2yy, A.a2yy);
+  A.b2xx = fmaf(Nn, h2xx, A.b2xx);
+  A.b2xy = fmaf(Nn, h2xy, A.b2xy);
+  A.b2yy = fmaf(Nn, h2yy, A.b2yy);
+  A.b3[0] = fmaf(Nn, h3xxx, A.b3[0]);
+  A.b3[1] = fmaf(Nn, h3xxy, A.b3[1]);
+  A.b3[2] = fmaf(Nn, h3xyy, A.b3[2]);
+  A.b3[3] = fmaf(Nn, h3yyy, A.b3[3]);
+  A.b4[0] = fmaf(Nn2, h40, A.b4[0]);
+  A.b4[1] = fmaf(Nn2, h41, A.b4[1]);
+  A.b4[2] = fmaf(Nn2, h42, A.b4[2]);
+  A.b4[3] = fmaf(Nn2, h43, A.b4[3]);
+  A.b4[4] = fmaf(Nn2, h44, A.b4[4]);
+}
+
+__device__ __forceinline__ float gal_value(const float* __restrict__ r, float dxx, float dxy, float dyy) {
+  return ex2(fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0]))));
+}
+
+constexpr int tri(int i, int j) { return i * NZ - (i * (i - 1)) / 2 + (j - i); }
+
+// Wave reduction of 80 doubles by recursive halving (masks 32, 16, 8, 4) and a
+// butterfly over the last 4 lanes; returns in out[0..4] the wave sums of the 5
+// entries with base index 40*b5 + 20*b4 + 10*b3 + 5*b2 (b_k = lane bit k).
+template <int N>
+__device__ __forceinline__ void halve(const double* v, double* o, int mask, bool up) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double send = up ? v[i] : v[i + N / 2];
+    const double keep = up ? v[i + N / 2] : v[i];
+    o[i] = keep + __shfl_xor(send, mask);
+  }
+}
+
+__device__ __forceinline__ int wave_reduce80(const double* acc, double* out5) {
+  const int lane = threadIdx.x & 63;
+  double t40[40], t20[20], t10[10];
+  halve<80>(acc, t40, 32, lane & 32);
+  halve<40>(t40, t20, 16, lane & 16);
+  halve<20>(t20, t10, 8, lane & 8);
+  halve<10>(t10, out5, 4, lane & 4);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    out5[i] += __shfl_xor(out5[i], 2);
+    out5[i] += __shfl_xor(out5[i], 1);
+  }
+  return ((lane >> 5) & 1) * 40 + ((lane >> 4) & 1) * 20 + ((lane >> 3) & 1) * 10 + ((lane >> 2) & 1) * 5;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_eval_full(const WorkItem* __restrict__ items,
+                                                     const ImgDev* __restrict__ imgs,
+                                                     const float* __restrict__ tables, int tstride, int n_exp,
+                                                     int n_dev, const int* __restrict__ src_flag,
+                                                     double* __restrict__ partials) {
+  __shared__ double red[BLOCK / 64][80];
+  const WorkItem wi = items[blockIdx.x];
+  if (src_flag && !src_flag[wi.src]) return;
+  const ImgDev& im = imgs[wi.img];
+  const float* __restrict__ T = tables + (size_t)wi.img * tstride;
+  const int w = im.w, pitch = im.pitch, npsf = im.n_psf;
+  const float* __restrict__ pix = im.pix;
+  const float* __restrict__ nbrE = im.nbr_mean;
+  const float* __restrict__ nbrV = im.nbr_var;
+  const int ncomp = n_exp + n_dev;
+  const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
+  const float io2 = io * io, io3 = io2 * io;
+
+  double acc[80];
+#pragma unroll
+  for (int i = 0; i < 80; ++i) acc[i] = 0.0;
+
+  for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
+    const int row = m / w, col = m - row * w;
+    const size_t o = (size_t)row * pitch + col;
+    const float x = pix[o];
+    const float ebg = sky + (nbrE ? nbrE[o] : 0.f);
+    const float vbg = nbrV ? nbrV[o] : 0.f;
+    const float dx0 = (float)col - psx, dy0 = (float)row - psy;
+
+    // ---- star: N, dN/dp, d2N/dp2
+    float s0 = 0.f, s1x = 0.f, s1y = 0.f, s2xx = 0.f, s2xy = 0.f, s2yy = 0.f;
+    for (int k = 0; k < npsf; ++k) {
+      const float* __restrict__ r = T + STAR + k * STAR_REC;
+      const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
+      const float N = ex2(fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0]))));
+      const float bx = fmaf(r[R_PXX], dx, r[R_PXY] * dy), by = fmaf(r[R_PXY], dx, r[R_PYY] * dy);
+      s0 += N;
+      s1x = fmaf(N, bx, s1x);
+      s1y = fmaf(N, by, s1y);
+      s2xx = fmaf(N, fmaf(bx, bx, -r[R_PXX]), s2xx);
+      s2xy = fmaf(N, fmaf(bx, by, -r[R_PXY]), s2xy);
+      s2yy = fmaf(N, fmaf(by, by, -r[R_PYY]), s2yy);
+    }
+
+    // ---- galaxy: Hermite moments per profile type
+    GalAcc X, D;
+    zero(X);
+    zero(D);
+    for (int k = 0; k < npsf; ++k) {
+      const float* __restrict__ sr = T + STAR + k * STAR_REC;
+      const float dx = dx0 - sr[S_XIX], dy = dy0 - sr[S_XIY];
+      const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+      const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
+      for (int j = 0; j < n_exp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+      for (int j = n_exp; j < ncomp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+    }
+
+    // ---- galaxy profile and its derivatives in y = (p_x, p_y, e_dev, e_axis, e_angle, e_scale)
+    const float ed = T[EDEV];
+    auto mix = [ed](float d, float x_) { return fmaf(ed, d - x_, x_); };
+    const float Gg = mix(D.a0, X.a0);
+    float dG[6], d2G[6][6];
+    dG[0] = mix(D.a1x, X.a1x);
+    dG[1] = mix(D.a1y, X.a1y);
+    dG[2] = D.a0 - X.a0;
+    const float b2c[3] = {mix(D.b2xx, X.b2xx), mix(D.b2xy, X.b2xy), mix(D.b2yy, X.b2yy)};
+    const float b2d[3] = {D.b2xx - X.b2xx, D.b2xy - X.b2xy, D.b2yy - X.b2yy};
+    float b3c[4], b4c[5];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b3c[i] = mix(D.b3[i], X.b3[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b4c[i] = mix(D.b4[i], X.b4[i]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const float w0 = T[W1 + 3 * e], w1 = T[W1 + 3 * e + 1], w2 = T[W1 + 3 * e + 2];
+      dG[3 + e] = fmaf(w0, b2c[0], fmaf(w1, b2c[1], w2 * b2c[2]));
+      d2G[0][3 + e] = fmaf(w0, b3c[0], fmaf(w1, b3c[1], w2 * b3c[2]));
+      d2G[1][3 + e] = fmaf(w0, b3c[1], fmaf(w1, b3c[2], w2 * b3c[3]));
+      d2G[2][3 + e] = fmaf(w0, b2d[0], fmaf(w1, b2d[1], w2 * b2d[2]));
+    }
+    d2G[0][0] = mix(D.a2xx, X.a2xx);
+    d2G[0][1] = mix(D.a2xy, X.a2xy);
+    d2G[1][1] = mix(D.a2yy, X.a2yy);
+    d2G[0][2] = D.a1x - X.a1x;
+    d2G[1][2] = D.a1y - X.a1y;
+    d2G[2][2] = 0.f;
+    {
+      int k = 0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+#pragma unroll
+        for (int f = e; f < 3; ++f, ++k) {
+          const float* w4 = T + W4 + 5 * k;
+          const float* w2 = T + W2 + 3 * k;
+          float v = w4[0] * b4c[0];
+#pragma unroll
+          for (int q = 1; q < 5; ++q) v = fmaf(w4[q], b4c[q], v);
+          v = fmaf(w2[0], b2c[0], fmaf(w2[1], b2c[1], fmaf(w2[2], b2c[2], v)));
+          d2G[3 + e][3 + f] = v;
+        }
+      }
+    }
+    // star derivatives in the same y coordinates (zero beyond the position)
+    const float dGs[2] = {s1x, s1y};
+
+    // ---- mean T and variance U of the source's contribution, and their z-derivatives
+    const float cs = T[CS], cg = T[CG], mus = T[MU_S], mug = T[MU_G];
+    const float Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+    const float Gs = s0;
+    const float Gs2 = Gs * Gs, Gg2 = Gg * Gg, Gsg = Gs * Gg;
+    const float Tv = fmaf(cs, Gs, cg * Gg);
+    const float Uv = fmaf(Ks, Gs2, fmaf(Kg, Gg2, Ksg * Gsg));
+    const float rhos = fmaf(2.f * Ks, Gs, Ksg * Gg), rhog = fmaf(2.f * Kg, Gg, Ksg * Gs);
+    float Tz[NZ], Uz[NZ];
+    Tz[0] = fmaf(mus, Gs, -mug * Gg);
+    Tz[1] = cs * Gs;
+    Tz[2] = 0.5f * Tz[1];
+    Tz[3] = cg * Gg;
+    Tz[4] = 0.5f * Tz[3];
+    Uz[0] = fmaf(T[KA_S], Gs2, fmaf(T[KA_G], Gg2, T[KA_SG] * Gsg));
+    Uz[1] = fmaf(2.f * Ks, Gs2, Ksg * Gsg);
+    Uz[2] = fmaf(T[KV_S], Gs2, 0.5f * Ksg * Gsg);
+    Uz[3] = fmaf(2.f * Kg, Gg2, Ksg * Gsg);
+    Uz[4] = fmaf(T[KV_G], Gg2, 0.5f * Ksg * Gsg);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float gs = k < 2 ? dGs[k] : 0.f;
+      Tz[5 + k] = fmaf(cs, gs, cg * dG[k]);
+      Uz[5 + k] = fmaf(rhos, gs, rhog * dG[k]);
+    }
+
+    // ---- delta-method pixel term and its partials in (E, V)
+    const float E = fmaf(io, Tv, ebg);
+    const float V = fmaf(io2, Uv, vbg);
+    const float rE = __builtin_amdgcn_rcpf(E);
+    const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
+    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
+    const float lE = fmaf(x - E, rE, V * xr3);
+    const float lV = -0.5f * xr2;
+    const float lEE = -fmaf(3.f * V * xr3, rE, xr2);
+    const float lEV = xr3;
+    const float wT = io * lE, wU = io2 * lV, wTT = io2 * lEE, wTU = io3 * lEV;
+
+    // ---- sparse second-order part S = wT d2T + wU d2U (upper triangle)
+    float S[NZ * (NZ + 1) / 2];
+    S[tri(0, 0)] = wU * fmaf(T[KS_AA], Gs2, fmaf(T[KG_AA], Gg2, T[KSG_AA] * Gsg));
+    S[tri(0, 1)] = fmaf(wT, mus * Gs, wU * fmaf(T[KS_AM], Gs2, T[KSG_AM] * Gsg));
+    S[tri(0, 2)] = fmaf(wT, 0.5f * mus * Gs, wU * fmaf(T[KS_AV], Gs2, T[KSG_AV] * Gsg));
+    S[tri(0, 3)] = fmaf(wT, -mug * Gg, wU * fmaf(T[KG_AM], Gg2, T[KSG_AM] * Gsg));
+    S[tri(0, 4)] = fmaf(wT, -0.5f * mug * Gg, wU * fmaf(T[KG_AV], Gg2, T[KSG_AV] * Gsg));
+    S[tri(1, 1)] = fmaf(wT, Tz[1], wU * fmaf(T[KS_MM], Gs2, Ksg * Gsg));
+    S[tri(1, 2)] = fmaf(wT, 0.5f * Tz[1], wU * fmaf(T[KS_MV], Gs2, 0.5f * Ksg * Gsg));
+    S[tri(1, 3)] = wU * Ksg * Gsg;
+    S[tri(1, 4)] = 0.5f * wU * Ksg * Gsg;
+    S[tri(2, 2)] = fmaf(wT, 0.25f * Tz[1], wU * fmaf(T[KS_VV], Gs2, 0.25f * Ksg * Gsg));
+    S[tri(2, 3)] = 0.5f * wU * Ksg * Gsg;
+    S[tri(2, 4)] = 0.25f * wU * Ksg * Gsg;
+    S[tri(3, 3)] = fmaf(wT, Tz[3], wU * fmaf(T[KG_MM], Gg2, Ksg * Gsg));
+    S[tri(3, 4)] = fmaf(wT, 0.5f * Tz[3], wU * fmaf(T[KG_MV], Gg2, 0.5f * Ksg * Gsg));
+    S[tri(4, 4)] = fmaf(wT, 0.25f * Tz[3], wU * fmaf(T[KG_VV], Gg2, 0.25f * Ksg * Gsg));
+    {
+      // brightness x geometry block
+      const float dks[5] = {T[KA_S], 2.f * Ks, T[KV_S], 0.f, 0.f};
+      const float dkg[5] = {T[KA_G], 0.f, 0.f, 2.f * Kg, T[KV_G]};
+      const float dksg[5] = {T[KA_SG], Ksg, 0.5f * Ksg, Ksg, 0.5f * Ksg};
+      const float cts[5] = {mus, cs, 0.5f * cs, 0.f, 0.f};
+      const float ctg[5] = {-mug, 0.f, 0.f, cg, 0.5f * cg};
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const float sgs = fmaf(wT, cts[i], wU * fmaf(2.f * dks[i], Gs, dksg[i] * Gg));
+        const float sgg = fmaf(wT, ctg[i], wU * fmaf(2.f * dkg[i], Gg, dksg[i] * Gs));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const float gs = k < 2 ? dGs[k] : 0.f;
+          S[tri(i, 5 + k)] = fmaf(sgs, gs, sgg * dG[k]);
+        }
+      }
+      // geometry x geometry block
+      const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
+      const float d2Gs[3] = {s2xx, s2xy, s2yy};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+#pragma unroll
+        for (int l = k; l < 6; ++l) {
+          const float gsk = k < 2 ? dGs[k] : 0.f, gsl = l < 2 ? dGs[l] : 0.f;
+          const float hs = (k < 2 && l < 2) ? d2Gs[k + l] : 0.f;
+          float v = fmaf(als, hs, alg * d2G[k][l]);
+          const float q = fmaf(2.f * Ks, gsk * gsl, fmaf(2.f * Kg, dG[k] * dG[l], Ksg * fmaf(gsk, dG[l], gsl * dG[k])));
+          S[tri(5 + k, 5 + l)] = fmaf(wU, q, v);
+        }
+      }
+    }
+
+    // ---- accumulate value, gradient and Hessian in FP64
+    acc[0] += (double)lval;
+    float hT[NZ], hU[NZ];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      acc[1 + j] += (double)fmaf(wT, Tz[j], wU * Uz[j]);
+      hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
+      hU[j] = wTU * Tz[j];
+    }
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+#pragma unroll
+      for (int j = i; j < NZ; ++j) {
+        acc[1 + NZ + tri(i, j)] += (double)fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+      }
+    }
+  }
+
+  // ---- block reduction (deterministic order) and one FP64 partial per work item
+  double part[5];
+  const int base = wave_reduce80(acc, part);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if ((lane & 3) == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) red[wv][base + i] = part[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NACC) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[k][threadIdx.x];
+    partials[(size_t)blockIdx.x * NACC + threadIdx.x] = s;
+  }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict__ items,
+                                                      const ImgDev* __restrict__ imgs,
+                                                      const float* __restrict__ tables, int tstride, int n_exp,
+                                                      int n_dev, const int* __restrict__ src_flag,
+                                                      double* __restrict__ partials) {
+  __shared__ double red[BLOCK / 64];
+  const WorkItem wi = items[blockIdx.x];
+  if (src_flag && !src_flag[wi.src]) return;
+  const ImgDev& im = imgs[wi.img];
+  const float* __restrict__ T = tables + (size_t)wi.img * tstride;
+  const int w = im.w, pitch = im.pitch, npsf = im.n_psf;
+  const float* __restrict__ pix = im.pix;
+  const float* __restrict__ nbrE = im.nbr_mean;
+  const float* __restrict__ nbrV = im.nbr_var;
+  const int ncomp = n_exp + n_dev;
+  const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
+  const float ed = T[EDEV];
+  const float cs = T[CS], cg = T[CG], Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+  double acc = 0.0;
+  for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
+    const int row = m / w, col = m - row * w;
+    const size_t o = (size_t)row * pitch + col;
+    const float x = pix[o];
+    const float ebg = sky + (nbrE ? nbrE[o] : 0.f);
+    const float vbg = nbrV ? nbrV[o] : 0.f;
+    const float dx0 = (float)col - psx, dy0 = (float)row - psy;
+    float Gs = 0.f, gx = 0.f, gd = 0.f;
+    for (int k = 0; k < npsf; ++k) {
+      const float* __restrict__ r = T + STAR + k * STAR_REC;
+      const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
+      const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+      Gs += gal_value(r, dxx, dxy, dyy);
+      const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
+      for (int j = 0; j < n_exp; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+      for (int j = n_exp; j < ncomp; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+    }
+    const float Gg = fmaf(ed, gd - gx, gx);
+    const float Tv = fmaf(cs, Gs, cg * Gg);
+    const float Uv = fmaf(Ks, Gs * Gs, fmaf(Kg, Gg * Gg, Ksg * Gs * Gg));
+    const float E = fmaf(io, Tv, ebg);
+    const float V = fmaf(io * io, Uv, vbg);
+    const float rE = __builtin_amdgcn_rcpf(E);
+    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * (x * rE * rE);
+    acc += (double)lval;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+    partials[blockIdx.x] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
+                            int n_exp, int n_dev, const int* src_flag, double* partials, int block, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (block == 128)
+    hipLaunchKernelGGL(k_eval_full<128>, dim3(n_items), dim3(128), 0, st, items, imgs, tables, tstride, n_exp, n_dev,
+                       src_flag, partials);
+  else
+    hipLaunchKernelGGL(k_eval_full<256>, dim3(n_items), dim3(256), 0, st, items, imgs, tables, tstride, n_exp, n_dev,
+                       src_flag, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
+                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (block == 128)
+    hipLaunchKernelGGL(k_eval_value<128>, dim3(n_items), dim3(128), 0, st, items, imgs, tables, tstride, n_exp,
+                       n_dev, src_flag, partials);
+  else
+    hipLaunchKernelGGL(k_eval_value<256>, dim3(n_items), dim3(256), 0, st, items, imgs, tables, tstride, n_exp,
+                       n_dev, src_flag, partials);
+  return hipGetLastError();
+}
+
+}  // namespace celeste

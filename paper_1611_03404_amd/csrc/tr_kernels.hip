@@ -1,0 +1,415 @@
+// Trust-region Newton state machine on the device (section III-B: Newton's method
+// with updates constrained by a trust region, dense hand-derived Hessian, per
+// source).  One wavefront per active source solves the 27x27 FP64 subproblem
+//     maximise g'p + p'Hp/2  subject to |p| <= Delta     (unconstrained coordinates)
+// through a cyclic Jacobi eigendecomposition of B = -H (parallel round-robin
+// ordering, 14 disjoint rotations per round held in LDS), followed by the secular
+// equation |(B + sI)^{-1} g| = Delta solved by safeguarded Newton on 1/|p(s)|
+// (More-Sorensen), including the hard case.  A separate kernel applies the
+// ratio test and updates the radius, one thread per source.
+#include <math.h>
+
+#include "celeste_internal.h"
+
+namespace celeste {
+
+namespace {
+
+constexpr int NPAD = 28;   // 27 padded to an even order for the round-robin schedule
+
+// Elementwise map theta_i = t_i(psi_i): scaled logistic on boxes, exp on variances.
+struct Box {
+  double lo, hi;
+  int kind;   // 0 identity, 1 logistic on [lo, hi], 2 exp
+};
+
+__device__ inline Box box_of(int i, const double* u0, double u_box) {
+  if (i == 0 || i == 1) return {u0[i] - u_box, u0[i] + u_box, 1};
+  if (i == 2 || i == 3) return {1e-4, 1.0 - 1e-4, 1};
+  if (i == 4) return {0.01, 0.99, 1};
+  if (i == 6) return {0.2, 15.0, 1};
+  if (i == 9 || i == 10 || i >= 19) return {0.0, 0.0, 2};
+  return {0.0, 0.0, 0};
+}
+
+__device__ inline double to_psi1(double th, Box b) {
+  if (b.kind == 0) return th;
+  if (b.kind == 2) return log(th);
+  const double span = b.hi - b.lo;
+  const double x = fmin(fmax(th, b.lo + 1e-9 * span), b.hi - 1e-9 * span);
+  const double f = (x - b.lo) / span;
+  return log(f) - log1p(-f);
+}
+
+__device__ inline double to_theta1(double psi, Box b, double* d1, double* d2) {
+  if (b.kind == 0) {
+    *d1 = 1.0;
+    *d2 = 0.0;
+    return psi;
+  }
+  if (b.kind == 2) {
+    const double e = exp(psi);
+    *d1 = e;
+    *d2 = e;
+    return e;
+  }
+  const double span = b.hi - b.lo;
+  const double s = 1.0 / (1.0 + exp(-psi));
+  *d1 = span * s * (1.0 - s);
+  *d2 = span * s * (1.0 - s) * (1.0 - 2.0 * s);
+  return b.lo + span * s;
+}
+
+// ---------------------------------------------------------------- start of a fit
+__global__ void k_fit_init(FitDev st, int n_src, FitParams fp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  double* th = st.theta + (size_t)s * NP;
+  double* ps = st.psi + (size_t)s * NP;
+  double* u0 = st.u0 + 2 * s;
+  u0[0] = th[0];
+  u0[1] = th[1];
+  for (int i = 0; i < NP; ++i) {
+    const Box b = box_of(i, u0, fp.u_box);
+    ps[i] = to_psi1(th[i], b);
+    double d1, d2;
+    th[i] = to_theta1(ps[i], b, &d1, &d2);
+  }
+  st.delta[s] = fp.delta0;
+  st.iter[s] = 0;
+  st.status[s] = CELESTE_MAX_ITER;
+  st.active[s] = 1;
+  st.need_full[s] = 1;
+  st.n_full[s] = 0;
+  st.pred[s] = 0.0;
+}
+
+// A source whose starting ELBO is not finite is not fitted.
+__global__ void k_fit_start(FitDev st, int n_src) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  if (!isfinite(st.f[s])) {
+    st.status[s] = CELESTE_NONFINITE;
+    st.active[s] = 0;
+    st.need_full[s] = 0;
+  }
+}
+
+__device__ inline void pair_of(int round, int k, int* p, int* q) {
+  // circle method over NPAD players: player NPAD-1 fixed, the rest rotate
+  const int m = NPAD - 1;
+  if (k == 0) {
+    *p = m;
+    *q = round;
+  } else {
+    *p = (round + k) % m;
+    *q = (round - k + m) % m;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
+  __shared__ double B[NPAD][NPAD + 1];
+  __shared__ double V[NPAD][NPAD + 1];
+  __shared__ double g[NPAD], gt[NPAD], lam[NPAD], pt[NPAD], d1s[NP];
+  __shared__ double rc[NPAD / 2], rs[NPAD / 2], rt[NPAD / 2], rapq[NPAD / 2], rapp[NPAD / 2], raqq[NPAD / 2];
+  __shared__ int rp[NPAD / 2], rq[NPAD / 2];
+  __shared__ int done;
+  const int s = blockIdx.x;
+  if (!st.active[s]) return;
+  const int t = threadIdx.x;
+  if (t == 0 && st.need_full[s]) {
+    st.n_full[s] += 1;
+    st.need_full[s] = 0;
+  }
+  const double* ps = st.psi + (size_t)s * NP;
+  const double* gn = st.g + (size_t)s * NP;
+  const double* Hn = st.H + (size_t)s * NP * NP;
+  const double* u0 = st.u0 + 2 * s;
+  // transform to unconstrained coordinates: g = t' g_n, B = -(D H D + diag(t'' g_n))
+  __shared__ double d2s[NP];
+  if (t < NP) {
+    double d1, d2;
+    to_theta1(ps[t], box_of(t, u0, fp.u_box), &d1, &d2);
+    d1s[t] = d1;
+    d2s[t] = d2;
+  }
+  __syncthreads();
+  for (int k = t; k < NPAD * NPAD; k += 64) {
+    const int i = k / NPAD, j = k - i * NPAD;
+    double b = 0.0;
+    if (i < NP && j < NP) {
+      b = -d1s[i] * Hn[i * NP + j] * d1s[j];
+      if (i == j) b -= d2s[i] * gn[i];
+    }
+    B[i][j] = b;
+    V[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (t < NPAD) g[t] = t < NP ? d1s[t] * gn[t] : 0.0;
+  __syncthreads();
+  // symmetrise (the Hessian is assembled symmetrically; this removes rounding asymmetry)
+  for (int k = t; k < NPAD * NPAD; k += 64) {
+    const int i = k / NPAD, j = k - i * NPAD;
+    if (i < j) {
+      const double m = 0.5 * (B[i][j] + B[j][i]);
+      B[i][j] = m;
+      B[j][i] = m;
+    }
+  }
+  __syncthreads();
+
+  // ---- cyclic Jacobi, round-robin parallel ordering
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, fro = 0.0;
+    for (int k = t; k < NPAD * NPAD; k += 64) {
+      const int i = k / NPAD, j = k - i * NPAD;
+      const double v = B[i][j] * B[i][j];
+      fro += v;
+      if (i != j) off += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      fro += __shfl_xor(fro, o);
+    }
+    if (off <= 1e-30 * fro || fro == 0.0) break;
+    for (int round = 0; round < NPAD - 1; ++round) {
+      if (t < NPAD / 2) {
+        int p, q;
+        pair_of(round, t, &p, &q);
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        const double apq = B[p][q], app = B[p][p], aqq = B[q][q];
+        double c = 1.0, sn = 0.0, tt = 0.0;
+        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          sn = tt * c;
+        }
+        rp[t] = p;
+        rq[t] = q;
+        rc[t] = c;
+        rs[t] = sn;
+        rt[t] = tt;
+        rapq[t] = apq;
+        rapp[t] = app;
+        raqq[t] = aqq;
+      }
+      __syncthreads();
+      // columns: B <- B J
+      for (int k = t; k < (NPAD / 2) * NPAD; k += 64) {
+        const int pr = k / NPAD, r = k - pr * NPAD;
+        const int p = rp[pr], q = rq[pr];
+        const double c = rc[pr], sn = rs[pr];
+        const double bp = B[r][p], bq = B[r][q];
+        B[r][p] = c * bp - sn * bq;
+        B[r][q] = sn * bp + c * bq;
+        const double vp = V[r][p], vq = V[r][q];
+        V[r][p] = c * vp - sn * vq;
+        V[r][q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+      // rows: B <- J^T B
+      for (int k = t; k < (NPAD / 2) * NPAD; k += 64) {
+        const int pr = k / NPAD, r = k - pr * NPAD;
+        const int p = rp[pr], q = rq[pr];
+        const double c = rc[pr], sn = rs[pr];
+        const double bp = B[p][r], bq = B[q][r];
+        B[p][r] = c * bp - sn * bq;
+        B[q][r] = sn * bp + c * bq;
+      }
+      __syncthreads();
+      if (t < NPAD / 2) {
+        const int p = rp[t], q = rq[t];
+        if (rt[t] != 0.0) {
+          B[p][p] = rapp[t] - rt[t] * rapq[t];
+          B[q][q] = raqq[t] + rt[t] * rapq[t];
+          B[p][q] = 0.0;
+          B[q][p] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- eigen-coordinates of g
+  if (t < NP) {
+    lam[t] = B[t][t];
+    double a = 0.0;
+    for (int r = 0; r < NP; ++r) a += V[r][t] * g[r];
+    gt[t] = a;
+  }
+  __syncthreads();
+
+  // ---- secular equation (one lane)
+  if (t == 0) {
+    const double delta = st.delta[s];
+    double lam0 = lam[0], lmax = fabs(lam[0]), gn2 = 0.0;
+    int i0 = 0;
+    for (int i = 0; i < NP; ++i) {
+      if (lam[i] < lam0) {
+        lam0 = lam[i];
+        i0 = i;
+      }
+      lmax = fmax(lmax, fabs(lam[i]));
+      gn2 += gt[i] * gt[i];
+    }
+    const double scale = fmax(1.0, lmax);
+    auto pnorm2 = [&](double sv) {
+      double a = 0.0;
+      for (int i = 0; i < NP; ++i) {
+        const double q = gt[i] / (lam[i] + sv);
+        a += q * q;
+      }
+      return a;
+    };
+    double sv = 0.0;
+    bool hard = false;
+    if (!(lam0 > 1e-14 * scale && pnorm2(0.0) <= delta * delta)) {
+      const double slo = fmax(0.0, -lam0);
+      double gbot2 = 0.0, prest2 = 0.0;
+      for (int i = 0; i < NP; ++i) {
+        if (fabs(lam[i] - lam0) <= 1e-12 * scale) {
+          gbot2 += gt[i] * gt[i];
+        } else {
+          const double q = gt[i] / (lam[i] + slo);
+          prest2 += q * q;
+        }
+      }
+      if (sqrt(gbot2) <= 1e-12 * fmax(1.0, sqrt(gn2)) && prest2 <= delta * delta) {
+        hard = true;
+        sv = slo;
+        for (int i = 0; i < NP; ++i)
+          pt[i] = (fabs(lam[i] - lam0) <= 1e-12 * scale) ? 0.0 : gt[i] / (lam[i] + slo);
+        pt[i0] += sqrt(fmax(delta * delta - prest2, 0.0));
+      } else {
+        double lo = slo, hi = slo + sqrt(gn2) / delta + 1.0;
+        sv = (slo > 0.0) ? slo + 1e-12 * scale : 0.0;
+        if (pnorm2(sv) > delta * delta) {
+          for (int it = 0; it < 200; ++it) {
+            double a2 = 0.0, b3 = 0.0;
+            for (int i = 0; i < NP; ++i) {
+              const double den = lam[i] + sv;
+              const double q = gt[i] / den;
+              a2 += q * q;
+              b3 += q * q / den;
+            }
+            const double pn = sqrt(a2);
+            if (fabs(pn - delta) <= 1e-13 * delta) break;
+            if (pn > delta) lo = fmax(lo, sv); else hi = fmin(hi, sv);
+            // Newton on 1/|p(s)| - 1/Delta, kept inside the bracket
+            double nx = sv + (a2 / b3) * (pn - delta) / delta;
+            if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+            if (nx == sv) break;
+            sv = nx;
+          }
+        }
+        // else: |p| <= Delta just above the pole (nearly the hard case): keep sv
+      }
+    }
+    if (!hard)
+      for (int i = 0; i < NP; ++i) pt[i] = gt[i] / (lam[i] + sv);
+    double pred = 0.0;
+    for (int i = 0; i < NP; ++i) pred += gt[i] * pt[i] - 0.5 * lam[i] * pt[i] * pt[i];
+    // convergence and iteration cap
+    const double f = st.f[s];
+    int d = 0;
+    if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
+      st.status[s] = CELESTE_CONVERGED;
+      d = 1;
+    } else if (st.iter[s] >= fp.max_iter) {
+      st.status[s] = CELESTE_MAX_ITER;
+      d = 1;
+    }
+    st.pred[s] = pred;
+    if (d) st.active[s] = 0;
+    done = d;
+  }
+  __syncthreads();
+  if (done) return;
+  // ---- step in psi and the trial point
+  double* pp = st.p + (size_t)s * NP;
+  double* tht = st.theta_trial + (size_t)s * NP;
+  double pn2 = 0.0;
+  if (t < NP) {
+    double a = 0.0;
+    for (int i = 0; i < NP; ++i) a += V[t][i] * pt[i];
+    pp[t] = a;
+    double d1, d2;
+    tht[t] = to_theta1(ps[t] + a, box_of(t, u0, fp.u_box), &d1, &d2);
+    pn2 = a * a;
+  }
+  for (int o = 32; o > 0; o >>= 1) pn2 += __shfl_xor(pn2, o);
+  if (t == 0) st.pnorm[s] = sqrt(pn2);
+}
+
+// Ratio test, radius update and acceptance; one thread per source.
+__global__ void k_accept(FitDev st, int n_src, FitParams fp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src || !st.active[s]) return;
+  const double ft = st.f_trial[s], f = st.f[s], pred = st.pred[s];
+  const double rho = isfinite(ft) ? (ft - f) / pred : -INFINITY;
+  const double pn = st.pnorm[s];
+  double delta = st.delta[s];
+  if (rho < 0.25)
+    delta = 0.25 * pn;
+  else if (rho > 0.75 && pn >= 0.99 * delta)
+    delta = fmin(2.0 * delta, fp.delta_max);
+  st.delta[s] = delta;
+  if (rho > fp.eta) {
+    double* th = st.theta + (size_t)s * NP;
+    double* ps = st.psi + (size_t)s * NP;
+    const double* tt = st.theta_trial + (size_t)s * NP;
+    const double* pp = st.p + (size_t)s * NP;
+    for (int i = 0; i < NP; ++i) {
+      ps[i] += pp[i];
+      th[i] = tt[i];
+    }
+    st.f[s] = ft;
+    st.need_full[s] = 1;
+  }
+  st.iter[s] += 1;
+  if (delta < fp.delta_min) {
+    st.status[s] = CELESTE_TR_COLLAPSED;
+    st.active[s] = 0;
+    st.need_full[s] = 0;
+    return;
+  }
+  atomicAdd(st.n_active, 1);
+}
+
+__global__ void k_zero(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_init, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_start(FitDev st, int n_src, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_start, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src);
+  return hipGetLastError();
+}
+
+hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s) {
+  hipLaunchKernelGGL(k_tr, dim3(n_src), dim3(64), 0, s, st, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s) {
+  hipLaunchKernelGGL(k_accept, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3((n + 127) / 128), dim3(128), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace celeste

@@ -1,0 +1,224 @@
+"""GPU parity of celeste_elbo_eval against the FP64 oracle (through the C ABI)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from synth.generate import perturb_theta
+from oracle import init as oinit
+from oracle import model
+from helpers import assert_derivs_close, assert_elbo_close, deriv_err, oracle_eval
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1611_03404_amd import celeste as cb_
+    cb_.load()
+    return cb_
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return synth.make_config(0)
+
+
+def _points(sb, seed):
+    pts = [sb.theta_truth.copy(), perturb_theta(sb.theta_truth, seed)]
+    plain = np.stack([oinit.plain_init(sb.u_cat[s], model.source_images(sb, s), sb.prior)
+                      for s in range(sb.n_sources)])
+    pts.append(plain)
+    return pts
+
+
+def _check_batch(cb, ctx, sb, thetas, nbr=None, what=""):
+    b = cb.Batch.from_synth(sb, nbr=nbr)
+    for k, th in enumerate(thetas):
+        el, g, H = ctx.elbo_eval(b, th)
+        for s in range(sb.n_sources):
+            onbr = None
+            if nbr is not None:
+                onbr = {i: (nbr[0][sb.img_pix_off[i]:sb.img_pix_off[i] + sb.img_h[i] * sb.img_w[i]].reshape(
+                    sb.img_h[i], sb.img_w[i]),
+                    nbr[1][sb.img_pix_off[i]:sb.img_pix_off[i] + sb.img_h[i] * sb.img_w[i]].reshape(
+                        sb.img_h[i], sb.img_w[i])) for i in range(sb.src_img_off[s], sb.src_img_off[s + 1])}
+            v0, g0, H0 = oracle_eval(sb, s, th[s], nbr=onbr)
+            tag = f"{what} point {k} source {s}"
+            _say(tag, "elbo", el[s], v0, "gerr", deriv_err(g[s], g0), "herr", deriv_err(H[s], H0))
+            assert_elbo_close(el[s], v0, what=tag)
+            assert_derivs_close(g[s], H[s], g0, H0, what=tag)
+
+
+def test_config0_three_points(cb, ctx, cfg0):
+    _say("case: config0, 3 points")
+    _check_batch(cb, ctx, cfg0, _points(cfg0, 1), what="cfg0")
+
+
+def test_config1_ragged_subset_small_chunks(cb, ctx):
+    """Sources of the smallest and largest patch sides, work items of 512 px (ragged tails)."""
+    full = synth.make_config(1)
+    side = full.truth["side"]
+    idx = list(np.argsort(side)[:3]) + list(np.argsort(side)[-3:])
+    sb = full.subset(idx)
+    _say("case: config1 subset sides", side[idx])
+    ctx.set_option(cb.OPT_CHUNK_PX, 512)
+    try:
+        _check_batch(cb, ctx, sb, [perturb_theta(sb.theta_truth, 3)], what="cfg1")
+    finally:
+        ctx.set_option(cb.OPT_CHUNK_PX, 4096)
+
+
+def test_multi_epoch_wcs_offsets(cb, ctx):
+    full = synth.make_config(2, n_sources=40)
+    npx = np.array([np.sum(full.img_h[full.src_img_off[s]:full.src_img_off[s + 1]].astype(np.int64) ** 2)
+                    for s in range(full.n_sources)])
+    multi = [s for s in range(full.n_sources) if full.truth["epochs"][s] > 1 and npx[s] < 60000]
+    sb = full.subset(multi[:3])
+    _say("case: multi-epoch", sb.truth["epochs"], sb.truth["side"])
+    _check_batch(cb, ctx, sb, [perturb_theta(sb.theta_truth, 4), sb.theta_truth], what="cfg2")
+
+
+def test_neighbours_and_general_wcs(cb, ctx, cfg0):
+    sb = cfg0.subset([0])
+    rng = np.random.default_rng(5)
+    ang = 0.4
+    A = 0.9 * np.array([[math.cos(ang), -math.sin(ang)], [math.sin(ang), math.cos(ang)]])
+    sb.img_wcs[:, 0:4] = A.ravel()
+    sb.img_wcs[:, 4:6] = [1.3, -0.7]
+    n = sb.n_pixels
+    nbr = (rng.uniform(0, 30, n).astype(np.float32), rng.uniform(0, 8, n).astype(np.float32))
+    th = perturb_theta(sb.theta_truth, 6)
+    th[:, 0:2] = np.linalg.solve(A, (np.array([15.0, 15.0]) - sb.img_wcs[0, 4:6]))[None, :]
+    _say("case: neighbours + rotated WCS")
+    _check_batch(cb, ctx, sb, [th], nbr=nbr, what="nbr")
+
+
+@pytest.mark.parametrize("case", ["round", "pure_star", "pure_gal", "dev_edge", "bright", "tiny_patch"])
+def test_degenerate_points(cb, ctx, cfg0, case):
+    sb = cfg0.subset([0])
+    th = perturb_theta(sb.theta_truth, 7)
+    if case == "round":
+        th[0, 4] = 1.0
+    elif case == "pure_star":
+        th[0, 2] = 1 - 1e-4
+    elif case == "pure_gal":
+        th[0, 2] = 1e-4
+    elif case == "dev_edge":
+        th[0, 3] = 0.0
+    elif case == "bright":
+        sb = synth.make_config(1, n_sources=2, bright=True).subset([0])
+        th = perturb_theta(sb.theta_truth, 8)
+    elif case == "tiny_patch":
+        sb.img_h[:] = 1
+        sb.img_w[:] = 1
+        sb.img_pitch[:] = cfg0.img_w
+        th[0, 0:2] = [0.2, -0.1]
+    _say("case: degenerate", case)
+    _check_batch(cb, ctx, sb, [th], what=case)
+
+
+def test_deterministic_and_batch_equals_single(cb, ctx):
+    full = synth.make_config(1, n_sources=6)
+    th = perturb_theta(full.theta_truth, 9)
+    b = cb.Batch.from_synth(full)
+    e1, g1, H1 = ctx.elbo_eval(b, th)
+    e2, g2, H2 = ctx.elbo_eval(b, th)
+    assert np.array_equal(e1, e2) and np.array_equal(g1, g2) and np.array_equal(H1, H2)
+    for s in (0, 3, 5):
+        one = full.subset([s])
+        e, g, H = ctx.elbo_eval(cb.Batch.from_synth(one), th[s:s + 1])
+        assert e[0] == e1[s] and np.array_equal(g[0], g1[s]) and np.array_equal(H[0], H1[s])
+    # block size does not change results
+    ctx.set_option(cb.OPT_BLOCK, 128)
+    try:
+        e3, g3, H3 = ctx.elbo_eval(b, th)
+    finally:
+        ctx.set_option(cb.OPT_BLOCK, 256)
+    assert np.allclose(e3, e1, rtol=1e-12) and deriv_err(H3, H1) < 1e-9
+
+
+def test_value_only_matches_full(cb, ctx):
+    full = synth.make_config(1, n_sources=5)
+    th = perturb_theta(full.theta_truth, 10)
+    b = cb.Batch.from_synth(full)
+    ev, _, _ = ctx.elbo_eval(b, th, want="value")
+    ef, gf, _ = ctx.elbo_eval(b, th, want="grad")
+    for s in range(5):
+        v0, _, _ = oracle_eval(full, s, th[s], want="value")
+        assert_elbo_close(ev[s], v0, what=f"value-only {s}")
+        assert_elbo_close(ef[s], v0, what=f"grad-only {s}")
+
+
+def test_device_memory_batch(cb, ctx):
+    import torch
+    full = synth.make_config(1, n_sources=4)
+    dev = synth.make_config(1, n_sources=4)
+    dev.pixels = torch.from_numpy(full.pixels).cuda()
+    th = perturb_theta(full.theta_truth, 11)
+    eh, gh, Hh = ctx.elbo_eval(cb.Batch.from_synth(full), th)
+    ed, gd, Hd = ctx.elbo_eval(cb.Batch.from_synth(dev), torch.from_numpy(th).cuda())
+    assert np.array_equal(eh, ed.cpu().numpy()) and np.array_equal(Hh, Hd.cpu().numpy())
+
+
+@pytest.mark.parametrize("bad", ["nan_pixel", "neg_pixel", "band", "n_psf", "a_range", "pitch"])
+def test_invalid_inputs_rejected(cb, ctx, cfg0, bad):
+    sb = cfg0.subset([0])
+    th = sb.theta_truth.copy()
+    b = cb.Batch.from_synth(sb)
+    if bad == "nan_pixel":
+        b._keep[0][17] = np.nan
+    elif bad == "neg_pixel":
+        b._keep[0][3] = -1.0
+    elif bad == "band":
+        b.images["band"][2] = 7
+    elif bad == "n_psf":
+        b.images["n_psf"][0] = 5
+    elif bad == "a_range":
+        th[0, 2] = 1.5
+    elif bad == "pitch":
+        b.images["pitch"][1] = 3
+    with pytest.raises(cb.CelesteError) as ei:
+        ctx.elbo_eval(b, th)
+    assert ei.value.code == cb.E_INVALID
+
+
+def test_full_size_config2_sampled(cb, ctx):
+    """Config 2 at its full size on device memory, launch as the benchmark runs it;
+    the oracle checks a sample of sources one by one."""
+    import torch
+    sb = synth.make_config(2, device="cuda")
+    _say("case: config2 full size", sb.n_sources, "sources", sb.n_pixels, "pixels")
+    th = perturb_theta(sb.theta_truth, 12, scale=0.5)
+    b = cb.Batch.from_synth(sb)
+    el, g, H = ctx.elbo_eval(b, torch.from_numpy(th).cuda())
+    el, g, H = el.cpu().numpy(), g.cpu().numpy(), H.cpu().numpy()
+    assert np.all(np.isfinite(el)) and np.all(np.isfinite(H))
+    npx = np.array([np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64) ** 2)
+                    for s in range(sb.n_sources)])
+    rng = np.random.default_rng(13)
+    pick = [int(np.argmin(npx)), int(rng.integers(sb.n_sources)), int(np.argsort(npx)[len(npx) // 2])]
+    sub = sb.subset(pick)
+    for k, s in enumerate(pick):
+        v0, g0, H0 = oracle_eval(sub, k, th[s])
+        tag = f"cfg2 full source {s} ({npx[s]} px)"
+        _say(tag, el[s], v0, deriv_err(g[s], g0), deriv_err(H[s], H0))
+        assert_elbo_close(el[s], v0, what=tag)
+        assert_derivs_close(g[s], H[s], g0, H0, what=tag)
