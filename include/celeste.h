@@ -73,8 +73,21 @@ enum { CELESTE_INIT_AS_GIVEN = 0, CELESTE_INIT_PLAIN = 1 };
 enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_CHUNK_PX = 1,     /* pixels per work item (64 .. 2^24; default 4096) */
   CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
-  CELESTE_OPT_USE_GRAPH = 3     /* batched fit replays a captured HIP graph per iteration (default 1) */
+  CELESTE_OPT_USE_GRAPH = 3,    /* batched fit replays a captured HIP graph per iteration (default 1) */
+  CELESTE_OPT_PROFILE = 4       /* 1: time every kernel phase with HIP events (fits run without a graph) */
 };
+
+/* Cumulative work and time counters of a context (since creation or the last reset). */
+typedef struct celeste_stats {
+  int64_t full_px;              /* pixel evaluations by the value+gradient+Hessian kernel */
+  int64_t value_px;             /* pixel evaluations by the value-only kernel */
+  int64_t full_launches;        /* launches of the value+gradient+Hessian pixel kernel */
+  int64_t value_launches;       /* launches of the value-only pixel kernel */
+  int64_t iterations;           /* trust-region iterations enqueued (all sources together) */
+  /* milliseconds per phase, measured with HIP events on the library's stream; only
+   * accumulated while CELESTE_OPT_PROFILE is set */
+  double ms_setup, ms_full, ms_reduce_full, ms_tr, ms_value, ms_reduce_value, ms_accept;
+} celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;
 
@@ -162,9 +175,12 @@ const char* celeste_last_error(void);
  * E_INVALID (unknown option or value out of range). */
 int celeste_ctx_set_option(celeste_ctx* ctx, int option, int64_t value);
 
+/* Read (and optionally reset) the context's counters.  Errors: E_INVALID, E_DEVICE. */
+int celeste_ctx_get_stats(celeste_ctx* ctx, celeste_stats* out, int reset);
+
 /* sizeof of the ABI structs, for bindings to check their layouts: 0 celeste_image,
  * 1 celeste_prior, 2 celeste_profiles, 3 celeste_batch, 4 celeste_fit_opts,
- * 5 celeste_fit_result; 0 for any other value. */
+ * 5 celeste_fit_result, 6 celeste_stats; 0 for any other value. */
 size_t celeste_struct_size(int which);
 
 /* Defaults for celeste_fit_opts (values in the comments above). */

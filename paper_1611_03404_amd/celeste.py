@@ -24,7 +24,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
 CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE = 0, 1, 2, 3
 INIT_AS_GIVEN, INIT_PLAIN = 0, 1
-OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH = 1, 2, 3
+OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE = 1, 2, 3, 4
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("reserved", "<i4"),
@@ -49,6 +49,13 @@ class FitOpts(ctypes.Structure):
                 ("curv_tol", ctypes.c_double), ("delta0", ctypes.c_double), ("delta_max", ctypes.c_double),
                 ("delta_min", ctypes.c_double), ("eta", ctypes.c_double), ("u_box", ctypes.c_double),
                 ("poll_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("full_px", ctypes.c_int64), ("value_px", ctypes.c_int64), ("full_launches", ctypes.c_int64),
+                ("value_launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("ms_setup", ctypes.c_double),
+                ("ms_full", ctypes.c_double), ("ms_reduce_full", ctypes.c_double), ("ms_tr", ctypes.c_double),
+                ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double)]
 
 
 class CelesteError(RuntimeError):
@@ -81,12 +88,13 @@ def load():
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_newton_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_batch_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp, vp]
+    lib.celeste_ctx_get_stats.argtypes = [vp, ctypes.POINTER(Stats), ctypes.c_int]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
-                 "celeste_batch_fit"):
+                 "celeste_batch_fit", "celeste_ctx_get_stats"):
         getattr(lib, name).restype = ctypes.c_int
-    sizes = [lib.celeste_struct_size(k) for k in range(6)]
+    sizes = [lib.celeste_struct_size(k) for k in range(7)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
-              ctypes.sizeof(FitOpts), RESULT_DT.itemsize]
+              ctypes.sizeof(FitOpts), RESULT_DT.itemsize, ctypes.sizeof(Stats)]
     if sizes != expect:
         raise RuntimeError(f"ABI struct sizes differ: library {sizes}, binding {expect}")
     _lib = lib
@@ -188,12 +196,16 @@ class Batch:
             return torch.empty(shape, dtype=torch.float64, device=self.torch_device)
         return np.empty(shape, dtype=np.float64)
 
-    def as_input(self, x):
+    def as_input(self, x, copy=False):
+        """x as an array of the batch's memory kind; copy=True always returns a fresh array
+        (used for the in/out parameter of the fits, so the caller's start is not overwritten)."""
         if self.device:
             import torch
-            return torch.as_tensor(np.asarray(x) if not _is_torch(x) else x, dtype=torch.float64,
-                                   device=self.torch_device).contiguous()
-        return np.ascontiguousarray(x.cpu().numpy() if _is_torch(x) else x, dtype=np.float64)
+            t = torch.as_tensor(np.asarray(x) if not _is_torch(x) else x, dtype=torch.float64,
+                                device=self.torch_device).contiguous()
+            return t.clone() if copy else t
+        a = np.ascontiguousarray(x.cpu().numpy() if _is_torch(x) else x, dtype=np.float64)
+        return a.copy() if copy else a
 
 
 class Context:
@@ -217,6 +229,11 @@ class Context:
 
     def set_option(self, option, value):
         _check(load().celeste_ctx_set_option(self._h, int(option), int(value)))
+
+    def stats(self, reset=False):
+        st = Stats()
+        _check(load().celeste_ctx_get_stats(self._h, ctypes.byref(st), 1 if reset else 0))
+        return {name: getattr(st, name) for name, _ in Stats._fields_}
 
     def _stream(self, batch):
         # Work on device tensors queued by torch must be complete before the library's
@@ -243,7 +260,8 @@ class Context:
     def newton_fit(self, batch: Batch, theta0, opts=None):
         if batch.n_sources != 1:
             raise ValueError("newton_fit takes one source")
-        th = batch.as_input(np.asarray(theta0).reshape(1, NP) if not _is_torch(theta0) else theta0.reshape(1, NP))
+        th = batch.as_input(np.asarray(theta0).reshape(1, NP) if not _is_torch(theta0) else theta0.reshape(1, NP),
+                            copy=True)
         res = np.zeros(1, dtype=RESULT_DT)
         o = opts if opts is not None else default_opts()
         self._stream(batch)
@@ -253,7 +271,7 @@ class Context:
 
     def batch_fit(self, batch: Batch, theta0, opts=None):
         S = batch.n_sources
-        th = batch.as_input(theta0)
+        th = batch.as_input(theta0, copy=True)
         if tuple(th.shape) != (S, NP):
             raise ValueError(f"theta0 must have shape ({S}, {NP})")
         res = np.zeros(S, dtype=RESULT_DT)

@@ -60,6 +60,9 @@ struct celeste_ctx {
   int use_graph = 1;
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
+  DevBuf ctr;      // device pixel-evaluation counters [full, value]
+  int profile = 0;
+  celeste_stats stats{};
 };
 
 namespace {
@@ -280,6 +283,9 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
       d.item_end = (int)P->items.size();
     }
     sd.item_end = (int)P->items.size();
+    sd.npix = 0;
+    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i)
+      sd.npix += (int64_t)b->images[i].h * b->images[i].w;
     P->srcs[s] = sd;
   }
   if (P->items.size() > (size_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
@@ -347,6 +353,33 @@ int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st)
 
 hipStream_t pick(celeste_ctx* ctx, void* stream) { return stream ? (hipStream_t)stream : ctx->stream; }
 
+unsigned long long* ctr_full(celeste_ctx* c) { return as<unsigned long long>(c->ctr); }
+unsigned long long* ctr_value(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 1; }
+
+// HIP events between the kernel phases of one iteration (profile mode).
+struct PhaseTimer {
+  bool on = false;
+  hipEvent_t ev[9] = {};
+  int init(bool enable) {
+    on = enable;
+    if (!on) return CELESTE_OK;
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    return CELESTE_OK;
+  }
+  ~PhaseTimer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int k, hipStream_t st) {
+    if (on) (void)hipEventRecord(ev[k], st);
+  }
+  float span(int a, int b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+    return ms;
+  }
+};
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -384,7 +417,29 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
+  if (ensure(c->ctr, 2 * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipStreamDestroy(c->stream);
+    if (c->ctr.p) (void)hipFree(c->ctr.p);
+    delete c;
+    return fail(CELESTE_E_DEVICE, "counter allocation failed");
+  }
   *out = c;
+  return CELESTE_OK;
+}
+
+int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
+  if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
+  HIPCHK(hipSetDevice(c->device));
+  unsigned long long h[2] = {0, 0};
+  HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
+  c->stats.full_px = (int64_t)h[0];
+  c->stats.value_px = (int64_t)h[1];
+  *out = c->stats;
+  if (reset) {
+    HIPCHK(hipMemset(c->ctr.p, 0, sizeof(h)));
+    c->stats = celeste_stats{};
+  }
   return CELESTE_OK;
 }
 
@@ -393,7 +448,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
-                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf};
+                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipStreamDestroy(c->stream);
@@ -414,6 +469,9 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
     case CELESTE_OPT_USE_GRAPH:
       c->use_graph = value ? 1 : 0;
       return CELESTE_OK;
+    case CELESTE_OPT_PROFILE:
+      c->profile = value ? 1 : 0;
+      return CELESTE_OK;
     default:
       return fail(CELESTE_E_INVALID, "unknown option %d", option);
   }
@@ -427,6 +485,7 @@ size_t celeste_struct_size(int which) {
     case 3: return sizeof(celeste_batch);
     case 4: return sizeof(celeste_fit_opts);
     case 5: return sizeof(celeste_fit_result);
+    case 6: return sizeof(celeste_stats);
     default: return 0;
   }
 }
@@ -468,24 +527,39 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
     }
   }
   const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
+  T.mark(0, st);
   HIPCHK(launch_setup(imgs, P.n_img, th_dev, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  T.mark(1, st);
   if (grad) {
     HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+    T.mark(2, st);
     HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
-                              as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess, st));
+                              as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
+                              ctr_full(ctx), st));
+    ctx->stats.full_launches += 1;
   } else {
     HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                              P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+    T.mark(2, st);
     HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
-                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, st));
+                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, ctr_value(ctx), st));
+    ctx->stats.value_launches += 1;
   }
+  T.mark(3, st);
   if (b->mem_kind == CELESTE_MEM_HOST) {
     HIPCHK(hipMemcpyAsync(elbo, d_elbo, sizeof(double) * S, hipMemcpyDeviceToHost, st));
     if (grad) HIPCHK(hipMemcpyAsync(grad, d_grad, sizeof(double) * NP * S, hipMemcpyDeviceToHost, st));
     if (hess) HIPCHK(hipMemcpyAsync(hess, d_hess, sizeof(double) * NP * NP * S, hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (T.on) {
+    ctx->stats.ms_setup += T.span(0, 1);
+    (grad ? ctx->stats.ms_full : ctx->stats.ms_value) += T.span(1, 2);
+    (grad ? ctx->stats.ms_reduce_full : ctx->stats.ms_reduce_value) += T.span(2, 3);
+  }
   return CELESTE_OK;
 }
 
@@ -546,25 +620,49 @@ int check_opts(const celeste_fit_opts* o) {
 
 // Enqueues one trust-region iteration over all sources (each kernel skips sources
 // whose flag is clear).
-int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const FitParams& fp, hipStream_t st) {
+int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const FitParams& fp, hipStream_t st,
+                      PhaseTimer* T) {
   const ImgDev* imgs = as<ImgDev>(ctx->imgs);
   const WorkItem* items = as<WorkItem>(ctx->items);
   const SrcDev* srcs = as<SrcDev>(ctx->srcs);
   float* tables = as<float>(ctx->tables);
   double* parts = as<double>(ctx->partials);
   const double* ic = as<double>(ctx->img_const);
+  T->mark(0, st);
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
+  T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
                           ctx->block, st));
-  HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H, st));
+  T->mark(2, st);
+  HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
+                            ctr_full(ctx), st));
+  T->mark(3, st);
   HIPCHK(launch_zero_int(F.n_active, 1, st));
   HIPCHK(launch_tr_step(F, P.n_src, fp, st));
+  T->mark(4, st);
   HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, F.active, P.prof, tables, P.tstride, st));
+  T->mark(5, st);
   HIPCHK(launch_eval_value(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.active, parts,
                            ctx->block, st));
-  HIPCHK(launch_reduce_value(srcs, P.n_src, imgs, parts, ic, F.theta_trial, P.prior, F.active, F.f_trial, st));
+  T->mark(6, st);
+  HIPCHK(launch_reduce_value(srcs, P.n_src, imgs, parts, ic, F.theta_trial, P.prior, F.active, F.f_trial,
+                             ctr_value(ctx), st));
+  T->mark(7, st);
   HIPCHK(launch_accept(F, P.n_src, fp, st));
+  T->mark(8, st);
   return CELESTE_OK;
+}
+
+void accumulate_phases(celeste_ctx* ctx, PhaseTimer& T) {
+  if (!T.on) return;
+  celeste_stats& s = ctx->stats;
+  s.ms_setup += T.span(0, 1) + T.span(4, 5);
+  s.ms_full += T.span(1, 2);
+  s.ms_reduce_full += T.span(2, 3);
+  s.ms_tr += T.span(3, 4);
+  s.ms_value += T.span(5, 6);
+  s.ms_reduce_value += T.span(6, 7);
+  s.ms_accept += T.span(7, 8);
 }
 
 int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
@@ -611,16 +709,20 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
   HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs, as<double>(ctx->partials), as<double>(ctx->img_const),
-                             F.theta, P.prior, nullptr, F.f, st));
+                             F.theta, P.prior, nullptr, F.f, ctr_value(ctx), st));
+  ctx->stats.value_launches += 1;
   HIPCHK(launch_fit_start(F, S, st));
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
 
   const int max_loops = o->max_iter + 1;
-  const int poll = batched ? std::max(1, o->poll_every) : 1;
+  const int poll = (batched && !T.on) ? std::max(1, o->poll_every) : 1;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  if (batched && ctx->use_graph) {
+  if (batched && ctx->use_graph && !T.on) {
+    PhaseTimer none;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iteration(ctx, P, F, fp, st);
+    int rc = enqueue_iteration(ctx, P, F, fp, st, &none);
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (rc != CELESTE_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -639,9 +741,12 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
         break;
       }
     } else {
-      rc = enqueue_iteration(ctx, P, F, fp, st);
+      rc = enqueue_iteration(ctx, P, F, fp, st, &T);
       if (rc != CELESTE_OK) break;
     }
+    ctx->stats.iterations += 1;
+    ctx->stats.full_launches += 1;
+    ctx->stats.value_launches += 1;
     if ((it + 1) % poll == 0 || it + 1 == max_loops) {
       hipError_t e = hipMemcpyAsync(&n_active, F.n_active, sizeof(int), hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -649,6 +754,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
         rc = fail(CELESTE_E_DEVICE, "active-count readback: %s", hipGetErrorString(e));
         break;
       }
+      accumulate_phases(ctx, T);
     }
   }
   if (exec) (void)hipGraphExecDestroy(exec);

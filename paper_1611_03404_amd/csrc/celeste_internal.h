@@ -34,6 +34,7 @@ struct WorkItem {
 // Source -> images / work items (CSR, contiguous).
 struct SrcDev {
   int32_t img_begin, img_end, item_begin, item_end;
+  int64_t npix;                   // pixels over all the source's images
 };
 
 // Prior with the colour covariance inverse and log-determinant precomputed (FP64).
@@ -96,10 +97,11 @@ hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* i
                              int block, hipStream_t st);
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                              double* elbo, double* grad, double* hess, hipStream_t st);
+                              double* elbo, double* grad, double* hess, unsigned long long* px_ctr,
+                              hipStream_t st);
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                               double* elbo, hipStream_t st);
+                               double* elbo, unsigned long long* px_ctr, hipStream_t st);
 
 // ---------------------------------------------------------------- trust-region state
 struct FitDev {

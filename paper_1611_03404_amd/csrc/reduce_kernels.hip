@@ -113,7 +113,8 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
                                                     const double* __restrict__ img_const,
                                                     const double* __restrict__ theta, PriorDev prior,
                                                     const int* __restrict__ src_flag, double* __restrict__ elbo,
-                                                    double* __restrict__ grad, double* __restrict__ hess) {
+                                                    double* __restrict__ grad, double* __restrict__ hess,
+                                                    unsigned long long* __restrict__ px_ctr) {
   __shared__ double tmp[NACC];
   __shared__ double Hz[NZ * NZ];
   __shared__ double Ht[NP * NP];
@@ -166,7 +167,10 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
   }
   if (t == 0) kl_value_grad(th, prior, kl);
   __syncthreads();
-  if (t == 0) elbo[s] = vt + kl.val;
+  if (t == 0) {
+    elbo[s] = vt + kl.val;
+    if (px_ctr) atomicAdd(px_ctr, (unsigned long long)sr.npix);
+  }
   if (grad && t < NP) grad[(size_t)s * NP + t] = gt[t] + kl.g[t];
   if (hess) {
     for (int k = t; k < NP * NP; k += RB) {
@@ -182,7 +186,8 @@ __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict_
                                                        const double* __restrict__ partials,
                                                        const double* __restrict__ img_const,
                                                        const double* __restrict__ theta, PriorDev prior,
-                                                       const int* __restrict__ src_flag, double* __restrict__ elbo) {
+                                                       const int* __restrict__ src_flag, double* __restrict__ elbo,
+                                                       unsigned long long* __restrict__ px_ctr) {
   const int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= n_src) return;
   if (src_flag && !src_flag[s]) return;
@@ -197,25 +202,27 @@ __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict_
   KL k;
   kl_value_grad(theta + (size_t)s * NP, prior, k);
   elbo[s] = v + k.val;
+  if (px_ctr) atomicAdd(px_ctr, (unsigned long long)sr.npix);
 }
 
 }  // namespace
 
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                              double* elbo, double* grad, double* hess, hipStream_t st) {
+                              double* elbo, double* grad, double* hess, unsigned long long* px_ctr,
+                              hipStream_t st) {
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_full, dim3(n_src), dim3(RB), 0, st, srcs, imgs, partials, img_const, theta, prior,
-                     src_flag, elbo, grad, hess);
+                     src_flag, elbo, grad, hess, px_ctr);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                               double* elbo, hipStream_t st) {
+                               double* elbo, unsigned long long* px_ctr, hipStream_t st) {
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_value_t, dim3((n_src + 63) / 64), dim3(64), 0, st, srcs, n_src, imgs, partials,
-                     img_const, theta, prior, src_flag, elbo);
+                     img_const, theta, prior, src_flag, elbo, px_ctr);
   return hipGetLastError();
 }
 

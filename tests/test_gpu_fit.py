@@ -1,0 +1,124 @@
+"""GPU trust-region fits (celeste_newton_fit / celeste_batch_fit) against oracle fits."""
+import multiprocessing as mp
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import init as oinit
+from oracle import model, newton
+from helpers import ELBO_RTOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1611_03404_amd import celeste as cb_
+    cb_.load()
+    return cb_
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle_fit(args):
+    sb, s = args
+    imgs = model.source_images(sb, s)
+    th0 = oinit.plain_init(sb.u_cat[s], imgs, sb.prior)
+    r = newton.fit(th0, imgs, sb.prior, sb.profiles)
+    return th0, r.theta, r.elbo, r.iters, r.status
+
+
+def _oracle_fits(sb):
+    with mp.get_context("fork").Pool(min(8, sb.n_sources)) as pool:
+        return pool.map(_oracle_fit, [(sb, s) for s in range(sb.n_sources)])
+
+
+def _fit_ok(sb, s, theta_gpu, elbo_ref):
+    """A22 rule: the oracle's ELBO at the GPU result is within 1e-5 relative of the oracle
+    optimum, or above it."""
+    v = model.elbo_value(theta_gpu, model.source_images(sb, s), sb.prior, sb.profiles)
+    return v >= elbo_ref - ELBO_RTOL * abs(elbo_ref), v
+
+
+def test_newton_fit_config0(cb, ctx):
+    sb = synth.make_config(0)
+    th0, th_ref, e_ref, it_ref, st_ref = _oracle_fit((sb, 0))
+    th, res = ctx.newton_fit(cb.Batch.from_synth(sb), th0)
+    ok, v = _fit_ok(sb, 0, th[0], e_ref)
+    _say("newton config0: gpu", res["elbo"], v, res["iters"], res["status"], "oracle", e_ref, it_ref, st_ref)
+    assert res["status"] == cb.CONVERGED and res["iters"] <= 50
+    assert ok
+    assert abs(res["elbo"] - v) <= ELBO_RTOL * abs(v)
+
+
+def test_batch_fit_config1_subset(cb, ctx):
+    full = synth.make_config(1)
+    sb = full.subset(list(range(12)))
+    ref = _oracle_fits(sb)
+    th0 = np.stack([r[0] for r in ref])
+    b = cb.Batch.from_synth(sb)
+    th, res = ctx.batch_fit(b, th0)
+    # the device plain start reproduces the oracle's plain start
+    thp = sb.theta_truth.copy()
+    thp[:, 0:2] = sb.u_cat
+    th2, res2 = ctx.batch_fit(b, thp, cb.default_opts(init_mode=cb.INIT_PLAIN))
+    n_ok = 0
+    for s in range(sb.n_sources):
+        ok, v = _fit_ok(sb, s, th[s], ref[s][2])
+        ok2, v2 = _fit_ok(sb, s, th2[s], ref[s][2])
+        _say(f"source {s}: gpu {v:.6f} it {res['iters'][s]} st {res['status'][s]} | plain-start {v2:.6f} "
+             f"it {res2['iters'][s]} | oracle {ref[s][2]:.6f} it {ref[s][3]} st {ref[s][4]}")
+        n_ok += ok and ok2
+        assert res["iters"][s] <= 50
+    assert n_ok == sb.n_sources
+
+
+def test_batch_equals_single_and_graph_equals_eager(cb, ctx):
+    full = synth.make_config(1, n_sources=3)
+    b = cb.Batch.from_synth(full)
+    th0 = full.theta_truth.copy()
+    th0[:, 0:2] = full.u_cat
+    o = cb.default_opts(init_mode=cb.INIT_PLAIN)
+    th_b, res_b = ctx.batch_fit(b, th0, o)
+    ctx.set_option(cb.OPT_USE_GRAPH, 0)
+    try:
+        th_e, res_e = ctx.batch_fit(b, th0, o)
+    finally:
+        ctx.set_option(cb.OPT_USE_GRAPH, 1)
+    assert np.array_equal(th_b, th_e) and np.array_equal(res_b["iters"], res_e["iters"])
+    for s in range(3):
+        one = full.subset([s])
+        th_s, res_s = ctx.newton_fit(cb.Batch.from_synth(one), th0[s], o)
+        assert np.array_equal(th_s[0], th_b[s]), s
+        assert res_s["iters"] == res_b["iters"][s]
+
+
+def test_status_paths_forced_from_host(cb, ctx):
+    sb = synth.make_config(0)
+    b = cb.Batch.from_synth(sb)
+    th0 = oinit.plain_init(sb.u_cat[0], model.source_images(sb, 0), sb.prior)[None, :]
+    _, r = ctx.batch_fit(b, th0, cb.default_opts(max_iter=1))
+    assert r["status"][0] == cb.MAX_ITER and r["iters"][0] == 1
+    _, r = ctx.batch_fit(b, th0, cb.default_opts(delta0=1e-12, delta_min=1e-10))
+    assert r["status"][0] == cb.TR_COLLAPSED
+    bad = th0.copy()
+    bad[0, 7:9] = 800.0          # brightness overflows: non-finite starting ELBO
+    _, r = ctx.batch_fit(b, bad, cb.default_opts())
+    assert r["status"][0] == cb.NONFINITE and r["iters"][0] == 0
+    with pytest.raises(cb.CelesteError):
+        ctx.batch_fit(b, th0, cb.default_opts(max_iter=0))
