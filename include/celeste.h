@@ -68,13 +68,22 @@ enum {                          /* per-source fit status */
   CELESTE_NONFINITE = 3         /* the starting point has a non-finite ELBO */
 };
 
-enum { CELESTE_INIT_AS_GIVEN = 0, CELESTE_INIT_PLAIN = 1 };
+enum {                          /* start of a fit */
+  CELESTE_INIT_AS_GIVEN = 0,    /* theta_inout as passed */
+  CELESTE_INIT_PLAIN = 1,       /* plain start from the data around theta_inout's position */
+  CELESTE_INIT_SURROGATE = 2    /* surrogate network's start, or the plain start where its ELBO is higher */
+};
+
+enum { CELESTE_FLAG_FALLBACK_USED = 1 };   /* per-source result flag: the plain start was kept */
 
 enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_CHUNK_PX = 1,     /* pixels per work item (64 .. 2^24; default 4096) */
   CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
   CELESTE_OPT_USE_GRAPH = 3,    /* batched fit replays a captured HIP graph per iteration (default 1) */
-  CELESTE_OPT_PROFILE = 4       /* 1: time every kernel phase with HIP events (fits run without a graph) */
+  CELESTE_OPT_PROFILE = 4,      /* 1: time every kernel phase with HIP events (fits run without a graph) */
+  CELESTE_OPT_VARIANT = 5       /* value+gradient+Hessian pixel-kernel variant 0..3 (default 3): bit 0 = two
+                                   resident waves per SIMD, bit 1 = loops unrolled for 6 exp + 8 dev
+                                   components; all variants compute the same arithmetic */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -90,6 +99,7 @@ typedef struct celeste_stats {
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;
+typedef struct celeste_net celeste_net;
 
 /* One band image cut-out ("patch") seen by one source (section III-A: image n has
  * metadata Lambda_n and pixels x_nm ~ Poisson(F_nm)).  Pixel element (r, c) is centred
@@ -158,7 +168,7 @@ typedef struct celeste_fit_result {
   int32_t iters;                /* trust-region iterations taken */
   int32_t status;               /* CELESTE_CONVERGED, ... */
   int32_t n_full_evals;         /* value+gradient+Hessian evaluations */
-  int32_t flags;                /* reserved, 0 */
+  int32_t flags;                /* CELESTE_FLAG_* bits */
 } celeste_fit_result;
 
 /* Create a context on HIP device `hip_device` (makes it current).  *out receives the
@@ -218,6 +228,45 @@ int celeste_newton_fit(celeste_ctx* ctx, const celeste_batch* batch, double* the
  * position).  Errors as for celeste_elbo_eval. */
 int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
                       const celeste_fit_opts* opts, celeste_fit_result* results, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Surrogate initialiser network.  A convolutional network maps a source's 5-band 32x32
+ * patch (each band's first image, centre-cropped or zero-padded around the source's
+ * position, scaled (x - sky) / sqrt(sky)) to its 27 parameters in standardised
+ * unconstrained coordinates: psi = psi_mean + psi_std * output, theta = T(psi) with the
+ * position box centred on the catalog position.  Layers: 3x3 convolutions 5->32->64->64->128
+ * (ReLU; 2x2 max-pool after the last three), dense 2048->256 (ReLU) and 256->27.  BF16
+ * activations and matrix products with FP32 accumulation; FP32 master weights and Adam.
+ * Parameter blob (float32): per convolution weights [out][in][3][3] then bias, then each
+ * dense layer's weights [out][in] then bias.  x arrays are device BF16 (n x 5 x 32 x 32),
+ * t / y device float32 (n x 27), orders device int32 (epochs x n, a permutation per epoch).
+ * The network belongs to the context's device and runs on the context's stream.
+ * ---------------------------------------------------------------------------------------- */
+int64_t celeste_net_num_params(void);
+int celeste_net_create(celeste_ctx* ctx, const float* params, int64_t n_params, const float* psi_mean,
+                       const float* psi_std, celeste_net** out);
+void celeste_net_destroy(celeste_net* net);
+int celeste_net_get_params(celeste_net* net, float* params_out /* host */);
+/* Mean squared error over batch x 27 outputs and its gradient (host, n_params; may be NULL). */
+int celeste_net_loss_grad(celeste_net* net, const void* x, const float* t, int batch, float* loss_out,
+                          float* grad_out);
+int celeste_net_forward(celeste_net* net, const void* x, int64_t n, float* y);
+/* Adam (lr, betas 0.9 / 0.999, eps 1e-8) over minibatches in the given orders; epoch_loss
+ * (host, epochs entries, may be NULL) receives the mean minibatch loss of each epoch. */
+int celeste_net_train(celeste_net* net, const void* x, const float* t, int64_t n, const int32_t* orders,
+                      int epochs, int batch, float lr, float* epoch_loss);
+/* Network inputs for every source of a batch around theta's positions (theta in mem_kind
+ * memory, n_sources x 27; out: device BF16 n_sources x 5 x 32 x 32). */
+int celeste_make_patches(celeste_ctx* ctx, const celeste_batch* batch, const double* theta, void* out);
+/* Network used by CELESTE_INIT_SURROGATE (NULL to clear).  The context does not own it. */
+int celeste_ctx_set_surrogate(celeste_ctx* ctx, celeste_net* net);
+
+/* Unconstrained coordinates of the fits (host arrays, n x 27): position in a box of
+ * half-width u_box around u0 (n x 2) by a scaled logistic, a and e_dev on [1e-4, 1-1e-4],
+ * e_axis on [0.01, 0.99], e_scale on [0.2, 15] by scaled logistics, variances by exp,
+ * the rest identity.  Values outside a box are clipped into it first. */
+int celeste_theta_to_psi(const double* theta, const double* u0, int64_t n, double u_box, double* psi);
+int celeste_psi_to_theta(const double* psi, const double* u0, int64_t n, double u_box, double* theta);
 
 #ifdef __cplusplus
 }

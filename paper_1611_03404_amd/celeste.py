@@ -23,8 +23,9 @@ NP = 27
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
 CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE = 0, 1, 2, 3
-INIT_AS_GIVEN, INIT_PLAIN = 0, 1
-OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE = 1, 2, 3, 4
+INIT_AS_GIVEN, INIT_PLAIN, INIT_SURROGATE = 0, 1, 2
+FLAG_FALLBACK_USED = 1
+OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("reserved", "<i4"),
@@ -89,8 +90,22 @@ def load():
     lib.celeste_newton_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_batch_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp, vp]
     lib.celeste_ctx_get_stats.argtypes = [vp, ctypes.POINTER(Stats), ctypes.c_int]
+    lib.celeste_net_num_params.restype = i64
+    lib.celeste_net_create.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(vp)]
+    lib.celeste_net_destroy.argtypes = [vp]
+    lib.celeste_net_destroy.restype = None
+    lib.celeste_net_get_params.argtypes = [vp, vp]
+    lib.celeste_net_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
+    lib.celeste_net_forward.argtypes = [vp, vp, i64, vp]
+    lib.celeste_net_train.argtypes = [vp, vp, vp, i64, vp, ctypes.c_int, ctypes.c_int, ctypes.c_float, vp]
+    lib.celeste_make_patches.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp]
+    lib.celeste_ctx_set_surrogate.argtypes = [vp, vp]
+    lib.celeste_theta_to_psi.argtypes = [vp, vp, i64, ctypes.c_double, vp]
+    lib.celeste_psi_to_theta.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
-                 "celeste_batch_fit", "celeste_ctx_get_stats"):
+                 "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
+                 "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
+                 "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta"):
         getattr(lib, name).restype = ctypes.c_int
     sizes = [lib.celeste_struct_size(k) for k in range(7)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
@@ -269,6 +284,20 @@ class Context:
                                          res.ctypes.data))
         return th, res[0]
 
+    def set_surrogate(self, net):
+        _check(load().celeste_ctx_set_surrogate(self._h, net._h if net is not None else None))
+        self._net = net
+
+    def make_patches(self, batch: Batch, theta):
+        """Network inputs (torch BF16 on the device, S x 5 x 32 x 32) around theta's positions."""
+        import torch
+        th = batch.as_input(theta)
+        dev = batch.torch_device if batch.device else torch.device("cuda", self.device)
+        out = torch.empty((batch.n_sources, 5, 32, 32), dtype=torch.bfloat16, device=dev)
+        self._stream(batch)
+        _check(load().celeste_make_patches(self._h, ctypes.byref(batch.c), _ptr(th), out.data_ptr()))
+        return out
+
     def batch_fit(self, batch: Batch, theta0, opts=None):
         S = batch.n_sources
         th = batch.as_input(theta0, copy=True)
@@ -279,3 +308,79 @@ class Context:
         _check(load().celeste_batch_fit(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o),
                                         res.ctypes.data, self._stream(batch)))
         return th, res
+
+
+def theta_to_psi(theta, u0, u_box=3.0):
+    theta = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NP)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(theta)
+    _check(load().celeste_theta_to_psi(theta.ctypes.data, u0.ctypes.data, theta.shape[0], u_box, out.ctypes.data))
+    return out
+
+
+def psi_to_theta(psi, u0, u_box=3.0):
+    psi = np.ascontiguousarray(psi, dtype=np.float64).reshape(-1, NP)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(psi)
+    _check(load().celeste_psi_to_theta(psi.ctypes.data, u0.ctypes.data, psi.shape[0], u_box, out.ctypes.data))
+    return out
+
+
+class Net:
+    """The surrogate initialiser network on a context's device (weights in FP32 + BF16)."""
+
+    def __init__(self, ctx: Context, params, psi_mean, psi_std):
+        lib = load()
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        mean = np.ascontiguousarray(psi_mean, dtype=np.float32)
+        sd = np.ascontiguousarray(psi_std, dtype=np.float32)
+        h = ctypes.c_void_p()
+        _check(lib.celeste_net_create(ctx._h, params.ctypes.data, params.size, mean.ctypes.data, sd.ctypes.data,
+                                      ctypes.byref(h)))
+        self._h = h
+        self.psi_mean, self.psi_std = mean, sd
+
+    @staticmethod
+    def num_params():
+        return int(load().celeste_net_num_params())
+
+    def close(self):
+        if self._h:
+            load().celeste_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(self.num_params(), dtype=np.float32)
+        _check(load().celeste_net_get_params(self._h, out.ctypes.data))
+        return out
+
+    def loss_grad(self, x, t, want_grad=True):
+        import torch
+        torch.cuda.synchronize()
+        loss = ctypes.c_float()
+        g = np.empty(self.num_params(), dtype=np.float32) if want_grad else None
+        _check(load().celeste_net_loss_grad(self._h, x.data_ptr(), t.data_ptr(), int(x.shape[0]),
+                                            ctypes.byref(loss), g.ctypes.data if g is not None else None))
+        return float(loss.value), g
+
+    def forward(self, x):
+        import torch
+        torch.cuda.synchronize()
+        y = torch.empty((x.shape[0], 27), dtype=torch.float32, device=x.device)
+        _check(load().celeste_net_forward(self._h, x.data_ptr(), int(x.shape[0]), y.data_ptr()))
+        return y
+
+    def train(self, x, t, orders, batch=256, lr=1e-3):
+        import torch
+        torch.cuda.synchronize()
+        epochs = int(orders.shape[0])
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(load().celeste_net_train(self._h, x.data_ptr(), t.data_ptr(), int(x.shape[0]), orders.data_ptr(),
+                                        epochs, int(batch), float(lr), losses.ctypes.data))
+        return losses

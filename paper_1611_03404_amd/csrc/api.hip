@@ -33,6 +33,14 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace celeste {
+void set_error(const char* msg) { g_err = msg; }
+}  // namespace celeste
+
+namespace {
+
 #define HIPCHK(x)                                                                          \
   do {                                                                                     \
     hipError_t e_ = (x);                                                                   \
@@ -58,12 +66,20 @@ struct celeste_ctx {
   int chunk_px = 4096;
   int block = 256;
   int use_graph = 1;
+  int variant = 3;   // pixel-kernel variant (register budget / unrolling), see CELESTE_OPT_VARIANT
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
   DevBuf ctr;      // device pixel-evaluation counters [full, value]
   int profile = 0;
   celeste_stats stats{};
+  celeste_net* net = nullptr;   // surrogate network (not owned)
+  DevBuf sur;                   // surrogate predictions (float, S x 27)
 };
+
+namespace celeste {
+int ctx_device(const celeste_ctx* c) { return c->device; }
+hipStream_t ctx_stream(const celeste_ctx* c) { return c->stream; }
+}  // namespace celeste
 
 namespace {
 
@@ -448,7 +464,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
-                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr};
+                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipStreamDestroy(c->stream);
@@ -471,6 +487,10 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
       return CELESTE_OK;
     case CELESTE_OPT_PROFILE:
       c->profile = value ? 1 : 0;
+      return CELESTE_OK;
+    case CELESTE_OPT_VARIANT:
+      if (value < 0 || value > 3) return fail(CELESTE_E_INVALID, "variant must be in 0..3");
+      c->variant = (int)value;
       return CELESTE_OK;
     default:
       return fail(CELESTE_E_INVALID, "unknown option %d", option);
@@ -534,7 +554,7 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
   T.mark(1, st);
   if (grad) {
     HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant, st));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
@@ -575,7 +595,7 @@ struct FitBufs {
 
 int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   const size_t nd = (size_t)S * (NP * 5 + NP * NP + 2 + 7);
-  const size_t ni = (size_t)S * 5 + 1;
+  const size_t ni = (size_t)S * 6 + 1;
   CHK(ensure(ctx->st_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
   double* d = as<double>(ctx->st_buf);
   auto take = [&](size_t n) {
@@ -603,15 +623,17 @@ int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   f->active = ip + 2 * S;
   f->need_full = ip + 3 * S;
   f->n_full = ip + 4 * S;
-  f->n_active = ip + 5 * S;
+  f->flags = ip + 5 * S;
+  f->n_active = ip + 6 * S;
   return CELESTE_OK;
 }
 
 int check_opts(const celeste_fit_opts* o) {
   if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
   if (o->max_iter < 1 || o->max_iter > 100000) return fail(CELESTE_E_INVALID, "max_iter must be in 1..100000");
-  if (o->init_mode != CELESTE_INIT_AS_GIVEN && o->init_mode != CELESTE_INIT_PLAIN)
-    return fail(CELESTE_E_UNSUPPORTED, "init_mode %d not supported", o->init_mode);
+  if (o->init_mode != CELESTE_INIT_AS_GIVEN && o->init_mode != CELESTE_INIT_PLAIN &&
+      o->init_mode != CELESTE_INIT_SURROGATE)
+    return fail(CELESTE_E_INVALID, "init_mode %d not known", o->init_mode);
   if (!(o->pred_rtol >= 0.0) || !(o->curv_tol >= 0.0) || !(o->delta0 > 0.0) || !(o->delta_max >= o->delta0) ||
       !(o->delta_min >= 0.0) || !(o->eta >= 0.0 && o->eta < 1.0) || !(o->u_box > 0.0))
     return fail(CELESTE_E_INVALID, "fit options out of range");
@@ -632,7 +654,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, st));
+                          ctx->block, ctx->variant, st));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -680,8 +702,10 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     HIPCHK(hipMemcpyAsync(th.data(), theta_inout, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  if (o->init_mode == CELESTE_INIT_SURROGATE && !ctx->net)
+    return fail(CELESTE_E_INVALID, "CELESTE_INIT_SURROGATE needs a network (celeste_ctx_set_surrogate)");
   for (int s = 0; s < S; ++s) {
-    if (o->init_mode == CELESTE_INIT_PLAIN) {
+    if (o->init_mode != CELESTE_INIT_AS_GIVEN) {
       if (!finite(th[(size_t)s * NP]) || !finite(th[(size_t)s * NP + 1]))
         return fail(CELESTE_E_INVALID, "theta[%d]: position must be finite", s);
     } else {
@@ -701,8 +725,29 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   fp.eta = o->eta;
   fp.u_box = o->u_box;
   HIPCHK(hipMemcpyAsync(F.theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st));
-  if (o->init_mode == CELESTE_INIT_PLAIN)
-    HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, as<ImgDev>(ctx->imgs), P.prior, F.theta, st));
+  HIPCHK(launch_zero_int(F.flags, S, st));
+  const ImgDev* imgs0 = as<ImgDev>(ctx->imgs);
+  if (o->init_mode == CELESTE_INIT_SURROGATE) {
+    // network start (from the catalog positions in F.theta) into theta_trial, plain start into theta,
+    // both evaluated; the better one is kept
+    CHK(ensure(ctx->sur, sizeof(float) * NP * (size_t)S));
+    CHK(surrogate_predict(ctx->net, as<SrcDev>(ctx->srcs), S, imgs0, F.theta, as<float>(ctx->sur), st));
+    HIPCHK(launch_psi_to_theta(as<float>(ctx->sur), F.theta, F.theta_trial, S, o->u_box, st));
+    HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
+    for (int k = 0; k < 2; ++k) {
+      double* tk = k == 0 ? F.theta : F.theta_trial;
+      HIPCHK(launch_setup(imgs0, P.n_img, tk, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+      HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs0, as<float>(ctx->tables), P.tstride,
+                               P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+      HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs0, as<double>(ctx->partials),
+                                 as<double>(ctx->img_const), tk, P.prior, nullptr, k == 0 ? F.f : F.f_trial,
+                                 ctr_value(ctx), st));
+      ctx->stats.value_launches += 1;
+    }
+    HIPCHK(launch_choose_start(F, S, st));
+  } else if (o->init_mode == CELESTE_INIT_PLAIN) {
+    HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
+  }
   HIPCHK(launch_fit_init(F, S, fp, st));
   const ImgDev* imgs = as<ImgDev>(ctx->imgs);
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
@@ -762,7 +807,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   if (rc != CELESTE_OK) return rc;
   // results
   std::vector<double> fv(S), pred(S), delta(S);
-  std::vector<int> iter(S), status(S), nfull(S);
+  std::vector<int> iter(S), status(S), nfull(S), flags(S);
   HIPCHK(hipMemcpyAsync(th.data(), F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(fv.data(), F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(pred.data(), F.pred, sizeof(double) * S, hipMemcpyDeviceToHost, st));
@@ -770,6 +815,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   HIPCHK(hipMemcpyAsync(iter.data(), F.iter, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(status.data(), F.status, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(nfull.data(), F.n_full, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(flags.data(), F.flags, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (b->mem_kind == CELESTE_MEM_HOST)
     std::memcpy(theta_inout, th.data(), sizeof(double) * th.size());
@@ -784,7 +830,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     res[s].iters = iter[s];
     res[s].status = status[s];
     res[s].n_full_evals = nfull[s];
-    res[s].flags = 0;
+    res[s].flags = flags[s];
   }
   return CELESTE_OK;
 }
@@ -805,6 +851,88 @@ int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_in
                       celeste_fit_result* results, void* stream) {
   if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
   return run_fit(ctx, b, theta_inout, opts, results, pick(ctx, stream), true);
+}
+
+}  // extern "C"
+
+// =============================================================================== surrogate glue
+
+namespace {
+
+struct HostBox {
+  double lo, hi;
+  int kind;   // 0 identity, 1 scaled logistic, 2 exp
+};
+
+HostBox host_box(int i, const double* u0, double u_box) {
+  if (i == 0 || i == 1) return {u0[i] - u_box, u0[i] + u_box, 1};
+  if (i == 2 || i == 3) return {1e-4, 1.0 - 1e-4, 1};
+  if (i == 4) return {0.01, 0.99, 1};
+  if (i == 6) return {0.2, 15.0, 1};
+  if (i == 9 || i == 10 || i >= 19) return {0.0, 0.0, 2};
+  return {0.0, 0.0, 0};
+}
+
+}  // namespace
+
+extern "C" {
+
+int celeste_ctx_set_surrogate(celeste_ctx* ctx, celeste_net* net) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  ctx->net = net;
+  return CELESTE_OK;
+}
+
+int celeste_make_patches(celeste_ctx* ctx, const celeste_batch* b, const double* theta, void* out) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  if (!theta || !out) return fail(CELESTE_E_INVALID, "theta and out must not be NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const double* th = theta;
+  if (b->mem_kind == CELESTE_MEM_HOST) {
+    CHK(ensure(ctx->theta, sizeof(double) * NP * P.n_src));
+    HIPCHK(hipMemcpyAsync(ctx->theta.p, theta, sizeof(double) * NP * P.n_src, hipMemcpyHostToDevice, st));
+    th = as<double>(ctx->theta);
+  }
+  CHK(prepare(ctx, b, &P, st));
+  HIPCHK(launch_patches(as<SrcDev>(ctx->srcs), P.n_src, as<ImgDev>(ctx->imgs), th, out, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+int celeste_theta_to_psi(const double* theta, const double* u0, int64_t n, double u_box, double* psi) {
+  if (!theta || !u0 || !psi || n < 0 || !(u_box > 0.0)) return fail(CELESTE_E_INVALID, "bad argument");
+  for (int64_t s = 0; s < n; ++s)
+    for (int i = 0; i < NP; ++i) {
+      const HostBox bx = host_box(i, u0 + 2 * s, u_box);
+      const double t = theta[s * NP + i];
+      double v = t;
+      if (bx.kind == 2) {
+        v = std::log(t);
+      } else if (bx.kind == 1) {
+        const double span = bx.hi - bx.lo;
+        const double x = std::min(std::max(t, bx.lo + 1e-9 * span), bx.hi - 1e-9 * span);
+        const double f = (x - bx.lo) / span;
+        v = std::log(f) - std::log1p(-f);
+      }
+      psi[s * NP + i] = v;
+    }
+  return CELESTE_OK;
+}
+
+int celeste_psi_to_theta(const double* psi, const double* u0, int64_t n, double u_box, double* theta) {
+  if (!theta || !u0 || !psi || n < 0 || !(u_box > 0.0)) return fail(CELESTE_E_INVALID, "bad argument");
+  for (int64_t s = 0; s < n; ++s)
+    for (int i = 0; i < NP; ++i) {
+      const HostBox bx = host_box(i, u0 + 2 * s, u_box);
+      const double p = psi[s * NP + i];
+      double v = p;
+      if (bx.kind == 2) v = std::exp(p);
+      else if (bx.kind == 1) v = bx.lo + (bx.hi - bx.lo) / (1.0 + std::exp(-p));
+      theta[s * NP + i] = v;
+    }
+  return CELESTE_OK;
 }
 
 }  // extern "C"

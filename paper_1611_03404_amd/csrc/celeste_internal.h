@@ -91,7 +91,7 @@ hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStr
 hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st);
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                            int block, hipStream_t st);
+                            int block, int variant, hipStream_t st);
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                              int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
                              int block, hipStream_t st);
@@ -123,6 +123,7 @@ struct FitDev {
   int* active;          // S  1 while the source is being fitted
   int* need_full;       // S  1 when g/H must be recomputed at theta
   int* n_full;          // S
+  int* flags;           // S  CELESTE_FLAG_* bits
   int* n_active;        // 1 counter
 };
 
@@ -132,6 +133,18 @@ struct FitParams {
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);
+hipError_t launch_psi_to_theta(const float* psi, const double* theta_cat, double* theta_out, int n_src,
+                               double u_box, hipStream_t s);
+hipError_t launch_choose_start(FitDev st, int n_src, hipStream_t s);
+
+// context accessors used by the network code, and the shared error slot
+int ctx_device(const celeste_ctx* c);
+hipStream_t ctx_stream(const celeste_ctx* c);
+void set_error(const char* msg);
+int surrogate_predict(celeste_net* net, const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* theta_cat,
+                      float* psi_out, hipStream_t st);
+hipError_t launch_patches(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* theta, void* out,
+                          hipStream_t st);
 hipError_t launch_plain_init(const SrcDev* srcs, int n_src, const ImgDev* imgs, PriorDev prior, double* theta,
                              hipStream_t s);
 hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s);

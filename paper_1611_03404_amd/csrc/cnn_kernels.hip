@@ -1,0 +1,850 @@
+// Surrogate initialiser network: hand-written training and inference kernels.
+//
+// A small CNN maps a source's 5-band 32x32 patch to its 27 parameters (in
+// standardised unconstrained coordinates) so that the trust-region fit starts
+// closer to the optimum; the plain start remains the fallback.  Layers: four
+// 3x3 same convolutions (5->32->64->64->128, ReLU, 2x2 max-pool after the last
+// three) and dense 2048->256 (ReLU) -> 27.  Every matrix product (convolution
+// forward, data gradient and weight gradient as implicit GEMMs, dense layers)
+// runs on one gather-GEMM kernel on the BF16 matrix cores (16x16x32 MFMA, FP32
+// accumulation, split-K partials summed in a fixed order).  Activations and
+// gradients feeding a product are BF16; master weights, Adam moments, biases and
+// all reductions are FP32.
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "celeste_internal.h"
+
+namespace celeste {
+
+typedef __bf16 bf16;
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(4))) float f32x4_t;
+
+__device__ __forceinline__ bf16 to_bf16(float x) { return (bf16)x; }
+__device__ __forceinline__ float from_bf16(bf16 x) { return (float)x; }
+
+constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;
+
+// ------------------------------------------------------------------ gather loaders
+// Each loader returns A(m, k) and B(k, n) of the product C[m][n] = sum_k A(m,k) B(k,n)
+// (callers guarantee m < M, n < N, k < K).
+
+struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img][ci][p + off(kk)]
+  const bf16* W;
+  const bf16* X;
+  int Cin, H, Wd;
+  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)m * Cin * 9 + k]); }
+  __device__ float b(int k, int n) const {
+    const int ci = k / 9, kk = k - ci * 9;
+    const int HW = H * Wd, img = n / HW, p = n - img * HW;
+    const int y = p / Wd + kk / 3 - 1, x = p % Wd + kk % 3 - 1;
+    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
+    return from_bf16(X[((size_t)img * Cin + ci) * HW + y * Wd + x]);
+  }
+};
+
+struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img][co][p - off(kk)]
+  const bf16* W;
+  const bf16* dY;
+  int Cin, Cout, H, Wd;
+  __device__ float a(int m, int k) const {
+    const int co = k / 9, kk = k - co * 9;
+    return from_bf16(W[((size_t)co * Cin + m) * 9 + kk]);
+  }
+  __device__ float b(int k, int n) const {
+    const int co = k / 9, kk = k - co * 9;
+    const int HW = H * Wd, img = n / HW, p = n - img * HW;
+    const int y = p / Wd - kk / 3 + 1, x = p % Wd - kk % 3 + 1;
+    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
+    return from_bf16(dY[((size_t)img * Cout + co) * HW + y * Wd + x]);
+  }
+};
+
+struct LdConvWgrad {      // dW[co][ci*9+kk] = sum_{img,p} dY[img][co][p] X[img][ci][p + off(kk)]
+  const bf16* dY;
+  const bf16* X;
+  int Cin, Cout, H, Wd;
+  __device__ float a(int m, int k) const {
+    const int HW = H * Wd, img = k / HW, p = k - img * HW;
+    return from_bf16(dY[((size_t)img * Cout + m) * HW + p]);
+  }
+  __device__ float b(int k, int n) const {
+    const int HW = H * Wd, img = k / HW, p = k - img * HW;
+    const int ci = n / 9, kk = n - ci * 9;
+    const int y = p / Wd + kk / 3 - 1, x = p % Wd + kk % 3 - 1;
+    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
+    return from_bf16(X[((size_t)img * Cin + ci) * HW + y * Wd + x]);
+  }
+};
+
+struct LdFcFwd {          // Y[o][b] = sum_i W[o][i] X[b][i]
+  const bf16* W;
+  const bf16* X;
+  int In;
+  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)m * In + k]); }
+  __device__ float b(int k, int n) const { return from_bf16(X[(size_t)n * In + k]); }
+};
+
+struct LdFcDgrad {        // dX[i][b] = sum_o W[o][i] dY[b][o]
+  const bf16* W;
+  const bf16* dY;
+  int In, Out;
+  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)k * In + m]); }
+  __device__ float b(int k, int n) const { return from_bf16(dY[(size_t)n * Out + k]); }
+};
+
+struct LdFcWgrad {        // dW[o][i] = sum_b dY[b][o] X[b][i]
+  const bf16* dY;
+  const bf16* X;
+  int In, Out;
+  __device__ float a(int m, int k) const { return from_bf16(dY[(size_t)k * Out + m]); }
+  __device__ float b(int k, int n) const { return from_bf16(X[(size_t)k * In + n]); }
+};
+
+// C[z][m][n] = sum over the z-th K split of A(m,k) B(k,n).  Block 256 = 4 waves in a
+// 2x2 arrangement, each wave a 32x32 sub-tile of 2x2 MFMA 16x16x32 tiles.
+template <class LD>
+__global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kchunk, float* __restrict__ C) {
+  __shared__ bf16 As[TM][TKP];
+  __shared__ bf16 Bs[TN][TKP];
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int lr = t >> 2, lk = (t & 3) * 8;
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    {
+      const int m = m0 + lr;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + lk + j;
+        As[lr][lk + j] = to_bf16((m < M && k < kend) ? ld.a(m, k) : 0.f);
+      }
+      const int n = n0 + lr;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + lk + j;
+        Bs[lr][lk + j] = to_bf16((n < N && k < kend) ? ld.b(k, n) : 0.f);
+      }
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      bf16x8_t av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = As[wm + i * 16 + r16][kq + e];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        bf16x8_t bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = Bs[wn + j * 16 + r16][kq + e];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* Cz = C + (size_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < M && n < N) Cz[(size_t)m * N + n] = acc[i][j][r];
+      }
+}
+
+__device__ __forceinline__ float split_sum(const float* C, int S, size_t MN, size_t idx) {
+  float s = C[idx];
+  for (int z = 1; z < S; ++z) s += C[(size_t)z * MN + idx];
+  return s;
+}
+
+// ------------------------------------------------------------------ epilogues and elementwise
+
+// conv forward: act[img][co][p] = bf16(relu(C[co][img*HW+p] + bias[co]))
+__global__ void k_ep_conv_fwd(const float* __restrict__ C, int S, int Cout, int B, int HW,
+                              const float* __restrict__ bias, bf16* __restrict__ act) {
+  const size_t total = (size_t)B * Cout * HW;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int p = i % HW;
+    const int co = (i / HW) % Cout;
+    const int img = i / ((size_t)HW * Cout);
+    const float v = split_sum(C, S, (size_t)Cout * B * HW, (size_t)co * B * HW + (size_t)img * HW + p) + bias[co];
+    act[i] = to_bf16(fmaxf(v, 0.f));
+  }
+}
+
+// dense forward: out[b][o] = C[o][b] + bias[o], ReLU + BF16 (hidden) or FP32 (output)
+__global__ void k_ep_fc_fwd(const float* __restrict__ C, int S, int Out, int B, const float* __restrict__ bias,
+                            bf16* __restrict__ act, float* __restrict__ outf) {
+  const int total = Out * B;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int o = i % Out, b = i / Out;
+    const float v = split_sum(C, S, (size_t)Out * B, (size_t)o * B + b) + bias[o];
+    if (act) act[i] = to_bf16(fmaxf(v, 0.f));
+    if (outf) outf[i] = v;
+  }
+}
+
+// weight gradient: dW[m][n] = sum_z C[z][m][n]
+__global__ void k_ep_sum(const float* __restrict__ C, int S, int MN, float* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MN; i += gridDim.x * blockDim.x)
+    out[i] = split_sum(C, S, MN, i);
+}
+
+// 2x2 max-pool (BF16)
+__global__ void k_pool_fwd(const bf16* __restrict__ in, int BC, int H, int W, bf16* __restrict__ out) {
+  const int Ho = H / 2, Wo = W / 2;
+  const size_t total = (size_t)BC * Ho * Wo;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int x = i % Wo, y = (i / Wo) % Ho;
+    const size_t bc = i / ((size_t)Ho * Wo);
+    const bf16* q = in + bc * H * W + (2 * y) * W + 2 * x;
+    const float v = fmaxf(fmaxf(from_bf16(q[0]), from_bf16(q[1])), fmaxf(from_bf16(q[W]), from_bf16(q[W + 1])));
+    out[i] = to_bf16(v);
+  }
+}
+
+// Backward through (optional) 2x2 max-pool and ReLU.  g comes from a GEMM as C[c*Hg*Wg + q][img]
+// (dense) or C[c][img*Hg*Wg + q] (convolution), summed over splits; r is the post-ReLU
+// activation at full resolution (H x W).  The pooled gradient goes to the first maximal
+// input of its window (row-major), then is masked by r > 0.
+__global__ void k_pool_relu_bwd(const float* __restrict__ C, int S, int dense_layout, int B, int Cch, int H, int W,
+                                int pooled, const bf16* __restrict__ r, float* __restrict__ dz,
+                                bf16* __restrict__ dzb) {
+  const int Hg = pooled ? H / 2 : H, Wg = pooled ? W / 2 : W;
+  const size_t MN = (size_t)Cch * Hg * Wg * B;
+  const size_t total = (size_t)B * Cch * H * W;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int x = i % W, y = (i / W) % H;
+    const int c = (i / ((size_t)W * H)) % Cch;
+    const int img = i / ((size_t)W * H * Cch);
+    const bf16* rr = r + ((size_t)img * Cch + c) * H * W;
+    const float rv = from_bf16(rr[y * W + x]);
+    float g = 0.f;
+    if (rv > 0.f) {
+      int gy = y, gx = x;
+      bool take = true;
+      if (pooled) {
+        gy = y / 2;
+        gx = x / 2;
+        const int y0 = 2 * gy, x0 = 2 * gx;
+        const float a0 = from_bf16(rr[y0 * W + x0]), a1 = from_bf16(rr[y0 * W + x0 + 1]);
+        const float a2 = from_bf16(rr[(y0 + 1) * W + x0]), a3 = from_bf16(rr[(y0 + 1) * W + x0 + 1]);
+        const float mx = fmaxf(fmaxf(a0, a1), fmaxf(a2, a3));
+        const int first = (a0 == mx) ? 0 : (a1 == mx) ? 1 : (a2 == mx) ? 2 : 3;
+        take = first == (y - y0) * 2 + (x - x0);
+      }
+      if (take) {
+        const int q = gy * Wg + gx;
+        const size_t idx = dense_layout ? ((size_t)(c * Hg * Wg + q) * B + img)
+                                        : ((size_t)c * B * Hg * Wg + (size_t)img * Hg * Wg + q);
+        g = split_sum(C, S, MN, idx);
+      }
+    }
+    dz[i] = g;
+    dzb[i] = to_bf16(g);
+  }
+}
+
+// dense hidden-layer backward: dz[b][i] = C[i][b] * (h[b][i] > 0)
+__global__ void k_relu_bwd_fc(const float* __restrict__ C, int S, int In, int B, const bf16* __restrict__ h,
+                              float* __restrict__ dz, bf16* __restrict__ dzb) {
+  const int total = In * B;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int f = i % In, b = i / In;
+    const float g = from_bf16(h[i]) > 0.f ? split_sum(C, S, (size_t)In * B, (size_t)f * B + b) : 0.f;
+    dz[i] = g;
+    dzb[i] = to_bf16(g);
+  }
+}
+
+// bias gradient: db[c] = sum over images and positions of dz[img][c][p] (one block per channel)
+__global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dz, int B, int Cch, int HW,
+                                                   float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int i = threadIdx.x; i < B * HW; i += 256) {
+    const int img = i / HW, p = i - img * HW;
+    s += dz[((size_t)img * Cch + c) * HW + p];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = sh[0];
+}
+
+// MSE loss over the batch: dy = 2 (y - t) / (B*27); loss written by one block
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t, int n,
+                                             float* __restrict__ dy, bf16* __restrict__ dyb,
+                                             float* __restrict__ loss) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const float d = y[i] - t[i];
+    s += d * d;
+    const float g = 2.f * d / (float)n;
+    dy[i] = g;
+    dyb[i] = to_bf16(g);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] / (float)n;
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, bf16* __restrict__ wb, int n, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, bf16* __restrict__ wb, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) wb[i] = to_bf16(w[i]);
+}
+
+__global__ void k_acc_loss(const float* __restrict__ loss, float* __restrict__ acc) { *acc += *loss; }
+
+// network output (standardised) -> unconstrained coordinates: psi = mean + std * y
+__global__ void k_destandardise(const float* __restrict__ y, const float* __restrict__ mean,
+                                const float* __restrict__ sd, int n, float* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int j = i % 27;
+    out[i] = mean[j] + sd[j] * y[i];
+  }
+}
+
+// minibatch gather: xb[i] = x[order[i]], tb[i] = t[order[i]]
+__global__ void k_gather(const bf16* __restrict__ x, const float* __restrict__ t, const int* __restrict__ order,
+                         int B, int xsz, int tsz, bf16* __restrict__ xb, float* __restrict__ tb) {
+  const int i = blockIdx.x;
+  const size_t src = (size_t)order[i];
+  for (int k = threadIdx.x; k < xsz; k += blockDim.x) xb[(size_t)i * xsz + k] = x[src * xsz + k];
+  for (int k = threadIdx.x; k < tsz; k += blockDim.x) tb[(size_t)i * tsz + k] = t[src * tsz + k];
+}
+
+// Network input: for each source and band, the first image of that band, centre-cropped
+// (or zero-padded) to 32x32 around the catalog position, scaled as (x - sky) / sqrt(sky).
+__global__ __launch_bounds__(256) void k_patches(const SrcDev* __restrict__ srcs, const ImgDev* __restrict__ imgs,
+                                                 const double* __restrict__ theta, bf16* __restrict__ out) {
+  const int s = blockIdx.x;
+  const double ux = theta[(size_t)s * NP], uy = theta[(size_t)s * NP + 1];
+  for (int b = 0; b < 5; ++b) {
+    int sel = -1;
+    for (int i = srcs[s].img_begin; i < srcs[s].img_end; ++i)
+      if (imgs[i].band == b) {
+        sel = i;
+        break;
+      }
+    bf16* o = out + ((size_t)s * 5 + b) * 1024;
+    if (sel < 0) {
+      for (int k = threadIdx.x; k < 1024; k += 256) o[k] = to_bf16(0.f);
+      continue;
+    }
+    const ImgDev& im = imgs[sel];
+    const double px = im.wcs[0] * ux + im.wcs[1] * uy + im.wcs[4] - im.origin[0];
+    const double py = im.wcs[2] * ux + im.wcs[3] * uy + im.wcs[5] - im.origin[1];
+    const int c0 = (int)floor(px + 0.5) - 16, r0 = (int)floor(py + 0.5) - 16;
+    const float inv = (float)(1.0 / sqrt(im.sky));
+    for (int k = threadIdx.x; k < 1024; k += 256) {
+      const int r = r0 + k / 32, c = c0 + k % 32;
+      float v = 0.f;
+      if (r >= 0 && r < im.h && c >= 0 && c < im.w)
+        v = ((float)im.pix[(size_t)r * im.pitch + c] - (float)im.sky) * inv;
+      o[k] = to_bf16(v);
+    }
+  }
+}
+
+// Launches the product with at most `splits` K-splits; *splits is set to the number used
+// (the count the epilogue must sum).
+template <class LD>
+hipError_t gemm(LD ld, int M, int N, int K, float* C, int& splits, hipStream_t st) {
+  const int kchunk = ((K + splits - 1) / splits + TK - 1) / TK * TK;
+  const int S = (K + kchunk - 1) / kchunk;
+  splits = S;
+  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, S);
+  hipLaunchKernelGGL(k_gemm<LD>, grid, dim3(256), 0, st, ld, M, N, K, kchunk, C);
+  return hipGetLastError();
+}
+
+inline int nblk(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 16384); }
+
+}  // namespace
+
+// ============================================================ network object (host side)
+
+struct NetLayout {
+  static constexpr int NCONV = 4;
+  int cin[4] = {5, 32, 64, 64}, cout[4] = {32, 64, 64, 128}, hw[4] = {32, 32, 16, 8};
+  int pool[4] = {0, 1, 1, 1};
+  size_t off[12];
+  size_t total = 0;
+  NetLayout() {
+    size_t o = 0;
+    for (int l = 0; l < 4; ++l) {
+      off[2 * l] = o;
+      o += (size_t)cout[l] * cin[l] * 9;
+      off[2 * l + 1] = o;
+      o += cout[l];
+    }
+    off[8] = o;
+    o += 256 * 2048;
+    off[9] = o;
+    o += 256;
+    off[10] = o;
+    o += 27 * 256;
+    off[11] = o;
+    o += 27;
+    total = o;
+  }
+};
+
+struct NetState {
+  NetLayout L;
+  float* w = nullptr;     // FP32 master weights
+  float* m = nullptr;     // Adam moments
+  float* v = nullptr;
+  float* g = nullptr;     // gradient
+  bf16* wb = nullptr;     // BF16 weights
+  int step = 0;
+  int cap_batch = 0;
+  // activations (BF16) and gradients for cap_batch images
+  bf16 *x = nullptr, *r[4] = {}, *p[4] = {}, *h = nullptr, *dyb = nullptr, *dzb = nullptr, *dhb = nullptr;
+  float *y = nullptr, *t = nullptr, *dy = nullptr, *dz = nullptr, *dh = nullptr, *C = nullptr, *loss = nullptr;
+  size_t c_cap = 0;
+};
+
+hipError_t net_alloc(NetState* n) {
+  const size_t P = n->L.total;
+  hipError_t e;
+  if ((e = hipMalloc(&n->w, P * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->m, P * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->v, P * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->g, P * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->wb, P * 2)) != hipSuccess) return e;
+  if ((e = hipMemset(n->m, 0, P * 4)) != hipSuccess) return e;
+  if ((e = hipMemset(n->v, 0, P * 4)) != hipSuccess) return e;
+  return hipMalloc(&n->loss, 16);
+}
+
+void net_free_work(NetState* n) {
+  bf16* bb[] = {n->x, n->r[0], n->r[1], n->r[2], n->r[3], n->p[0], n->p[1], n->p[2], n->p[3], n->h, n->dyb,
+                n->dzb, n->dhb};
+  for (bf16* q : bb)
+    if (q) (void)hipFree(q);
+  float* ff[] = {n->y, n->t, n->dy, n->dz, n->dh, n->C};
+  for (float* q : ff)
+    if (q) (void)hipFree(q);
+  n->x = n->h = n->dyb = n->dzb = n->dhb = nullptr;
+  for (int l = 0; l < 4; ++l) n->r[l] = n->p[l] = nullptr;
+  n->y = n->t = n->dy = n->dz = n->dh = n->C = nullptr;
+  n->cap_batch = 0;
+}
+
+void net_free(NetState* n) {
+  net_free_work(n);
+  float* ff[] = {n->w, n->m, n->v, n->g, n->loss};
+  for (float* q : ff)
+    if (q) (void)hipFree(q);
+  if (n->wb) (void)hipFree(n->wb);
+}
+
+static const int kSplitTarget = 1024;   // aim for about this many GEMM blocks
+
+hipError_t net_reserve(NetState* n, int B) {
+  if (B <= n->cap_batch) return hipSuccess;
+  net_free_work(n);
+  const NetLayout& L = n->L;
+  hipError_t e;
+#define ALLOC(ptr, bytes) \
+  if ((e = hipMalloc(&(ptr), (bytes))) != hipSuccess) return e
+  ALLOC(n->x, (size_t)B * 5 * 1024 * 2);
+  size_t maxact = 0;
+  for (int l = 0; l < 4; ++l) {
+    const size_t a = (size_t)B * L.cout[l] * L.hw[l] * L.hw[l];
+    ALLOC(n->r[l], a * 2);
+    const int ho = L.pool[l] ? L.hw[l] / 2 : L.hw[l];
+    ALLOC(n->p[l], (size_t)B * L.cout[l] * ho * ho * 2);
+    maxact = std::max(maxact, a);
+  }
+  ALLOC(n->h, (size_t)B * 256 * 2);
+  ALLOC(n->dyb, (size_t)B * 27 * 2);
+  ALLOC(n->dzb, maxact * 2);
+  ALLOC(n->dhb, (size_t)B * 256 * 2);
+  ALLOC(n->y, (size_t)B * 27 * 4);
+  ALLOC(n->t, (size_t)B * 27 * 4);
+  ALLOC(n->dy, (size_t)B * 27 * 4);
+  ALLOC(n->dz, maxact * 4);
+  ALLOC(n->dh, (size_t)B * 2048 * 4);
+  // split-K partial products: the largest M*N times the split count
+  n->c_cap = std::max(maxact * 2, (size_t)8 << 20);
+  ALLOC(n->C, n->c_cap * 4);
+#undef ALLOC
+  n->cap_batch = B;
+  return hipSuccess;
+}
+
+static int splits_for(size_t M, size_t N, size_t K, size_t cap) {
+  const size_t blocks = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  int s = 1;
+  while (blocks * s < (size_t)kSplitTarget && K / (size_t)(s * 2) >= 256 && (size_t)(s * 2) * M * N <= cap) s *= 2;
+  return s;
+}
+
+// Forward pass of B images at x_in (BF16, B x 5 x 32 x 32); leaves y (FP32, B x 27).
+hipError_t net_forward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
+  const NetLayout& L = n->L;
+  hipError_t e;
+  const bf16* in = x_in;
+  for (int l = 0; l < 4; ++l) {
+    const int HW = L.hw[l] * L.hw[l];
+    const size_t M = L.cout[l], N = (size_t)B * HW, K = (size_t)L.cin[l] * 9;
+    int S = splits_for(M, N, K, n->c_cap);
+    LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], L.hw[l], L.hw[l]};
+    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ep_conv_fwd, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, L.cout[l], B, HW,
+                       n->w + L.off[2 * l + 1], n->r[l]);
+    if (L.pool[l]) {
+      hipLaunchKernelGGL(k_pool_fwd, dim3(nblk((size_t)B * L.cout[l] * HW / 4)), dim3(256), 0, st, n->r[l],
+                         B * L.cout[l], L.hw[l], L.hw[l], n->p[l]);
+      in = n->p[l];
+    } else {
+      in = n->r[l];
+    }
+  }
+  {
+    int S = splits_for(256, B, 2048, n->c_cap);
+    LdFcFwd ld{n->wb + L.off[8], in, 2048};
+    if ((e = gemm(ld, 256, B, 2048, n->C, S, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ep_fc_fwd, dim3(nblk((size_t)256 * B)), dim3(256), 0, st, n->C, S, 256, B,
+                       n->w + L.off[9], n->h, (float*)nullptr);
+  }
+  {
+    int S = splits_for(27, B, 256, n->c_cap);
+    LdFcFwd ld{n->wb + L.off[10], n->h, 256};
+    if ((e = gemm(ld, 27, B, 256, n->C, S, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ep_fc_fwd, dim3(nblk((size_t)27 * B)), dim3(256), 0, st, n->C, S, 27, B,
+                       n->w + L.off[11], (bf16*)nullptr, n->y);
+  }
+  return hipGetLastError();
+}
+
+// Loss and full gradient (into n->g) for the B images at x_in (the forward input) with
+// targets in n->t.
+hipError_t net_backward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
+  const NetLayout& L = n->L;
+  hipError_t e;
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, n->y, n->t, B * 27, n->dy, n->dyb, n->loss);
+  // dense output layer
+  {
+    int S = splits_for(27, 256, B, n->c_cap);
+    LdFcWgrad ld{n->dyb, n->h, 256, 27};
+    if ((e = gemm(ld, 27, 256, B, n->C, S, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ep_sum, dim3(nblk(27 * 256)), dim3(256), 0, st, n->C, S, 27 * 256, n->g + L.off[10]);
+    hipLaunchKernelGGL(k_bias_grad, dim3(27), dim3(256), 0, st, n->dy, B, 27, 1, n->g + L.off[11]);
+    int S2 = splits_for(256, B, 27, n->c_cap);
+    LdFcDgrad ld2{n->wb + L.off[10], n->dyb, 256, 27};
+    if ((e = gemm(ld2, 256, B, 27, n->C, S2, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_relu_bwd_fc, dim3(nblk((size_t)256 * B)), dim3(256), 0, st, n->C, S2, 256, B, n->h, n->dh,
+                       n->dhb);
+  }
+  // dense hidden layer
+  {
+    int S = splits_for(256, 2048, B, n->c_cap);
+    LdFcWgrad ld{n->dhb, n->p[3], 2048, 256};
+    if ((e = gemm(ld, 256, 2048, B, n->C, S, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ep_sum, dim3(nblk(256 * 2048)), dim3(256), 0, st, n->C, S, 256 * 2048, n->g + L.off[8]);
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, st, n->dh, B, 256, 1, n->g + L.off[9]);
+    int S2 = splits_for(2048, B, 256, n->c_cap);
+    LdFcDgrad ld2{n->wb + L.off[8], n->dhb, 2048, 256};
+    if ((e = gemm(ld2, 2048, B, 256, n->C, S2, st)) != hipSuccess) return e;
+    // into conv4's post-ReLU activation through its pool (dense layout C[c*16+q][img])
+    hipLaunchKernelGGL(k_pool_relu_bwd, dim3(nblk((size_t)B * 128 * 64)), dim3(256), 0, st, n->C, S2, 1, B, 128, 8, 8,
+                       1, n->r[3], n->dz, n->dzb);
+  }
+  for (int l = 3; l >= 0; --l) {
+    const int HW = L.hw[l] * L.hw[l];
+    const bf16* xin = l == 0 ? x_in : (L.pool[l - 1] ? n->p[l - 1] : n->r[l - 1]);
+    // weight and bias gradients
+    {
+      const size_t M = L.cout[l], N = (size_t)L.cin[l] * 9, K = (size_t)B * HW;
+      int S = splits_for(M, N, K, n->c_cap);
+      LdConvWgrad ld{n->dzb, xin, L.cin[l], L.cout[l], L.hw[l], L.hw[l]};
+      if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_ep_sum, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, (int)(M * N), n->g + L.off[2 * l]);
+      hipLaunchKernelGGL(k_bias_grad, dim3(L.cout[l]), dim3(256), 0, st, n->dz, B, L.cout[l], HW,
+                         n->g + L.off[2 * l + 1]);
+    }
+    if (l == 0) break;
+    // data gradient into the previous layer's post-ReLU activation (through its pool)
+    {
+      const size_t M = L.cin[l], N = (size_t)B * HW, K = (size_t)L.cout[l] * 9;
+      int S = splits_for(M, N, K, n->c_cap);
+      LdConvDgrad ld{n->wb + L.off[2 * l], n->dzb, L.cin[l], L.cout[l], L.hw[l], L.hw[l]};
+      if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
+      const int Hp = L.hw[l - 1];
+      hipLaunchKernelGGL(k_pool_relu_bwd, dim3(nblk((size_t)B * L.cout[l - 1] * Hp * Hp)), dim3(256), 0, st, n->C, S,
+                         0, B, L.cout[l - 1], Hp, Hp, L.pool[l - 1], n->r[l - 1], n->dz, n->dzb);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t net_adam(NetState* n, float lr, hipStream_t st) {
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)n->step), c2 = 1.f - powf(b2, (float)n->step);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n->L.total)), dim3(256), 0, st, n->w, n->m, n->v, n->g, n->wb,
+                     (int)n->L.total, lr, b1, b2, c1, c2, 1e-8f);
+  return hipGetLastError();
+}
+
+hipError_t net_sync_bf16(NetState* n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n->L.total)), dim3(256), 0, st, n->w, n->wb, (int)n->L.total);
+  return hipGetLastError();
+}
+
+hipError_t net_gather(NetState* n, const void* x, const float* t, const int* order, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, st, (const bf16*)x, t, order, B, 5 * 1024, t ? 27 : 0, n->x,
+                     n->t);
+  return hipGetLastError();
+}
+
+hipError_t net_acc_loss(NetState* n, float* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_acc_loss, dim3(1), dim3(1), 0, st, n->loss, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_patches(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* theta, void* out,
+                          hipStream_t st) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_patches, dim3(n_src), dim3(256), 0, st, srcs, imgs, theta, (bf16*)out);
+  return hipGetLastError();
+}
+
+hipError_t net_destandardise(const float* y, const float* mean, const float* sd, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_destandardise, dim3(nblk(n)), dim3(256), 0, st, y, mean, sd, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace celeste
+
+// ============================================================ C ABI of the network
+
+using celeste::NetState;
+
+struct celeste_net {
+  NetState s;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float* psi_mean = nullptr;   // device, 27
+  float* psi_std = nullptr;    // device, 27
+  float* acc = nullptr;        // device per-epoch loss accumulators
+  int acc_cap = 0;
+  void* patches = nullptr;     // device BF16 inputs for inference inside fits
+  size_t patches_cap = 0;
+};
+
+namespace {
+thread_local std::string g_net_err;
+int net_fail(int code, const char* msg, hipError_t e = hipSuccess) {
+  g_net_err = msg;
+  if (e != hipSuccess) {
+    g_net_err += ": ";
+    g_net_err += hipGetErrorString(e);
+  }
+  celeste::set_error(g_net_err.c_str());
+  return code;
+}
+#define NETCHK(x, msg)                                     \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) return net_fail(CELESTE_E_DEVICE, msg, e_); \
+  } while (0)
+}  // namespace
+
+namespace celeste {
+
+// Predicted start for each source of a packed batch: patches around the catalog
+// positions (theta's u), network forward in chunks, and psi = mean + std * y.
+int surrogate_predict(celeste_net* net, const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* theta_cat,
+                      float* psi_out, hipStream_t st) {
+  const size_t need = (size_t)n_src * 5 * 1024 * 2;
+  if (need > net->patches_cap) {
+    if (net->patches) (void)hipFree(net->patches);
+    net->patches = nullptr;
+    net->patches_cap = 0;
+    NETCHK(hipMalloc(&net->patches, need), "surrogate patch buffer");
+    net->patches_cap = need;
+  }
+  NETCHK(launch_patches(srcs, n_src, imgs, theta_cat, net->patches, st), "patch extraction");
+  const int chunk = 4096;
+  NETCHK(net_reserve(&net->s, std::min(chunk, n_src)), "network workspace");
+  for (int a = 0; a < n_src; a += chunk) {
+    const int B = std::min(chunk, n_src - a);
+    NETCHK(net_forward(&net->s, (const bf16*)net->patches + (size_t)a * 5 * 1024, B, st), "network forward");
+    NETCHK(net_destandardise(net->s.y, net->psi_mean, net->psi_std, B * 27, psi_out + (size_t)a * 27, st),
+           "destandardise");
+  }
+  return CELESTE_OK;
+}
+
+}  // namespace celeste
+
+extern "C" {
+
+int64_t celeste_net_num_params(void) { return (int64_t)celeste::NetLayout().total; }
+
+int celeste_net_create(celeste_ctx* ctx, const float* params, int64_t n_params, const float* psi_mean,
+                       const float* psi_std, celeste_net** out) {
+  if (!ctx || !params || !psi_mean || !psi_std || !out) return net_fail(CELESTE_E_INVALID, "NULL argument");
+  *out = nullptr;
+  celeste_net* net = new (std::nothrow) celeste_net();
+  if (!net) return net_fail(CELESTE_E_NOMEM, "network allocation");
+  if (n_params != (int64_t)net->s.L.total) {
+    delete net;
+    return net_fail(CELESTE_E_INVALID, "parameter count does not match the network");
+  }
+  for (int j = 0; j < 27; ++j)
+    if (!(psi_std[j] > 0.f) || !std::isfinite(psi_mean[j])) {
+      delete net;
+      return net_fail(CELESTE_E_INVALID, "psi_std must be positive and psi_mean finite");
+    }
+  net->device = celeste::ctx_device(ctx);
+  net->stream = celeste::ctx_stream(ctx);
+  hipError_t e = hipSetDevice(net->device);
+  if (e == hipSuccess) e = celeste::net_alloc(&net->s);
+  if (e == hipSuccess) e = hipMalloc(&net->psi_mean, 27 * 4);
+  if (e == hipSuccess) e = hipMalloc(&net->psi_std, 27 * 4);
+  if (e == hipSuccess) e = hipMemcpy(net->s.w, params, net->s.L.total * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(net->psi_mean, psi_mean, 27 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(net->psi_std, psi_std, 27 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = celeste::net_sync_bf16(&net->s, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) {
+    celeste::net_free(&net->s);
+    delete net;
+    return net_fail(CELESTE_E_DEVICE, "network set-up", e);
+  }
+  *out = net;
+  return CELESTE_OK;
+}
+
+void celeste_net_destroy(celeste_net* net) {
+  if (!net) return;
+  (void)hipSetDevice(net->device);
+  (void)hipStreamSynchronize(net->stream);
+  celeste::net_free(&net->s);
+  if (net->psi_mean) (void)hipFree(net->psi_mean);
+  if (net->psi_std) (void)hipFree(net->psi_std);
+  if (net->acc) (void)hipFree(net->acc);
+  if (net->patches) (void)hipFree(net->patches);
+  delete net;
+}
+
+int celeste_net_get_params(celeste_net* net, float* out) {
+  if (!net || !out) return net_fail(CELESTE_E_INVALID, "NULL argument");
+  NETCHK(hipSetDevice(net->device), "set device");
+  NETCHK(hipStreamSynchronize(net->stream), "sync");
+  NETCHK(hipMemcpy(out, net->s.w, net->s.L.total * 4, hipMemcpyDeviceToHost), "read parameters");
+  return CELESTE_OK;
+}
+
+int celeste_net_loss_grad(celeste_net* net, const void* x, const float* t, int batch, float* loss, float* grad) {
+  if (!net || !x || !t || !loss || batch < 1) return net_fail(CELESTE_E_INVALID, "bad argument");
+  NETCHK(hipSetDevice(net->device), "set device");
+  hipStream_t st = net->stream;
+  NETCHK(celeste::net_reserve(&net->s, batch), "network workspace");
+  NETCHK(hipMemcpyAsync(net->s.t, t, (size_t)batch * 27 * 4, hipMemcpyDeviceToDevice, st), "targets");
+  NETCHK(celeste::net_forward(&net->s, (const celeste::bf16*)x, batch, st), "forward");
+  NETCHK(celeste::net_backward(&net->s, (const celeste::bf16*)x, batch, st), "backward");
+  NETCHK(hipMemcpyAsync(loss, net->s.loss, 4, hipMemcpyDeviceToHost, st), "loss");
+  if (grad) NETCHK(hipMemcpyAsync(grad, net->s.g, net->s.L.total * 4, hipMemcpyDeviceToHost, st), "gradient");
+  NETCHK(hipStreamSynchronize(st), "sync");
+  return CELESTE_OK;
+}
+
+int celeste_net_forward(celeste_net* net, const void* x, int64_t n, float* y) {
+  if (!net || !x || !y || n < 1) return net_fail(CELESTE_E_INVALID, "bad argument");
+  NETCHK(hipSetDevice(net->device), "set device");
+  hipStream_t st = net->stream;
+  const int chunk = 4096;
+  NETCHK(celeste::net_reserve(&net->s, (int)std::min<int64_t>(chunk, n)), "network workspace");
+  for (int64_t a = 0; a < n; a += chunk) {
+    const int B = (int)std::min<int64_t>(chunk, n - a);
+    NETCHK(celeste::net_forward(&net->s, (const celeste::bf16*)x + a * 5 * 1024, B, st), "forward");
+    NETCHK(hipMemcpyAsync(y + a * 27, net->s.y, (size_t)B * 27 * 4, hipMemcpyDeviceToDevice, st), "output");
+  }
+  NETCHK(hipStreamSynchronize(st), "sync");
+  return CELESTE_OK;
+}
+
+int celeste_net_train(celeste_net* net, const void* x, const float* t, int64_t n, const int32_t* orders, int epochs,
+                      int batch, float lr, float* epoch_loss) {
+  if (!net || !x || !t || !orders || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f))
+    return net_fail(CELESTE_E_INVALID, "bad argument");
+  NETCHK(hipSetDevice(net->device), "set device");
+  hipStream_t st = net->stream;
+  NETCHK(celeste::net_reserve(&net->s, batch), "network workspace");
+  if (epochs > net->acc_cap) {
+    if (net->acc) (void)hipFree(net->acc);
+    net->acc = nullptr;
+    NETCHK(hipMalloc(&net->acc, (size_t)epochs * 4), "loss accumulators");
+    net->acc_cap = epochs;
+  }
+  NETCHK(hipMemsetAsync(net->acc, 0, (size_t)epochs * 4, st), "zero accumulators");
+  const int64_t nb = (n + batch - 1) / batch;
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t b = 0; b < nb; ++b) {
+      const int B = (int)std::min<int64_t>(batch, n - b * batch);
+      NETCHK(celeste::net_gather(&net->s, x, t, (const int*)orders + (size_t)e * n + b * batch, B, st), "gather");
+      NETCHK(celeste::net_forward(&net->s, net->s.x, B, st), "forward");
+      NETCHK(celeste::net_backward(&net->s, net->s.x, B, st), "backward");
+      NETCHK(celeste::net_adam(&net->s, lr, st), "adam");
+      NETCHK(celeste::net_acc_loss(&net->s, net->acc + e, st), "loss");
+    }
+  }
+  if (epoch_loss) {
+    NETCHK(hipMemcpyAsync(epoch_loss, net->acc, (size_t)epochs * 4, hipMemcpyDeviceToHost, st), "losses");
+    NETCHK(hipStreamSynchronize(st), "sync");
+    for (int e = 0; e < epochs; ++e) epoch_loss[e] /= (float)nb;
+  }
+  NETCHK(hipStreamSynchronize(st), "sync");
+  return CELESTE_OK;
+}
+
+}  // extern "C"

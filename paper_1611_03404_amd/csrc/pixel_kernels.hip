@@ -118,8 +118,10 @@ __device__ __forceinline__ int wave_reduce80(const double* acc, double* out5) {
   return ((lane >> 5) & 1) * 40 + ((lane >> 4) & 1) * 20 + ((lane >> 3) & 1) * 10 + ((lane >> 2) & 1) * 5;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_eval_full(const WorkItem* __restrict__ items,
+// NE, ND > 0: compile-time component counts (fully unrolled loops); 0: runtime counts.
+// MINW: minimum resident waves per SIMD the register allocation must allow.
+template <int BLOCK, int MINW, int NE, int ND>
+__global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __restrict__ items,
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
@@ -133,7 +135,8 @@ __global__ __launch_bounds__(BLOCK) void k_eval_full(const WorkItem* __restrict_
   const float* __restrict__ pix = im.pix;
   const float* __restrict__ nbrE = im.nbr_mean;
   const float* __restrict__ nbrV = im.nbr_var;
-  const int ncomp = n_exp + n_dev;
+  const int ne = NE > 0 ? NE : n_exp;
+  const int ncomp = NE > 0 ? NE + ND : n_exp + n_dev;
   const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
   const float io2 = io * io, io3 = io2 * io;
 
@@ -173,8 +176,15 @@ __global__ __launch_bounds__(BLOCK) void k_eval_full(const WorkItem* __restrict_
       const float dx = dx0 - sr[S_XIX], dy = dy0 - sr[S_XIY];
       const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
-      for (int j = 0; j < n_exp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
-      for (int j = n_exp; j < ncomp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+      if constexpr (NE > 0) {
+#pragma unroll
+        for (int j = 0; j < NE; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+#pragma unroll
+        for (int j = NE; j < NE + ND; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+      } else {
+        for (int j = 0; j < ne; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+        for (int j = ne; j < ncomp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+      }
     }
 
     // ---- galaxy profile and its derivatives in y = (p_x, p_y, e_dev, e_axis, e_angle, e_scale)
@@ -408,14 +418,29 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
 }  // namespace
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
-                            int n_exp, int n_dev, const int* src_flag, double* partials, int block, hipStream_t st) {
+                            int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
+                            hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (block == 128)
-    hipLaunchKernelGGL(k_eval_full<128>, dim3(n_items), dim3(128), 0, st, items, imgs, tables, tstride, n_exp, n_dev,
-                       src_flag, partials);
-  else
-    hipLaunchKernelGGL(k_eval_full<256>, dim3(n_items), dim3(256), 0, st, items, imgs, tables, tstride, n_exp, n_dev,
-                       src_flag, partials);
+  const bool occ2 = (variant & 1) != 0;
+  const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
+  const dim3 g(n_items);
+#define CELESTE_LAUNCH_FULL(B, W, E, D) \
+  hipLaunchKernelGGL((k_eval_full<B, W, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
+                     src_flag, partials)
+  if (block == 128) {
+    if (unroll) {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8); else CELESTE_LAUNCH_FULL(128, 1, 6, 8);
+    } else {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0); else CELESTE_LAUNCH_FULL(128, 1, 0, 0);
+    }
+  } else {
+    if (unroll) {
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8); else CELESTE_LAUNCH_FULL(256, 1, 6, 8);
+    } else {
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0); else CELESTE_LAUNCH_FULL(256, 1, 0, 0);
+    }
+  }
+#undef CELESTE_LAUNCH_FULL
   return hipGetLastError();
 }
 

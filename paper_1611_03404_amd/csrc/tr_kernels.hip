@@ -84,6 +84,32 @@ __global__ void k_fit_init(FitDev st, int n_src, FitParams fp) {
   st.pred[s] = 0.0;
 }
 
+// Surrogate start: theta = T(psi) with the position box centred on the catalog position.
+__global__ void k_psi_to_theta(const float* __restrict__ psi, const double* __restrict__ theta_cat,
+                               double* __restrict__ theta_out, int n_src, double u_box) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  const double u0[2] = {theta_cat[(size_t)s * NP], theta_cat[(size_t)s * NP + 1]};
+  for (int i = 0; i < NP; ++i) {
+    double d1, d2;
+    theta_out[(size_t)s * NP + i] = to_theta1((double)psi[(size_t)s * NP + i], box_of(i, u0, u_box), &d1, &d2);
+  }
+}
+
+// Keep the surrogate start (theta_trial, ELBO f_trial) where its ELBO is finite and higher
+// than the plain start's (theta, f); otherwise flag the fallback.
+__global__ void k_choose_start(FitDev st, int n_src) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  const double fs = st.f_trial[s], fp = st.f[s];
+  if (isfinite(fs) && (!isfinite(fp) || fs > fp)) {
+    for (int i = 0; i < NP; ++i) st.theta[(size_t)s * NP + i] = st.theta_trial[(size_t)s * NP + i];
+    st.flags[s] = 0;
+  } else {
+    st.flags[s] = CELESTE_FLAG_FALLBACK_USED;
+  }
+}
+
 // A source whose starting ELBO is not finite is not fitted.
 __global__ void k_fit_start(FitDev st, int n_src) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,6 +415,18 @@ __global__ void k_zero(int* p, int n) {
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s) {
   hipLaunchKernelGGL(k_fit_init, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_psi_to_theta(const float* psi, const double* theta_cat, double* theta_out, int n_src,
+                               double u_box, hipStream_t s) {
+  hipLaunchKernelGGL(k_psi_to_theta, dim3((n_src + 127) / 128), dim3(128), 0, s, psi, theta_cat, theta_out, n_src,
+                     u_box);
+  return hipGetLastError();
+}
+
+hipError_t launch_choose_start(FitDev st, int n_src, hipStream_t s) {
+  hipLaunchKernelGGL(k_choose_start, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src);
   return hipGetLastError();
 }
 

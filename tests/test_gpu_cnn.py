@@ -1,0 +1,138 @@
+"""Surrogate network on the GPU (BF16 MFMA kernels) against the FP64 CPU reference."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from synth.surrogate import epoch_orders, init_params
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1611_03404_amd import celeste as cb_
+    cb_.load()
+    return cb_
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.Context(0)
+    yield c
+    c.close()
+
+
+def _bf16_round(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_forward_matches_reference(cb, ctx):
+    import torch
+    rng = np.random.default_rng(0)
+    p = init_params(11)
+    net = cb.Net(ctx, p, np.zeros(27), np.ones(27))
+    x = rng.normal(size=(70, 5, 32, 32)).astype(np.float32)
+    xg = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    y = net.forward(xg).cpu().numpy()
+    # reference on the same BF16-rounded inputs and weights
+    pr = p.copy()
+    offs = np.cumsum([0] + [int(np.prod(s)) for s in cnn.param_shapes()])
+    for k in range(0, 12, 2):                         # weights are used in BF16, biases in FP32
+        pr[offs[k]:offs[k + 1]] = _bf16_round(p[offs[k]:offs[k + 1]])
+    yr, _ = cnn.forward(pr, _bf16_round(x).reshape(x.shape))
+    err = np.max(np.abs(y - yr)) / np.max(np.abs(yr))
+    _say("forward rel err", err)
+    assert err < 2e-2
+    net.close()
+
+
+def test_gradient_matches_reference(cb, ctx):
+    import torch
+    rng = np.random.default_rng(1)
+    p = init_params(12)
+    net = cb.Net(ctx, p, np.zeros(27), np.ones(27))
+    B = 12
+    x = rng.normal(size=(B, 5, 32, 32)).astype(np.float32)
+    t = rng.normal(size=(B, 27)).astype(np.float32)
+    loss, g = net.loss_grad(torch.from_numpy(x).to(torch.bfloat16).cuda(), torch.from_numpy(t).cuda())
+    lr_, gr = cnn.loss_and_grad(p, _bf16_round(x).reshape(x.shape), t.astype(np.float64))
+    cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+    _say("loss", loss, lr_, "grad cosine", cos)
+    assert abs(loss - lr_) <= 2e-2 * abs(lr_)
+    assert cos >= 0.999
+    offs = np.cumsum([0] + [int(np.prod(s)) for s in cnn.param_shapes()])
+    for k in range(12):
+        a, b_ = g[offs[k]:offs[k + 1]], gr[offs[k]:offs[k + 1]]
+        c = float(a @ b_ / (np.linalg.norm(a) * np.linalg.norm(b_) + 1e-30))
+        _say("layer", k, "cosine", c)
+        assert c >= 0.99
+
+
+def test_training_reduces_loss(cb, ctx):
+    import torch
+    rng = np.random.default_rng(2)
+    n = 1024
+    x = rng.normal(size=(n, 5, 32, 32)).astype(np.float32)
+    w = rng.normal(size=(5 * 32 * 32, 27)).astype(np.float32) / 64.0
+    t = (x.reshape(n, -1) @ w).astype(np.float32)
+    t = (t - t.mean(0)) / t.std(0)
+    net = cb.Net(ctx, init_params(13), np.zeros(27), np.ones(27))
+    orders = torch.from_numpy(epoch_orders(n, 6, 14)).cuda()
+    losses = net.train(torch.from_numpy(x).to(torch.bfloat16).cuda(), torch.from_numpy(t).cuda(), orders,
+                       batch=64, lr=1e-3)
+    _say("losses", losses)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.7 * losses[0]
+
+
+def test_patches_match_direct_crop(cb, ctx):
+    sb = synth.make_config(1, n_sources=6)
+    b = cb.Batch.from_synth(sb)
+    th = np.zeros((6, 27))
+    th[:, 0:2] = sb.u_cat
+    x = ctx.make_patches(b, th).float().cpu().numpy()
+    for s in range(6):
+        for band in range(5):
+            i = int(sb.src_img_off[s]) + band
+            img = sb.image_pixels(i)
+            h, w = img.shape
+            c0 = int(np.floor(sb.u_cat[s, 0] - sb.img_origin[i, 0] + 0.5)) - 16
+            r0 = int(np.floor(sb.u_cat[s, 1] - sb.img_origin[i, 1] + 0.5)) - 16
+            ref = np.zeros((32, 32))
+            for r in range(32):
+                for c in range(32):
+                    if 0 <= r0 + r < h and 0 <= c0 + c < w:
+                        ref[r, c] = (img[r0 + r, c0 + c] - sb.img_sky[i]) / np.sqrt(sb.img_sky[i])
+            np.testing.assert_allclose(x[s, band], _bf16_round(ref).reshape(32, 32), rtol=0, atol=1e-6)
+
+
+def test_surrogate_start_with_fallback(cb, ctx):
+    """An untrained network: wherever its start is worse the plain start is used, and those
+    fits are identical to plain-start fits."""
+    sb = synth.make_config(1, n_sources=8)
+    b = cb.Batch.from_synth(sb)
+    th0 = np.zeros((8, 27))
+    th0[:, 0:2] = sb.u_cat
+    net = cb.Net(ctx, init_params(15), np.zeros(27), np.ones(27))
+    ctx.set_surrogate(net)
+    try:
+        th_s, r_s = ctx.batch_fit(b, th0, cb.default_opts(init_mode=cb.INIT_SURROGATE))
+    finally:
+        ctx.set_surrogate(None)
+    th_p, r_p = ctx.batch_fit(b, th0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+    fb = (r_s["flags"] & cb.FLAG_FALLBACK_USED) != 0
+    _say("fallback", fb, "iters surrogate", r_s["iters"], "plain", r_p["iters"])
+    assert fb.any()
+    assert np.array_equal(th_s[fb], th_p[fb])
+    net.close()
