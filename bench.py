@@ -1,8 +1,10 @@
 #!/usr/bin/env python3
 """Benchmark of the Celeste hot path on one MI355X.
 
-One step = a whole batched trust-region Newton fit (celeste_batch_fit, plain
-start computed on the device) of the batched-uneven workload: 20,000 sources,
+One step = a whole batched trust-region Newton fit (celeste_batch_fit) of the
+batched-uneven workload, started by the surrogate network with the plain start
+as fallback (the network is trained first, outside the timed region, on plain
+fits of 200,000 single-epoch sources): 20,000 sources,
 patch side log-uniform in 15..121 px, 5 bands x 1..10 epochs per source, each
 epoch with its own PSF (widths 1..3 px) and sky (50..300 counts/px); 1.90e9
 pixels resident in HBM before the timed region.  Every step evaluates ELBO,
@@ -15,7 +17,7 @@ the roofline of the dominant kernel (value+gradient+Hessian pixel kernel,
 timed with HIP events on the library's stream) and the FP64 CPU oracle timed
 on a bounded sample on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sources N] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sources N] [--no-surrogate] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -110,6 +112,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sources", type=int, default=None, help="first N sources only (default: all 20,000)")
+    ap.add_argument("--train-sources", type=int, default=200000, help="surrogate training sources")
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
+    ap.add_argument("--no-surrogate", action="store_true", help="plain start only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -121,10 +126,29 @@ def main():
     import torch
 
     import synth
+    from synth.surrogate import epoch_orders, init_params
     from paper_1611_03404_amd import celeste as cb
+    from paper_1611_03404_amd import surrogate
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
+
+    ctx = cb.Context(0)
+    ctx.set_option(cb.OPT_PROFILE, 1)
+    sur_info = None
+    net = None
+    if not args.no_surrogate:
+        # offline: label the training sources by plain fits and train the network (not timed)
+        t = time.perf_counter()
+        tr = synth.make_config(3, n_sources=args.train_sources, device="cuda")
+        trb = cb.Batch.from_synth(tr)
+        net, sur_info = surrogate.train(ctx, trb, tr.u_cat, init_params(161103404),
+                                        lambda n, e: epoch_orders(n, e, 161103405), epochs=args.epochs,
+                                        minibatch=256, lr=1e-3, log=log)
+        del trb, tr
+        torch.cuda.empty_cache()
+        sur_info["total_s"] = time.perf_counter() - t
+        ctx.set_surrogate(net)
 
     t_gen = time.perf_counter()
     sb = synth.make_config(2, n_sources=args.sources, device="cuda")
@@ -132,43 +156,65 @@ def main():
     log(f"workload: {sb.n_sources} sources, {sb.n_images} images, {sb.n_pixels} px "
         f"({time.perf_counter() - t_gen:.1f} s to generate)")
     batch = cb.Batch.from_synth(sb)
-    ctx = cb.Context(0)
-    ctx.set_option(cb.OPT_PROFILE, 1)
     theta0 = np.zeros((sb.n_sources, 27))
     theta0[:, 0:2] = sb.u_cat
-    opts = cb.default_opts(init_mode=cb.INIT_PLAIN)
+    modes = [("plain", cb.INIT_PLAIN)] + ([] if net is None else [("surrogate", cb.INIT_SURROGATE)])
+    runs = {}
+    for name, mode in modes:
+        opts = cb.default_opts(init_mode=mode)
+        for w in range(args.warmup):
+            t = time.perf_counter()
+            ctx.batch_fit(batch, theta0, opts)
+            log(f"{name} warmup {w}: {time.perf_counter() - t:.2f} s")
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = None
+        conv = 0
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            th, res = ctx.batch_fit(batch, theta0, opts)
+            c = int(np.sum(res["status"] == cb.CONVERGED))
+            conv += c
+            log(f"{name} step {k}: {time.perf_counter() - ts:.2f} s, converged {c}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[name] = dict(wall=wall, res=res, conv=conv, stats=ctx.stats())
+    # ELBO tolerance rule against the best optimum either start reached
+    best = np.max(np.stack([r["res"]["elbo"] for r in runs.values()]), axis=0)
 
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        ctx.batch_fit(batch, theta0, opts)
-        log(f"warmup {w}: {time.perf_counter() - t:.2f} s")
-    ctx.stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    conv = 0
-    res = None
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        th, res = ctx.batch_fit(batch, theta0, opts)
-        conv += int(np.sum(res["status"] == cb.CONVERGED))
-        log(f"step {k}: {time.perf_counter() - ts:.2f} s, converged {int(np.sum(res['status'] == cb.CONVERGED))}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = ctx.stats()
-    wall = t1 - t0
+    def at_tol(res):
+        ok = (res["status"] == cb.CONVERGED) & (res["elbo"] >= best - 1e-5 * np.abs(best))
+        return int(np.sum(ok))
+
+    head = "surrogate" if net is not None else "plain"
+    H = runs[head]
+    st = H["stats"]
+    wall = H["wall"]
+    conv_tol = at_tol(H["res"]) * args.steps
     K = 3
     E, D = len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0])
     f_full = flop_full_per_px(K, E, D)
     full_s = st["ms_full"] / 1e3
     achieved = f_full * st["full_px"] / full_s / 1e12 if full_s > 0 else 0.0
     hbm_bytes = 4.0 * st["full_px"]
+    res = H["res"]
     iters = res["iters"]
     status_counts = {name: int(np.sum(res["status"] == code)) for name, code in
                      (("converged", cb.CONVERGED), ("max_iter", cb.MAX_ITER), ("tr_collapsed", cb.TR_COLLAPSED),
                       ("nonfinite", cb.NONFINITE))}
+
+    def summary(r):
+        rr = r["res"]
+        return {"converged_per_s": at_tol(rr) * args.steps / r["wall"], "ms_per_step": 1e3 * r["wall"] / args.steps,
+                "converged_status": int(np.sum(rr["status"] == cb.CONVERGED)), "converged_at_tol": at_tol(rr),
+                "iterations_mean": float(np.mean(rr["iters"])), "full_evals_mean": float(np.mean(rr["n_full_evals"])),
+                "fallback_rate": float(np.mean((rr["flags"] & cb.FLAG_FALLBACK_USED) != 0)),
+                "pixel_evals_per_s": r["stats"]["full_px"] / r["wall"]}
+
     out = {
-        "metric": "converged sources/s at ELBO rel err<=1e-5 (plain start); pixel-evals/s",
-        "value": conv / wall,
+        "metric": "converged sources/s at ELBO rel err<=1e-5 (surrogate start with plain fallback); pixel-evals/s",
+        "value": conv_tol / wall,
         "unit": "converged sources/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -177,13 +223,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve",
+        "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve, bf16 network",
         "data": "synthetic",
         "config": {"workload": "batched uneven sources: 20,000 sources, side log-uniform 15-121 px, "
                                "5 bands x 1-10 epochs, per-epoch PSF and sky" if args.sources is None else
                    f"first {sb.n_sources} sources of the batched-uneven workload",
                    "n_sources": sb.n_sources, "n_images": sb.n_images, "n_pixels": sb.n_pixels,
-                   "init": "plain (device)", "max_iter": 50},
+                   "start": head, "max_iter": 50},
+        "tolerance_rule": "status converged and ELBO >= best of the plain-start and surrogate-start optima - 1e-5 |L|",
         "pixel_evals_per_s": st["full_px"] / wall,
         "value_pixel_evals_per_s": st["value_px"] / wall,
         "kernel_pixel_evals_per_s": st["full_px"] / full_s if full_s > 0 else None,
@@ -191,6 +238,9 @@ def main():
         "iterations_hist": np.bincount(iters, minlength=52).tolist(),
         "status": status_counts,
         "phase_ms_per_step": {k[3:]: v / args.steps for k, v in st.items() if k.startswith("ms_")},
+        "starts": {name: summary(r) for name, r in runs.items()},
+        "surrogate_training": None if sur_info is None else
+        {k: v for k, v in sur_info.items() if k not in ("psi_mean", "psi_std")},
         "roofline": {
             "kernel": "k_eval_full (value+gradient+Hessian pixel kernel)",
             "bound": "alu",
@@ -206,11 +256,16 @@ def main():
             "traffic": None,
         },
     }
+    if "plain" in runs and net is not None:
+        out["surrogate_gain"] = out["starts"]["surrogate"]["converged_per_s"] / out["starts"]["plain"]["converged_per_s"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(sb, theta0, st["full_px"] / args.steps, st["value_px"] / args.steps,
-                                           conv / args.steps)
+                                           conv_tol / args.steps)
     print(json.dumps(out), flush=True)
+    if net is not None:
+        ctx.set_surrogate(None)
+        net.close()
     ctx.close()
 
 
