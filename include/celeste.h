@@ -109,7 +109,7 @@ typedef struct celeste_image {
   int32_t h, w;                 /* patch rows and columns, >= 1 */
   int32_t pitch;                /* elements between rows of pixels/nbr arrays, >= w */
   int32_t n_psf;                /* PSF mixture components, 1..CELESTE_MAX_PSF */
-  int32_t reserved;             /* must be 0 */
+  int32_t nbr_pitch;            /* elements between rows of nbr_mean/nbr_var (>= w), or 0 = pitch */
   double origin[2];             /* image-frame (x, y) of element (0,0)'s centre */
   double wcs[6];                /* p = A u + b: A row-major 2x2 (wcs[0..3]), b (wcs[4..5]) */
   double sky;                   /* sky level epsilon_n, counts per pixel, > 0 */
@@ -267,6 +267,40 @@ int celeste_ctx_set_surrogate(celeste_ctx* ctx, celeste_net* net);
  * the rest identity.  Values outside a box are clipped into it first. */
 int celeste_theta_to_psi(const double* theta, const double* u0, int64_t n, double u_box, double* psi);
 int celeste_psi_to_theta(const double* psi, const double* u0, int64_t n, double u_box, double* theta);
+
+/* ----------------------------------------------------------------------------------------
+ * Crowded fields (section III-B: each source is optimised with the other sources held fixed
+ * at their current estimates; a pixel can receive photons from several sources).  Patches
+ * are views into shared field images: image i of the batch belongs to field img_field[i],
+ * its origin is the integer field-pixel position of its element (0,0) and it lies inside
+ * the field.  Batches must use CELESTE_MEM_DEVICE.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct celeste_fields {
+  int32_t n_fields, height, width;   /* field images, each height x width, row-major */
+  int32_t reserved;                  /* must be 0 */
+  const int32_t* img_field;          /* host: field of every image of the batch */
+  float* mean;                       /* device, n_fields x height x width */
+  float* var;                        /* device, n_fields x height x width */
+} celeste_fields;
+
+/* Sum over all sources of calib * E[l G] (expected counts without sky) and of the variance
+ * into fields->mean / fields->var, each source within its own patches, at theta (device,
+ * n_sources x 27).  Deterministic (a gather per 32x32 tile in source order, FP64 sums). */
+int celeste_render_fields(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                          const celeste_fields* fields);
+
+/* Per-patch neighbour arrays: rendered fields minus the source's own contribution at theta,
+ * clamped at 0, written with pitch = w at nbr_mean/nbr_var + nbr_off[i] (device; nbr_off
+ * host, one element offset per image).  Feed them back as celeste_image.nbr_mean/nbr_var. */
+int celeste_neighbour_arrays(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                             const celeste_fields* fields, const int64_t* nbr_off, float* nbr_mean,
+                             float* nbr_var);
+
+/* The start a fit with these options would use (plain or surrogate-with-fallback, clipped
+ * into the boxes), without fitting; elbo_out (n_sources, batch memory, may be NULL) gets its
+ * ELBO.  opts->max_iter is ignored. */
+int celeste_start(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout, const celeste_fit_opts* opts,
+                  double* elbo_out);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
 
 IMAGE_DT = np.dtype([
-    ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("reserved", "<i4"),
+    ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("nbr_pitch", "<i4"),
     ("origin", "<f8", (2,)), ("wcs", "<f8", (6,)), ("sky", "<f8"), ("calib", "<f8"), ("psf", "<f8", (4, 6)),
     ("pixels", "<u8"), ("nbr_mean", "<u8"), ("nbr_var", "<u8"),
 ])
@@ -57,6 +57,12 @@ class Stats(ctypes.Structure):
                 ("value_launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("ms_setup", ctypes.c_double),
                 ("ms_full", ctypes.c_double), ("ms_reduce_full", ctypes.c_double), ("ms_tr", ctypes.c_double),
                 ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double)]
+
+
+class CFields(ctypes.Structure):
+    _fields_ = [("n_fields", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("img_field", ctypes.c_void_p), ("mean", ctypes.c_void_p),
+                ("var", ctypes.c_void_p)]
 
 
 class CelesteError(RuntimeError):
@@ -101,11 +107,15 @@ def load():
     lib.celeste_make_patches.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp]
     lib.celeste_ctx_set_surrogate.argtypes = [vp, vp]
     lib.celeste_theta_to_psi.argtypes = [vp, vp, i64, ctypes.c_double, vp]
+    lib.celeste_render_fields.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields)]
+    lib.celeste_neighbour_arrays.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields), vp, vp, vp]
+    lib.celeste_start.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_psi_to_theta.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
                  "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
                  "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
-                 "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta"):
+                 "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta",
+                 "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start"):
         getattr(lib, name).restype = ctypes.c_int
     sizes = [lib.celeste_struct_size(k) for k in range(7)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
@@ -143,7 +153,7 @@ class Batch:
     """ABI batch from structure-of-arrays image metadata (keeps its arrays alive)."""
 
     def __init__(self, src_img_off, band, h, w, pitch, origin, wcs, sky, calib, psf, npsf, pixels, pix_off,
-                 prior, profiles, nbr_mean=None, nbr_var=None, nbr_off=None):
+                 prior, profiles, nbr_mean=None, nbr_var=None, nbr_off=None, nbr_pitch=None):
         n_img = int(len(band))
         self.device = _is_torch(pixels) and pixels.is_cuda
         if self.device:
@@ -173,6 +183,12 @@ class Batch:
                 self._keep.append(arr)
                 off = pix_off if nbr_off is None else nbr_off
                 img[name] = _ptr(arr) + 4 * np.asarray(off, dtype=np.uint64)
+        # neighbour rows: nbr_pitch if given, else contiguous per image when separate offsets
+        # are given, else the pixel pitch
+        if nbr_pitch is not None:
+            img["nbr_pitch"] = nbr_pitch
+        elif nbr_off is not None:
+            img["nbr_pitch"] = w
         pr = np.zeros(1, dtype=PRIOR_DT)
         pr["p_star"] = prior["p_star"]
         pr["r_mean"] = prior["r_mean"]
@@ -297,6 +313,42 @@ class Context:
         self._stream(batch)
         _check(load().celeste_make_patches(self._h, ctypes.byref(batch.c), _ptr(th), out.data_ptr()))
         return out
+
+    def start(self, batch: Batch, theta0, opts=None):
+        """The start a fit with these options would use, and its ELBO (no fitting)."""
+        th = batch.as_input(theta0, copy=True)
+        el = batch.array((batch.n_sources,))
+        o = opts if opts is not None else default_opts()
+        self._stream(batch)
+        _check(load().celeste_start(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o), _ptr(el)))
+        return th, el
+
+    def render_fields(self, batch: Batch, theta, img_field, n_fields, height, width, out=None):
+        """Expected counts and variance of all sources summed into the field images (device)."""
+        import torch
+        th = batch.as_input(theta)
+        if out is None:
+            out = (torch.empty(n_fields * height * width, dtype=torch.float32, device=batch.torch_device),
+                   torch.empty(n_fields * height * width, dtype=torch.float32, device=batch.torch_device))
+        f, keep = self._fields(img_field, n_fields, height, width, out)
+        self._stream(batch)
+        _check(load().celeste_render_fields(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(f)))
+        return out
+
+    def neighbour_arrays(self, batch: Batch, theta, img_field, n_fields, height, width, fields, nbr_off, nbr_mean,
+                         nbr_var):
+        th = batch.as_input(theta)
+        f, keep = self._fields(img_field, n_fields, height, width, fields)
+        off = np.ascontiguousarray(nbr_off, dtype=np.int64)
+        self._stream(batch)
+        _check(load().celeste_neighbour_arrays(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(f),
+                                               off.ctypes.data, _ptr(nbr_mean), _ptr(nbr_var)))
+
+    @staticmethod
+    def _fields(img_field, n_fields, height, width, arrays):
+        imf = np.ascontiguousarray(img_field, dtype=np.int32)
+        f = CFields(int(n_fields), int(height), int(width), 0, imf.ctypes.data, _ptr(arrays[0]), _ptr(arrays[1]))
+        return f, imf
 
     def batch_fit(self, batch: Batch, theta0, opts=None):
         S = batch.n_sources

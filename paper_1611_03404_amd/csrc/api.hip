@@ -74,6 +74,7 @@ struct celeste_ctx {
   celeste_stats stats{};
   celeste_net* net = nullptr;   // surrogate network (not owned)
   DevBuf sur;                   // surrogate predictions (float, S x 27)
+  DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
 };
 
 namespace celeste {
@@ -193,7 +194,8 @@ int check_image(const celeste_image& im, int64_t idx) {
   if ((int64_t)im.h * im.w > (int64_t)1 << 30) return fail(CELESTE_E_INVALID, "image %lld: patch too large", (long long)idx);
   if (im.n_psf < 1 || im.n_psf > CELESTE_MAX_PSF)
     return fail(CELESTE_E_INVALID, "image %lld: n_psf %d not in 1..%d", (long long)idx, im.n_psf, CELESTE_MAX_PSF);
-  if (im.reserved != 0) return fail(CELESTE_E_INVALID, "image %lld: reserved field must be 0", (long long)idx);
+  if (im.nbr_pitch != 0 && im.nbr_pitch < im.w)
+    return fail(CELESTE_E_INVALID, "image %lld: nbr_pitch must be 0 or >= w", (long long)idx);
   if (!im.pixels) return fail(CELESTE_E_INVALID, "image %lld: pixels is NULL", (long long)idx);
   if (!(im.sky > 0.0) || !finite(im.sky) || !(im.calib > 0.0) || !finite(im.calib))
     return fail(CELESTE_E_INVALID, "image %lld: sky and calib must be positive and finite", (long long)idx);
@@ -283,6 +285,7 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
       d.h = im.h;
       d.w = im.w;
       d.pitch = im.pitch;
+      d.nbr_pitch = im.nbr_pitch ? im.nbr_pitch : im.pitch;
       d.band = im.band;
       d.n_psf = im.n_psf;
       d.src = s;
@@ -326,7 +329,8 @@ int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipSt
     for (int k = 0; k < 3; ++k) {
       if (!srcs[k]) continue;
       offs[3 * i + k] = off;
-      for (int r = 0; r < im.h; ++r) std::memcpy(&host[off + (size_t)r * im.w], srcs[k] + (size_t)r * im.pitch, sizeof(float) * im.w);
+      const size_t rp = k == 0 ? (size_t)im.pitch : (size_t)(im.nbr_pitch ? im.nbr_pitch : im.pitch);
+      for (int r = 0; r < im.h; ++r) std::memcpy(&host[off + (size_t)r * im.w], srcs[k] + (size_t)r * rp, sizeof(float) * im.w);
       off += (size_t)im.h * im.w;
     }
   }
@@ -337,6 +341,7 @@ int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipSt
   for (int i = 0; i < P->n_img; ++i) {
     ImgDev& d = P->imgs[i];
     d.pitch = d.w;
+    d.nbr_pitch = d.w;
     d.pix = base + offs[3 * i];
     d.nbr_mean = offs[3 * i + 1] != (size_t)-1 ? base + offs[3 * i + 1] : nullptr;
     d.nbr_var = offs[3 * i + 2] != (size_t)-1 ? base + offs[3 * i + 2] : nullptr;
@@ -344,8 +349,9 @@ int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipSt
   return CELESTE_OK;
 }
 
-// Metadata upload + pixel validation + per-image constants.  Synchronous.
-int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st) {
+// Metadata upload + pixel validation + per-image constants (the last two only when the
+// call reads pixels).  Synchronous.
+int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st, bool pixels = true) {
   if (b->mem_kind == CELESTE_MEM_HOST) CHK(stage_host_pixels(ctx, b, P, st));
   CHK(ensure(ctx->imgs, sizeof(ImgDev) * P->n_img));
   CHK(ensure(ctx->items, sizeof(WorkItem) * P->n_items));
@@ -357,6 +363,10 @@ int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st)
   HIPCHK(hipMemcpyAsync(ctx->imgs.p, P->imgs.data(), sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->items.p, P->items.data(), sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->srcs.p, P->srcs.data(), sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
+  if (!pixels) {
+    HIPCHK(hipStreamSynchronize(st));
+    return CELESTE_OK;
+  }
   HIPCHK(launch_zero_int(as<int>(ctx->flag), 4, st));
   HIPCHK(launch_check_pixels(as<ImgDev>(ctx->imgs), P->n_img, as<int>(ctx->flag), st));
   int bad = 0;
@@ -464,7 +474,8 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
-                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur};
+                    &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
+                    &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   (void)hipStreamDestroy(c->stream);
@@ -688,11 +699,19 @@ void accumulate_phases(celeste_ctx* ctx, PhaseTimer& T) {
 }
 
 int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
-            celeste_fit_result* res, hipStream_t st, bool batched) {
+            celeste_fit_result* res, hipStream_t st, bool batched, double* start_elbo = nullptr,
+            bool start_only = false) {
   Packed P;
   CHK(validate_and_pack(ctx, b, &P));
-  CHK(check_opts(o));
-  if (!theta_inout || !res) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+  if (start_only) {
+    if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
+    celeste_fit_opts o2 = *o;
+    o2.max_iter = 1;
+    CHK(check_opts(&o2));
+  } else {
+    CHK(check_opts(o));
+  }
+  if (!theta_inout || (!res && !start_only)) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
   HIPCHK(hipSetDevice(ctx->device));
   const int S = P.n_src;
   std::vector<double> th(NP * (size_t)S);
@@ -757,6 +776,17 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
                              F.theta, P.prior, nullptr, F.f, ctr_value(ctx), st));
   ctx->stats.value_launches += 1;
   HIPCHK(launch_fit_start(F, S, st));
+  if (start_only) {
+    if (b->mem_kind == CELESTE_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    } else {
+      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToDevice, st));
+      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return CELESTE_OK;
+  }
   PhaseTimer T;
   CHK(T.init(ctx->profile != 0));
 
@@ -933,6 +963,123 @@ int celeste_psi_to_theta(const double* psi, const double* u0, int64_t n, double 
       theta[s * NP + i] = v;
     }
   return CELESTE_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================== crowded fields
+
+namespace {
+
+int check_fields(const celeste_batch* b, const Packed& P, const celeste_fields* f) {
+  if (!f || !f->img_field || !f->mean || !f->var) return fail(CELESTE_E_INVALID, "fields and its arrays must not be NULL");
+  if (b->mem_kind != CELESTE_MEM_DEVICE) return fail(CELESTE_E_INVALID, "crowded fields need CELESTE_MEM_DEVICE");
+  if (f->n_fields < 1 || f->height < 1 || f->width < 1 || f->reserved != 0)
+    return fail(CELESTE_E_INVALID, "bad field dimensions");
+  for (int i = 0; i < P.n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const int fi = f->img_field[i];
+    if (fi < 0 || fi >= f->n_fields) return fail(CELESTE_E_INVALID, "image %d: field index out of range", i);
+    const double ox = im.origin[0], oy = im.origin[1];
+    if (ox != std::floor(ox) || oy != std::floor(oy)) return fail(CELESTE_E_INVALID, "image %d: origin not integer", i);
+    if (ox < 0 || oy < 0 || ox + im.w > f->width || oy + im.h > f->height)
+      return fail(CELESTE_E_INVALID, "image %d: patch outside its field", i);
+  }
+  return CELESTE_OK;
+}
+
+int upload_theta(celeste_ctx* ctx, const celeste_batch* b, const Packed& P, const double* theta, const double** out,
+                 hipStream_t st) {
+  if (!theta) return fail(CELESTE_E_INVALID, "theta is NULL");
+  std::vector<double> h(NP * (size_t)P.n_src);
+  HIPCHK(hipMemcpyAsync(h.data(), theta, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int s = 0; s < P.n_src; ++s) CHK(check_theta(h.data() + (size_t)s * NP, s));
+  *out = theta;
+  (void)ctx;
+  (void)b;
+  return CELESTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int celeste_render_fields(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const celeste_fields* f) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_fields(b, P, f));
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const double* th = nullptr;
+  CHK(upload_theta(ctx, b, P, theta, &th, st));
+  CHK(prepare(ctx, b, &P, st, false));
+  // tile -> images index (counting sort, images in source order within a tile)
+  const int tx = (f->width + 31) / 32, ty = (f->height + 31) / 32;
+  const int tpf = tx * ty;
+  const int64_t n_tiles64 = (int64_t)tpf * f->n_fields;
+  if (n_tiles64 > INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many tiles");
+  const int n_tiles = (int)n_tiles64;
+  std::vector<int> cnt(n_tiles + 1, 0);
+  for (int i = 0; i < P.n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const int c0 = (int)im.origin[0], r0 = (int)im.origin[1];
+    const int base = f->img_field[i] * tpf;
+    for (int yy = r0 / 32; yy <= (r0 + im.h - 1) / 32; ++yy)
+      for (int xx = c0 / 32; xx <= (c0 + im.w - 1) / 32; ++xx) cnt[base + yy * tx + xx + 1] += 1;
+  }
+  for (int t = 0; t < n_tiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1), lst((size_t)cnt[n_tiles]);
+  for (int i = 0; i < P.n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const int c0 = (int)im.origin[0], r0 = (int)im.origin[1];
+    const int base = f->img_field[i] * tpf;
+    for (int yy = r0 / 32; yy <= (r0 + im.h - 1) / 32; ++yy)
+      for (int xx = c0 / 32; xx <= (c0 + im.w - 1) / 32; ++xx) lst[pos[base + yy * tx + xx]++] = i;
+  }
+  CHK(ensure(ctx->tile_off, sizeof(int) * cnt.size()));
+  CHK(ensure(ctx->tile_img, sizeof(int) * std::max<size_t>(1, lst.size())));
+  HIPCHK(hipMemcpyAsync(ctx->tile_off.p, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice, st));
+  if (!lst.empty())
+    HIPCHK(hipMemcpyAsync(ctx->tile_img.p, lst.data(), sizeof(int) * lst.size(), hipMemcpyHostToDevice, st));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  HIPCHK(launch_setup(imgs, P.n_img, th, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  HIPCHK(launch_render(as<int>(ctx->tile_off), as<int>(ctx->tile_img), n_tiles, imgs, as<float>(ctx->tables),
+                       P.tstride, P.prof.n_exp, P.prof.n_dev, f->height, f->width, tx, tpf, f->mean, f->var, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+int celeste_neighbour_arrays(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const celeste_fields* f,
+                             const int64_t* nbr_off, float* nbr_mean, float* nbr_var) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_fields(b, P, f));
+  if (!nbr_off || !nbr_mean || !nbr_var) return fail(CELESTE_E_INVALID, "neighbour arrays must not be NULL");
+  for (int i = 0; i < P.n_img; ++i)
+    if (nbr_off[i] < 0) return fail(CELESTE_E_INVALID, "negative neighbour offset");
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const double* th = nullptr;
+  CHK(upload_theta(ctx, b, P, theta, &th, st));
+  CHK(prepare(ctx, b, &P, st, false));
+  CHK(ensure(ctx->img_field, sizeof(int) * P.n_img));
+  CHK(ensure(ctx->nbr_off, sizeof(long long) * P.n_img));
+  HIPCHK(hipMemcpyAsync(ctx->img_field.p, f->img_field, sizeof(int) * P.n_img, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->nbr_off.p, nbr_off, sizeof(long long) * P.n_img, hipMemcpyHostToDevice, st));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  HIPCHK(launch_setup(imgs, P.n_img, th, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  HIPCHK(launch_neighbours(imgs, P.n_img, as<int>(ctx->img_field), as<float>(ctx->tables), P.tstride, P.prof.n_exp,
+                           P.prof.n_dev, f->height, f->width, f->mean, f->var, as<long long>(ctx->nbr_off), nbr_mean,
+                           nbr_var, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+int celeste_start(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* opts,
+                  double* elbo_out) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  return run_fit(ctx, b, theta_inout, opts, nullptr, ctx->stream, true, elbo_out, true);
 }
 
 }  // extern "C"

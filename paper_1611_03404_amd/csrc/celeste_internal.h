@@ -20,6 +20,7 @@ struct ImgDev {
   int32_t h, w, pitch, band;
   int32_t n_psf, src;
   int32_t item_begin, item_end;   // work items covering this image
+  int32_t nbr_pitch, pad_;        // row stride of the neighbour arrays
   double origin[2];
   double wcs[6];
   double sky, calib;
@@ -102,6 +103,13 @@ hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs,
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                                double* elbo, unsigned long long* px_ctr, hipStream_t st);
+
+hipError_t launch_render(const int* tile_off, const int* tile_img, int n_tiles, const ImgDev* imgs,
+                         const float* tables, int tstride, int n_exp, int n_dev, int H, int W, int tiles_x,
+                         int tiles_per_field, float* mean, float* var, hipStream_t st);
+hipError_t launch_neighbours(const ImgDev* imgs, int n_img, const int* img_field, const float* tables, int tstride,
+                             int n_exp, int n_dev, int H, int W, const float* mean, const float* var,
+                             const long long* nbr_off, float* nbr_mean, float* nbr_var, hipStream_t st);
 
 // ---------------------------------------------------------------- trust-region state
 struct FitDev {

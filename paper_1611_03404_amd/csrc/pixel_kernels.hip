@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   if (src_flag && !src_flag[wi.src]) return;
   const ImgDev& im = imgs[wi.img];
   const float* __restrict__ T = tables + (size_t)wi.img * tstride;
-  const int w = im.w, pitch = im.pitch, npsf = im.n_psf;
+  const int w = im.w, pitch = im.pitch, npitch = im.nbr_pitch, npsf = im.n_psf;
   const float* __restrict__ pix = im.pix;
   const float* __restrict__ nbrE = im.nbr_mean;
   const float* __restrict__ nbrV = im.nbr_var;
@@ -147,9 +147,10 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
     const int row = m / w, col = m - row * w;
     const size_t o = (size_t)row * pitch + col;
+    const size_t on = (size_t)row * npitch + col;
     const float x = pix[o];
-    const float ebg = sky + (nbrE ? nbrE[o] : 0.f);
-    const float vbg = nbrV ? nbrV[o] : 0.f;
+    const float ebg = sky + (nbrE ? nbrE[on] : 0.f);
+    const float vbg = nbrV ? nbrV[on] : 0.f;
     const float dx0 = (float)col - psx, dy0 = (float)row - psy;
 
     // ---- star: N, dN/dp, d2N/dp2
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   if (src_flag && !src_flag[wi.src]) return;
   const ImgDev& im = imgs[wi.img];
   const float* __restrict__ T = tables + (size_t)wi.img * tstride;
-  const int w = im.w, pitch = im.pitch, npsf = im.n_psf;
+  const int w = im.w, pitch = im.pitch, npitch = im.nbr_pitch, npsf = im.n_psf;
   const float* __restrict__ pix = im.pix;
   const float* __restrict__ nbrE = im.nbr_mean;
   const float* __restrict__ nbrV = im.nbr_var;
@@ -381,9 +382,10 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
     const int row = m / w, col = m - row * w;
     const size_t o = (size_t)row * pitch + col;
+    const size_t on = (size_t)row * npitch + col;
     const float x = pix[o];
-    const float ebg = sky + (nbrE ? nbrE[o] : 0.f);
-    const float vbg = nbrV ? nbrV[o] : 0.f;
+    const float ebg = sky + (nbrE ? nbrE[on] : 0.f);
+    const float vbg = nbrV ? nbrV[on] : 0.f;
     const float dx0 = (float)col - psx, dy0 = (float)row - psy;
     float Gs = 0.f, gx = 0.f, gd = 0.f;
     for (int k = 0; k < npsf; ++k) {

@@ -228,8 +228,9 @@ __global__ __launch_bounds__(256) void k_const(const ImgDev* __restrict__ imgs, 
   for (int m = threadIdx.x; m < n; m += 256) {
     const int r = m / im.w, c = m - r * im.w;
     const size_t o = (size_t)r * im.pitch + c;
+    const size_t on = (size_t)r * im.nbr_pitch + c;
     const double x = im.pix[o];
-    const double ebg = im.sky + (im.nbr_mean ? (double)im.nbr_mean[o] : 0.0);
+    const double ebg = im.sky + (im.nbr_mean ? (double)im.nbr_mean[on] : 0.0);
     acc += x * log(ebg) - ebg - lgamma(x + 1.0);
   }
   const double tot = block_sum<256>(acc, sh);
@@ -244,14 +245,15 @@ __global__ __launch_bounds__(256) void k_check(const ImgDev* __restrict__ imgs, 
   for (int m = threadIdx.x; m < n; m += 256) {
     const int r = m / im.w, c = m - r * im.w;
     const size_t o = (size_t)r * im.pitch + c;
+    const size_t on = (size_t)r * im.nbr_pitch + c;
     const float x = im.pix[o];
     if (!(x >= 0.0f) || !isfinite(x)) flag = 1;
     if (im.nbr_mean) {
-      const float e = im.nbr_mean[o];
+      const float e = im.nbr_mean[on];
       if (!(e >= 0.0f) || !isfinite(e)) flag = 1;
     }
     if (im.nbr_var) {
-      const float v = im.nbr_var[o];
+      const float v = im.nbr_var[on];
       if (!(v >= 0.0f) || !isfinite(v)) flag = 1;
     }
   }

@@ -9,5 +9,5 @@ photons (Poisson count per band, positions drawn from the PSF and the galaxy
 prototype mixtures, binned into unit pixels) on top of Poisson sky.
 """
 from .generate import (  # noqa: F401
-    PRIOR, load_profiles, SynthBatch, make_config, CONFIG_SEED_BASE, N_PARAMS,
+    PRIOR, load_profiles, SynthBatch, SynthField, make_config, make_field, CONFIG_SEED_BASE, N_PARAMS,
 )

@@ -377,3 +377,122 @@ def perturb_theta(theta, seed, scale=1.0):
     t[:, 11:19] += rng.normal(0, 0.2 * scale, (S, 8))
     t[:, 19:27] = rng.uniform(0.01, 0.2, (S, 8))
     return t
+
+
+# ----------------------------------------------------------------------------
+# crowded field
+# ----------------------------------------------------------------------------
+
+@dataclass
+class SynthField:
+    """A multi-source field: n_fields images of size H x W and a SynthBatch whose patches are
+    views into them (pitch = W); img_field[i] gives the field of patch image i."""
+    batch: SynthBatch
+    fields: object                 # (n_fields * H * W) float32, numpy or torch on a device
+    n_fields: int
+    H: int
+    W: int
+    img_field: np.ndarray          # int32 (I)
+    field_band: np.ndarray         # int32 (n_fields)
+    field_wcs: np.ndarray          # f64 (n_fields, 6)
+    field_sky: np.ndarray
+    field_psf: np.ndarray
+
+
+def make_field(n_sources=100000, size=2048, epochs=4, seed=None, device=None, k=4):
+    """Crowded-field workload: sources at Poisson positions with intensity proportional to
+    1 + x/size across the field, patch sides log-uniform in 15..121 clipped to the field,
+    5 bands x `epochs` field images each with its own PSF (widths 1..3 px), sky (50..300)
+    and sub-pixel offset; catalog position = nearest pixel centre of the truth."""
+    seed = CONFIG_SEED_BASE + k if seed is None else seed
+    ss = np.random.SeedSequence(seed)
+    r_truth, r_psf, r_noise, r_init = [np.random.default_rng(s) for s in ss.spawn(4)]
+    profiles = load_profiles()
+    S, H, W = int(n_sources), int(size), int(size)
+    # x from the density 1 + x/W on [0, W): inverse CDF of (x + x^2/(2W)) / (1.5 W)
+    uu = r_truth.random(S)
+    x = -W + np.sqrt(W * W + 2.0 * W * 1.5 * W * uu)
+    y = r_truth.uniform(0, H, S)
+    u_true = np.stack([x - 0.5, y - 0.5], axis=1)          # pixel centres at integers 0..W-1
+    is_star = r_truth.random(S) < PRIOR["p_star"]
+    log_fr = r_truth.normal(PRIOR["r_mean"][0], math.sqrt(PRIOR["r_var"][0]), size=S)
+    colours = np.empty((S, 4))
+    for t, sel in ((0, is_star), (1, ~is_star)):
+        colours[sel] = r_truth.multivariate_normal(PRIOR["c_mean"][t], PRIOR["c_cov"][t], size=int(sel.sum()))
+    e_dev = r_truth.uniform(0, 1, S)
+    e_axis = r_truth.uniform(0.2, 1.0, S)
+    e_angle = r_truth.uniform(0, math.pi, S)
+    e_scale = np.exp(r_truth.uniform(math.log(0.5), math.log(3.0), S))
+    side = np.rint(np.exp(r_truth.uniform(math.log(15), math.log(121), S))).astype(np.int64)
+    u_cat = np.clip(np.rint(u_true), 0, [W - 1, H - 1]).astype(np.float64)
+    # field images: band-major within epoch
+    NF = N_BANDS * epochs
+    field_band = np.tile(np.arange(N_BANDS), epochs).astype(np.int32)
+    field_psf = _draw_psf(r_psf, NF, 1.0, 3.0)
+    field_sky = r_psf.uniform(50.0, 300.0, NF)
+    field_wcs = np.zeros((NF, 6))
+    field_wcs[:, 0] = field_wcs[:, 3] = 1.0
+    eoff = r_psf.uniform(-0.5, 0.5, size=(epochs, 2))
+    field_wcs[:, 4:6] = np.repeat(eoff, N_BANDS, axis=0)
+    # patches: one per (source, field), centred on the catalog position in that field, clipped
+    I = S * NF
+    img_src = np.repeat(np.arange(S), NF)
+    img_field = np.tile(np.arange(NF), S).astype(np.int32)
+    half = side // 2
+    pc = u_cat[img_src] + field_wcs[img_field, 4:6]
+    cx, cy = np.rint(pc[:, 0]).astype(np.int64), np.rint(pc[:, 1]).astype(np.int64)
+    x0 = np.clip(cx - half[img_src], 0, W - 1)
+    y0 = np.clip(cy - half[img_src], 0, H - 1)
+    x1 = np.clip(cx - half[img_src] + side[img_src], 1, W)
+    y1 = np.clip(cy - half[img_src] + side[img_src], 1, H)
+    img_w = (x1 - x0).astype(np.int32)
+    img_h = (y1 - y0).astype(np.int32)
+    img_origin = np.stack([x0, y0], axis=1).astype(np.float64)
+    img_pix_off = (img_field.astype(np.int64) * H * W + y0 * W + x0).astype(np.int64)
+    # pixels: Poisson sky + photons of every source in every field image
+    lam = np.exp(_band_log_flux(log_fr, colours))[:, field_band]          # (S, NF) nMgy
+    n_phot = r_noise.poisson(lam.ravel())
+    img_of = np.repeat(np.arange(I), n_phot)
+    pos = u_true[img_src] + field_wcs[img_field, 4:6]
+    shape = np.stack([e_dev, e_axis, e_angle, e_scale], axis=1)[img_src]
+    xy = _shoot_photons(r_noise, img_of, pos, field_psf[img_field], is_star[img_src], shape, profiles)
+    fx = np.floor(xy[:, 0] + 0.5).astype(np.int64)
+    fy = np.floor(xy[:, 1] + 0.5).astype(np.int64)
+    ok = (fx >= 0) & (fx < W) & (fy >= 0) & (fy < H)
+    flat = img_field[img_of[ok]].astype(np.int64) * H * W + fy[ok] * W + fx[ok]
+    ph_idx, ph_cnt = np.unique(flat, return_counts=True)
+    del xy, img_of, flat
+    if device is None:
+        fields = r_noise.poisson(np.repeat(field_sky, H * W)).astype(np.float32)
+        np.add.at(fields, ph_idx, ph_cnt.astype(np.float32))
+    else:
+        import torch
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed))
+        fields = torch.empty(NF * H * W, dtype=torch.float32, device=device)
+        for f in range(NF):
+            rate = torch.full((H * W,), float(field_sky[f]), dtype=torch.float32, device=device)
+            fields[f * H * W:(f + 1) * H * W] = torch.poisson(rate, generator=gen)
+        fields.index_add_(0, torch.from_numpy(ph_idx).to(device), torch.from_numpy(ph_cnt.astype(np.float32)).to(device))
+    th = np.zeros((S, N_PARAMS))
+    th[:, 0:2] = u_true
+    th[:, 2] = np.where(is_star, 0.99, 0.01)
+    th[:, 3] = np.clip(e_dev, 0.02, 0.98)
+    th[:, 4] = np.clip(e_axis, 0.02, 0.98)
+    th[:, 5] = e_angle
+    th[:, 6] = e_scale
+    th[:, 7] = th[:, 8] = log_fr
+    th[:, 9] = th[:, 10] = 0.05
+    th[:, 11:15] = th[:, 15:19] = colours
+    th[:, 19:27] = 0.01
+    sb = SynthBatch(
+        n_sources=S, src_img_off=np.arange(0, I + 1, NF, dtype=np.int64), img_band=field_band[img_field].copy(),
+        img_h=img_h, img_w=img_w, img_pitch=np.full(I, W, np.int32), img_origin=img_origin,
+        img_wcs=field_wcs[img_field].copy(), img_sky=field_sky[img_field].copy(), img_calib=np.ones(I),
+        img_psf=field_psf[img_field].copy(), img_npsf=np.full(I, 3, np.int32), img_pix_off=img_pix_off,
+        pixels=fields, u_cat=u_cat,
+        truth=dict(u=u_true, is_star=is_star, log_flux_r=log_fr, colours=colours, e_dev=e_dev, e_axis=e_axis,
+                   e_angle=e_angle, e_scale=e_scale, side=side, epochs=np.full(S, epochs)),
+        theta_truth=th, profiles=profiles, name=f"field{size}x{size}x{NF}")
+    return SynthField(batch=sb, fields=fields, n_fields=NF, H=H, W=W, img_field=img_field, field_band=field_band,
+                      field_wcs=field_wcs, field_sky=field_sky, field_psf=field_psf)

@@ -1,0 +1,128 @@
+"""Crowded fields on the GPU: rendering, neighbour arrays and block coordinate ascent,
+against the FP64 oracle."""
+import multiprocessing as mp
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import model, newton
+from helpers import ELBO_RTOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1611_03404_amd import celeste as cb
+    ctx = cb.Context(0)
+    sf = synth.make_field(n_sources=400, size=256, epochs=1, device="cuda", seed=5)
+    yield cb, ctx, sf
+    ctx.close()
+
+
+def _oracle_source_rate(sb, i, theta, px, py):
+    z = model.image_z(theta, int(sb.img_band[i]), sb.img_wcs[i])
+    d = np.array([[px - z[5], py - z[6]]], dtype=np.float64)
+    psf = sb.img_psf[i][: int(sb.img_npsf[i])]
+    A = np.array([[sb.img_wcs[i][0], sb.img_wcs[i][1]], [sb.img_wcs[i][2], sb.img_wcs[i][3]]])
+    Gs = model.star_value(d, psf)
+    Gg = model.galaxy_value(d, psf, theta[3], theta[4], theta[5], theta[6], sb.profiles, A)
+    e, v = model.rate_values(z, Gs, Gg, 0.0, float(sb.img_calib[i]), 0.0, 0.0)
+    return float(e[0]), float(v[0])
+
+
+def _covering(sf, f, px, py):
+    sb = sf.batch
+    ox, oy = sb.img_origin[:, 0], sb.img_origin[:, 1]
+    return np.nonzero((sf.img_field == f) & (px >= ox) & (px < ox + sb.img_w) & (py >= oy) & (py < oy + sb.img_h))[0]
+
+
+def test_render_and_neighbours_match_oracle(env):
+    import torch
+    cb, ctx, sf = env
+    sb = sf.batch
+    b = cb.Batch.from_synth(sb)
+    th = synth.generate.perturb_theta(sb.theta_truth, 21, scale=0.2)
+    thd = torch.from_numpy(th).cuda()
+    mean, var = ctx.render_fields(b, thd, sf.img_field, sf.n_fields, sf.H, sf.W)
+    mean2, var2 = ctx.render_fields(b, thd, sf.img_field, sf.n_fields, sf.H, sf.W)
+    assert torch.equal(mean, mean2) and torch.equal(var, var2)
+    mean, var = mean.cpu().numpy(), var.cpu().numpy()
+    rng = np.random.default_rng(1)
+    for _ in range(25):
+        f, px, py = int(rng.integers(sf.n_fields)), int(rng.integers(sf.W)), int(rng.integers(sf.H))
+        cov = _covering(sf, f, px, py)
+        e = v = 0.0
+        for i in cov:
+            de, dv = _oracle_source_rate(sb, i, th[i // sf.n_fields], px, py)
+            e += de
+            v += dv
+        o = (f * sf.H + py) * sf.W + px
+        _say("pixel", f, px, py, "sources", len(cov), "gpu", mean[o], var[o], "oracle", e, v)
+        assert abs(mean[o] - e) <= 1e-5 * max(e, 1e-3) + 1e-6
+        assert abs(var[o] - v) <= 1e-4 * max(v, 1e-3) + 1e-6
+    # neighbour arrays: field total minus the source's own contribution
+    npx = sb.img_h.astype(np.int64) * sb.img_w
+    off = np.concatenate([[0], np.cumsum(npx)[:-1]]).astype(np.int64)
+    nm = torch.empty(int(npx.sum()), dtype=torch.float32, device="cuda")
+    nv = torch.empty_like(nm)
+    ctx.neighbour_arrays(b, thd, sf.img_field, sf.n_fields, sf.H, sf.W,
+                         (torch.from_numpy(mean).cuda(), torch.from_numpy(var).cuda()), off, nm, nv)
+    nm, nv = nm.cpu().numpy(), nv.cpu().numpy()
+    for _ in range(25):
+        i = int(rng.integers(sb.n_images))
+        r, c = int(rng.integers(sb.img_h[i])), int(rng.integers(sb.img_w[i]))
+        px, py = int(sb.img_origin[i, 0]) + c, int(sb.img_origin[i, 1]) + r
+        own_e, own_v = _oracle_source_rate(sb, i, th[i // sf.n_fields], px, py)
+        o = (int(sf.img_field[i]) * sf.H + py) * sf.W + px
+        k = off[i] + r * sb.img_w[i] + c
+        assert abs(nm[k] - max(mean[o] - own_e, 0.0)) <= 1e-5 * max(mean[o], 1e-3) + 1e-6
+        assert nv[k] >= 0.0
+
+
+def _oracle_fit(args):
+    sb, s, th0, nbr = args
+    imgs = model.source_images(sb, s, nbr=nbr)
+    return newton.fit(th0, imgs, sb.prior, sb.profiles).elbo
+
+
+def test_block_coordinate_ascent(env):
+    from paper_1611_03404_amd import field
+    cb, ctx, sf = env
+    sb = sf.batch
+    theta, res, info = field.bca(ctx, sb, (sf.img_field, sf.n_fields, sf.H, sf.W), sweeps=2,
+                                 start_mode=cb.INIT_PLAIN, log=_say)
+    theta = theta.cpu().numpy()
+    assert np.mean(res["status"] == cb.CONVERGED) > 0.95
+    nm, nv, off = (x.cpu().numpy() if hasattr(x, "cpu") else x for x in info["nbr"])
+    rng = np.random.default_rng(2)
+    pick = [int(s) for s in rng.choice(sb.n_sources, size=4, replace=False)]
+    sub = sb.subset(pick)          # host copies: the oracle workers never see device memory
+    args = []
+    for k, s in enumerate(pick):
+        nbr = {}
+        for j in range(int(sub.src_img_off[k]), int(sub.src_img_off[k + 1])):
+            i = int(sb.src_img_off[s]) + (j - int(sub.src_img_off[k]))
+            h, w = int(sb.img_h[i]), int(sb.img_w[i])
+            nbr[j] = (nm[off[i]:off[i] + h * w].reshape(h, w), nv[off[i]:off[i] + h * w].reshape(h, w))
+        v = model.elbo_value(theta[s], model.source_images(sub, k, nbr=nbr), sub.prior, sub.profiles)
+        _say("source", s, "gpu elbo", res["elbo"][s], "oracle at gpu theta", v)
+        assert abs(v - res["elbo"][s]) <= ELBO_RTOL * abs(v)
+        args.append((sub, k, theta[s], nbr))
+    # the GPU optimum is also a (near-)optimum for the oracle from the same point
+    with mp.get_context("fork").Pool(4) as pool:
+        ref = pool.map(_oracle_fit, args)
+    for (a, r) in zip(args, ref):
+        v = model.elbo_value(a[2], model.source_images(a[0], a[1], nbr=a[3]), a[0].prior, a[0].profiles)
+        _say("oracle refit", r, "gpu", v)
+        assert v >= r - ELBO_RTOL * abs(r)
