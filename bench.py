@@ -47,8 +47,23 @@ def flop_value_per_px(K, E, D):
     return K * (13 + 8 * (E + D)) + 30
 
 
+def _one_thread():
+    """Pool initialiser: one BLAS/OpenMP thread per worker process."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+class _indexed:
+    """Wraps a worker so imap_unordered results carry their task index."""
+
+    def __init__(self, fn):
+        self.fn = fn
+
+    def __call__(self, k):
+        return k, self.fn(k)
+
+
 def _oracle_eval_worker(args):
-    os.environ["OMP_NUM_THREADS"] = "1"
     sb, s, theta = args
     from oracle import model
     imgs = model.source_images(sb, s)
@@ -88,7 +103,7 @@ def cpu_baseline(sb, theta0, gpu_full_px_per_step, gpu_value_px_per_step, conver
         imgs = model.source_images(sub, k)
         args.append((sub, k, oinit.plain_init(sub.u_cat[k], imgs, sub.prior)))
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
+    with mp.get_context("fork").Pool(cores, initializer=_one_thread) as pool:
         out = pool.map(_oracle_eval_worker, args, chunksize=1)
     wall = time.perf_counter() - t0
     px = sum(o[0] for o in out)
@@ -103,6 +118,96 @@ def cpu_baseline(sb, theta0, gpu_full_px_per_step, gpu_value_px_per_step, conver
                    f"value evaluation each at the plain start on {cores} processes ({wall:.1f} s wall); scaled to "
                    f"whole fits with the GPU fits' pixel-evaluation counts per step"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
+    }
+
+
+_FIELD_JOB = None   # (subset, per-source neighbour dicts, thetas, n_full): inherited by forked workers
+
+
+def _field_oracle_worker(k):
+    sb, nbrs, thetas, n_full = _FIELD_JOB
+    s, theta, nbr, full = k, thetas[k], nbrs[k], k < n_full
+    from oracle import model
+    imgs = model.source_images(sb, s, nbr=nbr)
+    t0 = time.perf_counter()
+    if full:
+        model.elbo(theta, imgs, sb.prior, sb.profiles)
+    t1 = time.perf_counter()
+    v = model.elbo_value(theta, imgs, sb.prior, sb.profiles)
+    t2 = time.perf_counter()
+    npx = int(sum(int(im["h"]) * int(im["w"]) for im in imgs))
+    return npx, t1 - t0, t2 - t1, v
+
+
+def _field_host_subset(sb, pick, nbr):
+    """Host copies of the picked sources' patches and of their neighbour arrays (image index
+    of the subset -> (mean, var)), for the oracle."""
+    import numpy as np
+    import torch
+    nm, nv, off = nbr
+    sub = sb.subset(pick)
+    out = []
+    for k, s in enumerate(pick):
+        i0, i1 = int(sb.src_img_off[s]), int(sb.src_img_off[s + 1])
+        sizes = [int(sb.img_h[i]) * int(sb.img_w[i]) for i in range(i0, i1)]
+        m = torch.cat([nm[int(off[i]):int(off[i]) + n] for i, n in zip(range(i0, i1), sizes)]).cpu().numpy()
+        v = torch.cat([nv[int(off[i]):int(off[i]) + n] for i, n in zip(range(i0, i1), sizes)]).cpu().numpy()
+        d, o = {}, 0
+        for j, i in enumerate(range(i0, i1)):
+            h, w = int(sb.img_h[i]), int(sb.img_w[i])
+            d[int(sub.src_img_off[k]) + j] = (m[o:o + h * w].reshape(h, w), v[o:o + h * w].reshape(h, w))
+            o += h * w
+        out.append(d)
+    return sub, out
+
+
+def field_cpu_baseline(sb, theta, res, nbr, gpu_full_px_per_step, gpu_value_px_per_step, sources_per_step,
+                       n_check, budget_s=15.0):
+    """Oracle on the host cores for the crowded field, at the GPU's final estimates with the
+    last sweep's neighbour arrays: value+gradient+Hessian and value evaluations of a few
+    random sources, scaled to the step with the GPU's pixel-evaluation counts; and the
+    ELBO of n_check random sources against the GPU's."""
+    import multiprocessing as mp
+    import numpy as np
+    cores = max(1, min(16, os.cpu_count() or 1))
+    rng = np.random.default_rng(161103406)
+    check = [int(s) for s in rng.choice(sb.n_sources, size=min(n_check, sb.n_sources), replace=False)]
+    npx = np.array([int(np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64)
+                               * sb.img_w[sb.src_img_off[s]:sb.src_img_off[s + 1]])) for s in check])
+    n_full, est = 0, 0.0
+    while n_full < len(check) and est < budget_s * cores and n_full < 4 * cores:
+        est += 7e-5 * npx[n_full]
+        n_full += 1
+    t = time.perf_counter()
+    sub, nbrs = _field_host_subset(sb, check, nbr)
+    t_copy = time.perf_counter() - t
+    global _FIELD_JOB
+    _FIELD_JOB = (sub, nbrs, theta[check], n_full)
+    t0 = time.perf_counter()
+    out = [None] * len(check)
+    with mp.get_context("fork").Pool(cores, initializer=_one_thread) as pool:
+        for done, (k, o) in enumerate(pool.imap_unordered(_indexed(_field_oracle_worker), range(len(check)))):
+            out[k] = o
+            if (done + 1) % 100 == 0 or done + 1 == len(check):
+                print(f"[bench] oracle: {done + 1}/{len(check)} sources, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+    _FIELD_JOB = None
+    wall = time.perf_counter() - t0
+    px_full = sum(o[0] for o in out[:n_full])
+    full_rate = px_full / sum(o[1] for o in out[:n_full]) * cores
+    val_rate = sum(o[0] for o in out) / sum(o[2] for o in out) * cores
+    step_s = gpu_full_px_per_step / full_rate + gpu_value_px_per_step / val_rate
+    ref = np.array([o[3] for o in out])
+    gpu = np.asarray(res["elbo"])[check]
+    rel = np.abs(gpu - ref) / np.abs(ref)
+    return {
+        "value": sources_per_step / step_s, "unit": "sources/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{n_full} random sources ({px_full} px): one value+gradient+Hessian and one value evaluation "
+                   f"each at the GPU's final estimates with the last sweep's neighbour arrays, on {cores} processes; "
+                   f"scaled to the step with the GPU's pixel-evaluation counts"),
+        "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
+        "elbo_check": {"sources": len(check), "max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
+                       "host_copy_s": t_copy, "oracle_wall_s": wall},
     }
 
 
@@ -331,6 +436,11 @@ def field_bench(args, ctx, net, sur_info, log):
                      "avg_launch_ms": st["ms_full"] / max(1, st["full_launches"]), "launches": st["full_launches"],
                      "traffic": None},
     }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) and ELBO check on a 1% sample ...")
+        out["cpu_baseline"] = field_cpu_baseline(sb, theta.cpu().numpy(), res, info["nbr"],
+                                                 st["full_px"] / args.steps, st["value_px"] / args.steps,
+                                                 sb.n_sources, n_check=max(1, sb.n_sources // 100))
     print(json.dumps(out), flush=True)
     if net is not None:
         ctx.set_surrogate(None)

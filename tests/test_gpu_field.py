@@ -126,3 +126,61 @@ def test_block_coordinate_ascent(env):
         v = model.elbo_value(a[2], model.source_images(a[0], a[1], nbr=a[3]), a[0].prior, a[0].profiles)
         _say("oracle refit", r, "gpu", v)
         assert v >= r - ELBO_RTOL * abs(r)
+
+
+_JOB = None   # (subset, [(source index in subset, theta, neighbour dict)]): inherited by forked workers
+
+
+def _oracle_value(k):
+    sb, jobs = _JOB
+    s, th, nbr = jobs[k]
+    return model.elbo_value(th, model.source_images(sb, s, nbr=nbr), sb.prior, sb.profiles)
+
+
+def test_full_field_one_percent_sample():
+    """The full crowded field (2048x2048 px, 5 bands x 4 epochs, 100,000 sources) with the
+    fit options the benchmark uses: after one sweep, the ELBO of a 1% sample of sources at the
+    GPU's estimates, with the GPU's neighbour arrays, against the oracle."""
+    import torch
+    from paper_1611_03404_amd import celeste as cb
+    from paper_1611_03404_amd import field
+    ctx = cb.Context(0)
+    ctx.set_option(cb.OPT_PROFILE, 1)
+    try:
+        sf = synth.make_field(n_sources=100000, size=2048, epochs=4, device="cuda")
+        sb = sf.batch
+        _say("field", sb.n_sources, "sources", sb.n_images, "patches", sb.n_pixels, "px")
+        theta, res, info = field.bca(ctx, sb, (sf.img_field, sf.n_fields, sf.H, sf.W), sweeps=1,
+                                     start_mode=cb.INIT_PLAIN, log=_say)
+        theta = theta.cpu().numpy()
+        assert np.mean(res["status"] == cb.CONVERGED) > 0.95
+        nm, nv, off = info["nbr"]
+        rng = np.random.default_rng(4)
+        pick = [int(s) for s in rng.choice(sb.n_sources, size=1000, replace=False)]
+        sub = sb.subset(pick)
+        args = []
+        for k, s in enumerate(pick):
+            i0, i1 = int(sb.src_img_off[s]), int(sb.src_img_off[s + 1])
+            nbr = {}
+            for j, i in enumerate(range(i0, i1)):
+                h, w = int(sb.img_h[i]), int(sb.img_w[i])
+                o = int(off[i])
+                nbr[int(sub.src_img_off[k]) + j] = (nm[o:o + h * w].cpu().numpy().reshape(h, w),
+                                                    nv[o:o + h * w].cpu().numpy().reshape(h, w))
+            args.append((k, theta[s], nbr))
+        del nm, nv, info
+        torch.cuda.empty_cache()
+        _say("oracle ELBO of", len(args), "sources")
+        global _JOB
+        _JOB = (sub, args)
+        try:
+            with mp.get_context("fork").Pool(16) as pool:
+                ref = np.array(pool.map(_oracle_value, range(len(args)), chunksize=8))
+        finally:
+            _JOB = None
+        gpu = res["elbo"][pick]
+        rel = np.abs(gpu - ref) / np.abs(ref)
+        _say("max rel err", rel.max(), "median", np.median(rel))
+        assert rel.max() <= ELBO_RTOL
+    finally:
+        ctx.close()
