@@ -297,8 +297,9 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
       for (int k = 0; k < CELESTE_MAX_PSF; ++k)
         for (int j = 0; j < 6; ++j) d.psf[k][j] = k < im.n_psf ? im.psf[k][j] : 0.0;
       d.item_begin = (int)P->items.size();
-      const int n = im.h * im.w;
-      for (int a = 0; a < n; a += chunk) P->items.push_back(WorkItem{(int)i, s, a, std::min(n, a + chunk)});
+      // bands of whole 8-row tile rows holding about `chunk` pixels
+      const int band = std::max(TILE, (chunk / std::max(1, im.w)) / TILE * TILE);
+      for (int r = 0; r < im.h; r += band) P->items.push_back(WorkItem{(int)i, s, r, std::min(im.h, r + band)});
       d.item_end = (int)P->items.size();
     }
     sd.item_end = (int)P->items.size();

@@ -27,10 +27,12 @@ struct ImgDev {
   double psf[CELESTE_MAX_PSF][6];
 };
 
-// One unit of pixel work: a contiguous run of one image's pixels (row-major index).
+// One unit of pixel work: a band of rows [row_begin, row_end) of one image, all columns.
+// The pixel kernels walk a band in 8x8 tiles, one tile per wavefront step.
 struct WorkItem {
-  int32_t img, src, px_begin, px_end;
+  int32_t img, src, row_begin, row_end;
 };
+constexpr int TILE = 8;
 
 // Source -> images / work items (CSR, contiguous).
 struct SrcDev {

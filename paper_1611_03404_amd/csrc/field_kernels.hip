@@ -15,7 +15,7 @@ namespace {
 
 using namespace tab;
 
-constexpr int TILE = 32;
+constexpr int RTILE = 32;
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -55,8 +55,8 @@ __global__ __launch_bounds__(256) void k_render(const int* __restrict__ tile_off
   const int tile = blockIdx.x;
   const int f = tile / tiles_per_field, tt = tile - f * tiles_per_field;
   const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
-  const int px = tx * TILE + (threadIdx.x & (TILE - 1));
-  const int py0 = ty * TILE + (threadIdx.x >> 5);
+  const int px = tx * RTILE + (threadIdx.x & (RTILE - 1));
+  const int py0 = ty * RTILE + (threadIdx.x >> 5);
   double e[4] = {0.0, 0.0, 0.0, 0.0}, v[4] = {0.0, 0.0, 0.0, 0.0};
   const int ncomp = n_exp + n_dev;
   for (int q = tile_off[tile]; q < tile_off[tile + 1]; ++q) {

@@ -1,7 +1,7 @@
 // Pixel-sum kernels: the hot loop of the per-source ELBO (sections III-A/B).
 //
-// One work item = a contiguous run of one image's pixels; a 256-thread block
-// takes one work item, each lane one pixel at a time.  Per pixel the kernel
+// One work item = a band of rows of one image; a block takes one work item and
+// its wavefronts walk the band in 8x8 pixel tiles, one pixel per lane.  Per pixel the kernel
 // evaluates the PSF-convolved star mixture and the exp/dev galaxy mixtures with
 // all derivatives needed for the gradient and dense Hessian, forms the mean and
 // variance of the Poisson rate under q, applies the delta-method expected
@@ -12,6 +12,19 @@
 // respect to the covariance are position-space derivatives: per pixel the kernel
 // accumulates Hermite moments of orders 0-4 weighted by nu^k, and maps them onto
 // (e_axis, e_angle, e_scale) once per pixel with per-image coefficients of dW/deta.
+//
+// Work that is exactly zero is skipped, never approximated: a mixture component whose
+// exponent is below -160 on every lane of a wavefront has density exactly 0 in FP32
+// there (2^-160 is far below the smallest subnormal), so all its contributions are
+// exactly 0 and the wavefront branches over it.  Lanes of a tile that fall outside the
+// image evaluate a point far from every component with a zero count and zero
+// background variance, which makes every one of their terms exactly 0 as well.
+//
+// Accumulation: the ELBO value is accumulated per lane in FP64.  The 77 derivative
+// entries are summed per lane in FP32 over at most FLUSH tile steps, then summed across
+// the wavefront by a pairwise FP32 butterfly and added to FP64 accumulators; so every
+// FP64 addend is a sum of at most 64 * FLUSH pixel terms formed with at most
+// FLUSH - 1 + 6 FP32 roundings.
 #include "celeste_internal.h"
 
 namespace celeste {
@@ -21,6 +34,13 @@ namespace {
 using namespace tab;
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+constexpr float E_ZERO = -160.f;   // exp2 below this is exactly 0 in FP32
+constexpr float FAR = 1.0e4f;      // offset used by lanes outside the image
+constexpr int FLUSH = 16;          // tile steps summed per lane in FP32 before a wavefront flush
+
+// True if the predicate holds on some lane of the wavefront (a uniform branch condition).
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 // Hermite moments of one galaxy profile type (exp or dev), summed over components.
 struct GalAcc {
@@ -46,6 +66,7 @@ __device__ __forceinline__ void zero(GalAcc& A) {
 __device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
                                          float dyy, GalAcc& A) {
   const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
+  if (!wave_any(e >= E_ZERO)) return;
   const float N = ex2(e);
   const float Pxx = r[R_PXX], Pxy = r[R_PXY], Pyy = r[R_PYY];
   const float bx = fmaf(Pxx, dx, Pxy * dy);
@@ -85,37 +106,42 @@ __device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, 
 }
 
 __device__ __forceinline__ float gal_value(const float* __restrict__ r, float dxx, float dxy, float dyy) {
-  return ex2(fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0]))));
+  const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
+  return wave_any(e >= E_ZERO) ? ex2(e) : 0.f;
 }
 
 constexpr int tri(int i, int j) { return i * NZ - (i * (i - 1)) / 2 + (j - i); }
 
-// Wave reduction of 80 doubles by recursive halving (masks 32, 16, 8, 4) and a
-// butterfly over the last 4 lanes; returns in out[0..4] the wave sums of the 5
-// entries with base index 40*b5 + 20*b4 + 10*b3 + 5*b2 (b_k = lane bit k).
+// Wavefront sum of 80 lane values by recursive halving (masks 32, 16, 8, 4) and a
+// butterfly over the last 4 lanes: on return the lanes of each quad hold the wavefront
+// sums of the 5 entries starting at quad_base(lane) = 40*b5 + 20*b4 + 10*b3 + 5*b2
+// (b_k = lane bit k).
 template <int N>
-__device__ __forceinline__ void halve(const double* v, double* o, int mask, bool up) {
+__device__ __forceinline__ void halvef(const float* v, float* o, int mask, bool up) {
 #pragma unroll
   for (int i = 0; i < N / 2; ++i) {
-    const double send = up ? v[i] : v[i + N / 2];
-    const double keep = up ? v[i + N / 2] : v[i];
+    const float send = up ? v[i] : v[i + N / 2];
+    const float keep = up ? v[i + N / 2] : v[i];
     o[i] = keep + __shfl_xor(send, mask);
   }
 }
 
-__device__ __forceinline__ int wave_reduce80(const double* acc, double* out5) {
+__device__ __forceinline__ int quad_base(int lane) {
+  return ((lane >> 5) & 1) * 40 + ((lane >> 4) & 1) * 20 + ((lane >> 3) & 1) * 10 + ((lane >> 2) & 1) * 5;
+}
+
+__device__ __forceinline__ void wave_sum80f(const float* v, float* out5) {
   const int lane = threadIdx.x & 63;
-  double t40[40], t20[20], t10[10];
-  halve<80>(acc, t40, 32, lane & 32);
-  halve<40>(t40, t20, 16, lane & 16);
-  halve<20>(t20, t10, 8, lane & 8);
-  halve<10>(t10, out5, 4, lane & 4);
+  float t40[40], t20[20], t10[10];
+  halvef<80>(v, t40, 32, lane & 32);
+  halvef<40>(t40, t20, 16, lane & 16);
+  halvef<20>(t20, t10, 8, lane & 8);
+  halvef<10>(t10, out5, 4, lane & 4);
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     out5[i] += __shfl_xor(out5[i], 2);
     out5[i] += __shfl_xor(out5[i], 1);
   }
-  return ((lane >> 5) & 1) * 40 + ((lane >> 4) & 1) * 20 + ((lane >> 3) & 1) * 10 + ((lane >> 2) & 1) * 5;
 }
 
 // NE, ND > 0: compile-time component counts (fully unrolled loops); 0: runtime counts.
@@ -140,25 +166,43 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
   const float io2 = io * io, io3 = io2 * io;
 
-  double acc[80];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tiles_x = (w + TILE - 1) / TILE;
+  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + TILE - 1) / TILE);
+  double val = 0.0;                 // ELBO value, per lane
+  double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // wavefront sums of 5 derivative entries (quad-uniform)
+  const int base5 = quad_base(lane);              // first of the 5 entries this lane's quad holds
+  float accf[80];                   // per-lane FP32 sums of the derivative entries since the last flush
 #pragma unroll
-  for (int i = 0; i < 80; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 80; ++i) accf[i] = 0.f;
+  int since = 0;                    // tile steps since the last flush (wavefront-uniform)
+  auto flush = [&]() {
+    float part[5];
+    wave_sum80f(accf, part);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) acc5[i] += (double)part[i];
+#pragma unroll
+    for (int i = 0; i < 80; ++i) accf[i] = 0.f;
+  };
 
-  for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
-    const int row = m / w, col = m - row * w;
-    const size_t o = (size_t)row * pitch + col;
-    const size_t on = (size_t)row * npitch + col;
-    const float x = pix[o];
-    const float ebg = sky + (nbrE ? nbrE[on] : 0.f);
-    const float vbg = nbrV ? nbrV[on] : 0.f;
-    const float dx0 = (float)col - psx, dy0 = (float)row - psy;
+  for (int t = wv; t < n_tiles; t += BLOCK / 64) {
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int row = wi.row_begin + ty * TILE + (lane >> 3), col = tx * TILE + (lane & 7);
+    const bool live = row < wi.row_end && col < w;
+    const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
+    const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
+    const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
+    const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
+    const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
 
     // ---- star: N, dN/dp, d2N/dp2
     float s0 = 0.f, s1x = 0.f, s1y = 0.f, s2xx = 0.f, s2xy = 0.f, s2yy = 0.f;
     for (int k = 0; k < npsf; ++k) {
       const float* __restrict__ r = T + STAR + k * STAR_REC;
       const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
-      const float N = ex2(fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0]))));
+      const float e = fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0])));
+      if (!wave_any(e >= E_ZERO)) continue;
+      const float N = ex2(e);
       const float bx = fmaf(r[R_PXX], dx, r[R_PXY] * dy), by = fmaf(r[R_PXY], dx, r[R_PYY] * dy);
       s0 += N;
       s1x = fmaf(N, bx, s1x);
@@ -324,31 +368,35 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       }
     }
 
-    // ---- accumulate value, gradient and Hessian in FP64
-    acc[0] += (double)lval;
+    // ---- value in FP64 per lane; gradient and Hessian in the per-lane FP32 sums
+    val += (double)lval;
     float hT[NZ], hU[NZ];
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
-      acc[1 + j] += (double)fmaf(wT, Tz[j], wU * Uz[j]);
+      accf[j] += fmaf(wT, Tz[j], wU * Uz[j]);
       hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
       hU[j] = wTU * Tz[j];
     }
 #pragma unroll
     for (int i = 0; i < NZ; ++i) {
 #pragma unroll
-      for (int j = i; j < NZ; ++j) {
-        acc[1 + NZ + tri(i, j)] += (double)fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
-      }
+      for (int j = i; j < NZ; ++j) accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+    }
+    if (++since == FLUSH) {
+      flush();
+      since = 0;
     }
   }
+  if (since > 0) flush();
 
   // ---- block reduction (deterministic order) and one FP64 partial per work item
-  double part[5];
-  const int base = wave_reduce80(acc, part);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o);
+  if (lane == 0) red[wv][0] = val;
   if ((lane & 3) == 0) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) red[wv][base + i] = part[i];
+    for (int i = 0; i < 5; ++i)
+      if (base5 + i < NACC - 1) red[wv][1 + base5 + i] = acc5[i];
   }
   __syncthreads();
   if (threadIdx.x < NACC) {
@@ -378,15 +426,19 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
   const float ed = T[EDEV];
   const float cs = T[CS], cg = T[CG], Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tiles_x = (w + TILE - 1) / TILE;
+  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + TILE - 1) / TILE);
   double acc = 0.0;
-  for (int m = wi.px_begin + (int)threadIdx.x; m < wi.px_end; m += BLOCK) {
-    const int row = m / w, col = m - row * w;
-    const size_t o = (size_t)row * pitch + col;
-    const size_t on = (size_t)row * npitch + col;
-    const float x = pix[o];
-    const float ebg = sky + (nbrE ? nbrE[on] : 0.f);
-    const float vbg = nbrV ? nbrV[on] : 0.f;
-    const float dx0 = (float)col - psx, dy0 = (float)row - psy;
+  for (int t = wv; t < n_tiles; t += BLOCK / 64) {
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int row = wi.row_begin + ty * TILE + (lane >> 3), col = tx * TILE + (lane & 7);
+    const bool live = row < wi.row_end && col < w;
+    const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
+    const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
+    const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
+    const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
+    const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
     float Gs = 0.f, gx = 0.f, gd = 0.f;
     for (int k = 0; k < npsf; ++k) {
       const float* __restrict__ r = T + STAR + k * STAR_REC;

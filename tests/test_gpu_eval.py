@@ -146,13 +146,14 @@ def test_deterministic_and_batch_equals_single(cb, ctx):
         one = full.subset([s])
         e, g, H = ctx.elbo_eval(cb.Batch.from_synth(one), th[s:s + 1])
         assert e[0] == e1[s] and np.array_equal(g[0], g1[s]) and np.array_equal(H[0], H1[s])
-    # block size does not change results
+    # block size regroups the per-lane FP32 sums of the derivative terms (the value is
+    # summed in FP64 per lane): results move by FP32 rounding of those partial sums only
     ctx.set_option(cb.OPT_BLOCK, 128)
     try:
         e3, g3, H3 = ctx.elbo_eval(b, th)
     finally:
         ctx.set_option(cb.OPT_BLOCK, 256)
-    assert np.allclose(e3, e1, rtol=1e-12) and deriv_err(H3, H1) < 1e-9
+    assert np.allclose(e3, e1, rtol=1e-12) and deriv_err(g3, g1) < 2e-5 and deriv_err(H3, H1) < 2e-5
 
 
 def test_value_only_matches_full(cb, ctx):
