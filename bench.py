@@ -225,6 +225,7 @@ def main():
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps")
     ap.add_argument("--sweeps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported in this build "
@@ -269,6 +270,14 @@ def main():
     batch = cb.Batch.from_synth(sb)
     theta0 = np.zeros((sb.n_sources, 27))
     theta0[:, 0:2] = sb.u_cat
+    tune = None
+    if not args.no_autotune:
+        # launch and tile shapes of the pixel kernels, timed on a sample at the plain start (not timed)
+        th_start, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+        t = time.perf_counter()
+        tune = ctx.autotune(batch, th_start)
+        tune["tune_s"] = time.perf_counter() - t
+        log(f"autotune: {tune}")
     modes = [("plain", cb.INIT_PLAIN)] + ([] if net is None else [("surrogate", cb.INIT_SURROGATE)])
     runs = {}
     for name, mode in modes:
@@ -350,6 +359,7 @@ def main():
         "status": status_counts,
         "phase_ms_per_step": {k[3:]: v / args.steps for k, v in st.items() if k.startswith("ms_")},
         "starts": {name: summary(r) for name, r in runs.items()},
+        "autotune": tune,
         "surrogate_training": None if sur_info is None else
         {k: v for k, v in sur_info.items() if k not in ("psi_mean", "psi_std")},
         "roofline": {
@@ -398,6 +408,15 @@ def field_bench(args, ctx, net, sur_info, log):
         f"{sb.n_pixels} patch px ({time.perf_counter() - t_gen:.1f} s to generate)")
     meta = (sf.img_field, sf.n_fields, sf.H, sf.W)
     mode = cb.INIT_SURROGATE if net is not None else cb.INIT_PLAIN
+    tune = None
+    if not args.no_autotune:
+        b0 = cb.Batch.from_synth(sb)
+        th0 = np.zeros((sb.n_sources, 27))
+        th0[:, 0:2] = sb.u_cat
+        th_start, _ = ctx.start(b0, th0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+        tune = ctx.autotune(b0, th_start)
+        log(f"autotune: {tune}")
+        del b0
     for w in range(args.warmup):
         t = time.perf_counter()
         field.bca(ctx, sb, meta, sweeps=1, start_mode=mode)
@@ -427,6 +446,7 @@ def field_bench(args, ctx, net, sur_info, log):
                                f"{sb.n_sources} sources, {args.sweeps} Jacobi sweeps",
                    "n_patch_pixels": sb.n_pixels, "start": "surrogate" if net is not None else "plain"},
         "converged_last_sweep": int(np.sum(res["status"] == cb.CONVERGED)),
+        "autotune": tune,
         "sweeps": info["history"], "timings_s_per_step": {k: v / args.steps for k, v in info["timings"].items()},
         "pixel_evals_per_s": st["full_px"] / wall,
         "kernel_pixel_evals_per_s": st["full_px"] / full_s if full_s > 0 else None,

@@ -81,9 +81,14 @@ enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
   CELESTE_OPT_USE_GRAPH = 3,    /* batched fit replays a captured HIP graph per iteration (default 1) */
   CELESTE_OPT_PROFILE = 4,      /* 1: time every kernel phase with HIP events (fits run without a graph) */
-  CELESTE_OPT_VARIANT = 5       /* value+gradient+Hessian pixel-kernel variant 0..3 (default 3): bit 0 = two
-                                   resident waves per SIMD, bit 1 = loops unrolled for 6 exp + 8 dev
-                                   components; all variants compute the same arithmetic */
+  CELESTE_OPT_VARIANT = 5,      /* pixel-kernel variant 0..3 (default 3): bit 0 = two resident waves per
+                                   SIMD (value+gradient+Hessian kernel), bit 1 = loops unrolled for
+                                   6 exp + 8 dev components (both kernels); all variants compute the
+                                   same arithmetic */
+  CELESTE_OPT_TILE_W = 6,       /* width of the 64-pixel tile a wavefront of the value+gradient+Hessian
+                                   kernel takes per step: 8, 16, 32 or 64 (default 8) */
+  CELESTE_OPT_VALUE_BLOCK = 7,  /* threads per value-kernel block: 128 or 256 (default 256) */
+  CELESTE_OPT_VALUE_TILE_W = 8  /* tile width of the value kernel: 8, 16, 32 or 64 (default 8) */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -180,9 +185,9 @@ void celeste_ctx_destroy(celeste_ctx* ctx);
 /* Message for the last failing call on this host thread ("" if none). */
 const char* celeste_last_error(void);
 
-/* Set a tuning option of the context (CELESTE_OPT_*).  Results do not depend on the
- * block size; the chunk size changes only the FP64 summation grouping.  Errors:
- * E_INVALID (unknown option or value out of range). */
+/* Set a tuning option of the context (CELESTE_OPT_*).  The options change only how the
+ * pixel sums are grouped (results move by rounding, far inside the stated tolerances).
+ * Errors: E_INVALID (unknown option or value out of range). */
 int celeste_ctx_set_option(celeste_ctx* ctx, int option, int64_t value);
 
 /* Read (and optionally reset) the context's counters.  Errors: E_INVALID, E_DEVICE. */
@@ -190,7 +195,7 @@ int celeste_ctx_get_stats(celeste_ctx* ctx, celeste_stats* out, int reset);
 
 /* sizeof of the ABI structs, for bindings to check their layouts: 0 celeste_image,
  * 1 celeste_prior, 2 celeste_profiles, 3 celeste_batch, 4 celeste_fit_opts,
- * 5 celeste_fit_result, 6 celeste_stats; 0 for any other value. */
+ * 5 celeste_fit_result, 6 celeste_stats, 7 celeste_tune_result; 0 for any other value. */
 size_t celeste_struct_size(int which);
 
 /* Defaults for celeste_fit_opts (values in the comments above). */
@@ -301,6 +306,34 @@ int celeste_neighbour_arrays(celeste_ctx* ctx, const celeste_batch* batch, const
  * ELBO.  opts->max_iter is ignored. */
 int celeste_start(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout, const celeste_fit_opts* opts,
                   double* elbo_out);
+
+/* ------------------------------------------------------------------ autotuner */
+
+/* Options chosen by celeste_autotune and the kernel times behind the choice. */
+typedef struct celeste_tune_result {
+  int32_t chunk_px, block, variant, tile_w;   /* value+gradient+Hessian kernel (CELESTE_OPT_*) */
+  int32_t value_block, value_tile_w;          /* value kernel */
+  int32_t n_candidates;                       /* configurations timed (0 when read from the cache) */
+  int32_t from_cache;                         /* 1: taken from the cache file without timing */
+  int64_t sample_sources, sample_px;          /* tuning sample */
+  double full_ms, value_ms;                   /* best time per launch over the sample */
+  double default_full_ms, default_value_ms;   /* the default options' times on the same sample */
+} celeste_tune_result;
+
+/* Tile shapes and launch shapes of the pixel kernels, chosen by timing (the batching of
+ * the per-source pixel sums of section III-B on this device).  Takes a deterministic
+ * sample of the batch (every k-th source, about sample_px pixels; sample_px <= 0 means
+ * 6e7), evaluates it at theta (n_sources x 27, batch memory) with the value+gradient+
+ * Hessian kernel under every candidate work-item size (2048..16384 px), block size,
+ * register budget and tile width, then with the value kernel under every block size and
+ * tile width, keeps the fastest (minimum of three timed launches each, HIP events on the
+ * library's stream) and sets them on the context.  cache_path (may be NULL) names a text
+ * file of earlier choices, one per line, keyed by device, compute-unit count, component
+ * counts and the batch's size class: a hit is applied without timing, a miss is appended.
+ * out may be NULL.  Errors: as celeste_elbo_eval; E_INVALID for an unreadable or
+ * unwritable cache file. */
+int celeste_autotune(celeste_ctx* ctx, const celeste_batch* batch, const double* theta, int64_t sample_px,
+                     const char* cache_path, celeste_tune_result* out);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,7 @@ CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE = 0, 1, 2, 3
 INIT_AS_GIVEN, INIT_PLAIN, INIT_SURROGATE = 0, 1, 2
 FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
+OPT_TILE_W, OPT_VALUE_BLOCK, OPT_VALUE_TILE_W = 6, 7, 8
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("nbr_pitch", "<i4"),
@@ -57,6 +58,14 @@ class Stats(ctypes.Structure):
                 ("value_launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("ms_setup", ctypes.c_double),
                 ("ms_full", ctypes.c_double), ("ms_reduce_full", ctypes.c_double), ("ms_tr", ctypes.c_double),
                 ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("chunk_px", ctypes.c_int32), ("block", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("value_block", ctypes.c_int32), ("value_tile_w", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("sample_sources", ctypes.c_int64),
+                ("sample_px", ctypes.c_int64), ("full_ms", ctypes.c_double), ("value_ms", ctypes.c_double),
+                ("default_full_ms", ctypes.c_double), ("default_value_ms", ctypes.c_double)]
 
 
 class CFields(ctypes.Structure):
@@ -111,15 +120,16 @@ def load():
     lib.celeste_neighbour_arrays.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields), vp, vp, vp]
     lib.celeste_start.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_psi_to_theta.argtypes = [vp, vp, i64, ctypes.c_double, vp]
+    lib.celeste_autotune.argtypes = [vp, ctypes.POINTER(CBatch), vp, i64, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
                  "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
                  "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
                  "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta",
-                 "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start"):
+                 "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start", "celeste_autotune"):
         getattr(lib, name).restype = ctypes.c_int
-    sizes = [lib.celeste_struct_size(k) for k in range(7)]
+    sizes = [lib.celeste_struct_size(k) for k in range(8)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
-              ctypes.sizeof(FitOpts), RESULT_DT.itemsize, ctypes.sizeof(Stats)]
+              ctypes.sizeof(FitOpts), RESULT_DT.itemsize, ctypes.sizeof(Stats), ctypes.sizeof(TuneResult)]
     if sizes != expect:
         raise RuntimeError(f"ABI struct sizes differ: library {sizes}, binding {expect}")
     _lib = lib
@@ -260,6 +270,16 @@ class Context:
 
     def set_option(self, option, value):
         _check(load().celeste_ctx_set_option(self._h, int(option), int(value)))
+
+    def autotune(self, batch: Batch, theta, sample_px=0, cache_path=None):
+        """Time the pixel kernels' launch and tile shapes on a sample of the batch at theta and
+        keep the fastest on this context (celeste_autotune).  Returns the choice as a dict."""
+        th = batch.as_input(theta)
+        r = TuneResult()
+        self._stream(batch)
+        _check(load().celeste_autotune(self._h, ctypes.byref(batch.c), _ptr(th), int(sample_px),
+                                       None if cache_path is None else os.fsencode(cache_path), ctypes.byref(r)))
+        return {name: getattr(r, name) for name, _ in TuneResult._fields_}
 
     def stats(self, reset=False):
         st = Stats()

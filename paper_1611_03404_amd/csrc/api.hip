@@ -67,6 +67,9 @@ struct celeste_ctx {
   int block = 256;
   int use_graph = 1;
   int variant = 3;   // pixel-kernel variant (register budget / unrolling), see CELESTE_OPT_VARIANT
+  int tile_log2 = 3;     // log2 tile width of the value+gradient+Hessian kernel
+  int vblock = 256;      // value kernel block size
+  int vtile_log2 = 3;    // log2 tile width of the value kernel
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
   DevBuf ctr;      // device pixel-evaluation counters [full, value]
@@ -504,6 +507,19 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 3) return fail(CELESTE_E_INVALID, "variant must be in 0..3");
       c->variant = (int)value;
       return CELESTE_OK;
+    case CELESTE_OPT_TILE_W:
+    case CELESTE_OPT_VALUE_TILE_W: {
+      int l = -1;
+      for (int k = 3; k <= 6; ++k)
+        if (value == (1 << k)) l = k;
+      if (l < 0) return fail(CELESTE_E_INVALID, "tile width must be 8, 16, 32 or 64");
+      (option == CELESTE_OPT_TILE_W ? c->tile_log2 : c->vtile_log2) = l;
+      return CELESTE_OK;
+    }
+    case CELESTE_OPT_VALUE_BLOCK:
+      if (value != 128 && value != 256) return fail(CELESTE_E_INVALID, "value block must be 128 or 256");
+      c->vblock = (int)value;
+      return CELESTE_OK;
     default:
       return fail(CELESTE_E_INVALID, "unknown option %d", option);
   }
@@ -518,6 +534,7 @@ size_t celeste_struct_size(int which) {
     case 4: return sizeof(celeste_fit_opts);
     case 5: return sizeof(celeste_fit_result);
     case 6: return sizeof(celeste_stats);
+    case 7: return sizeof(celeste_tune_result);
     default: return 0;
   }
 }
@@ -566,7 +583,8 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
   T.mark(1, st);
   if (grad) {
     HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant, st));
+                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant,
+                            ctx->tile_log2, st));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
@@ -574,7 +592,8 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
     ctx->stats.full_launches += 1;
   } else {
     HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
+                             ctx->vtile_log2, st));
     T.mark(2, st);
     HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
                                as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, ctr_value(ctx), st));
@@ -666,7 +685,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, ctx->variant, st));
+                          ctx->block, ctx->variant, ctx->tile_log2, st));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -677,7 +696,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, F.active, P.prof, tables, P.tstride, st));
   T->mark(5, st);
   HIPCHK(launch_eval_value(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.active, parts,
-                           ctx->block, st));
+                           ctx->vblock, ctx->variant, ctx->vtile_log2, st));
   T->mark(6, st);
   HIPCHK(launch_reduce_value(srcs, P.n_src, imgs, parts, ic, F.theta_trial, P.prior, F.active, F.f_trial,
                              ctr_value(ctx), st));
@@ -758,7 +777,8 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
       double* tk = k == 0 ? F.theta : F.theta_trial;
       HIPCHK(launch_setup(imgs0, P.n_img, tk, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
       HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs0, as<float>(ctx->tables), P.tstride,
-                               P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+                               P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
+                             ctx->vtile_log2, st));
       HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs0, as<double>(ctx->partials),
                                  as<double>(ctx->img_const), tk, P.prior, nullptr, k == 0 ? F.f : F.f_trial,
                                  ctr_value(ctx), st));
@@ -772,7 +792,8 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   const ImgDev* imgs = as<ImgDev>(ctx->imgs);
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
   HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                           P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, st));
+                           P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
+                             ctx->vtile_log2, st));
   HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs, as<double>(ctx->partials), as<double>(ctx->img_const),
                              F.theta, P.prior, nullptr, F.f, ctr_value(ctx), st));
   ctx->stats.value_launches += 1;
@@ -1084,3 +1105,242 @@ int celeste_start(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout,
 }
 
 }  // extern "C"
+
+// =============================================================================== autotuner
+
+namespace {
+
+std::string tune_key(celeste_ctx* ctx, const Packed& P, const celeste_batch* b) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) std::memset(&prop, 0, sizeof(prop));
+  int max_psf = 1;
+  double px = 0.0;
+  for (int i = 0; i < P.n_img; ++i) {
+    max_psf = std::max(max_psf, b->images[i].n_psf);
+    px += (double)b->images[i].h * b->images[i].w;
+  }
+  const int cls = (int)std::lround(std::log2(std::max(1.0, px / std::max(1, P.n_img))));
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s|%s|cu%d|exp%d|dev%d|psf%d|px2^%d", prop.name, prop.gcnArchName,
+                prop.multiProcessorCount, P.prof.n_exp, P.prof.n_dev, max_psf, cls);
+  std::string k(buf);
+  for (char& c : k)
+    if (c == ' ' || c == '\t' || c == '\n') c = '_';
+  return k;
+}
+
+// 1 if the cache holds the key (fills r), 0 if not or the file does not exist yet.
+int tune_cache_read(const char* path, const std::string& key, celeste_tune_result* r) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return 0;
+  char line[1024];
+  int found = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[600];
+    celeste_tune_result t{};
+    if (std::sscanf(line, "%599s %d %d %d %d %d %d %lf %lf", k, &t.chunk_px, &t.block, &t.variant, &t.tile_w,
+                    &t.value_block, &t.value_tile_w, &t.full_ms, &t.value_ms) == 9 &&
+        key == k) {
+      *r = t;   // the last matching line wins
+      found = 1;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+int tune_cache_append(const char* path, const std::string& key, const celeste_tune_result& r) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return fail(CELESTE_E_INVALID, "autotune cache %s: cannot open for appending", path);
+  std::fprintf(f, "%s %d %d %d %d %d %d %.6f %.6f\n", key.c_str(), r.chunk_px, r.block, r.variant, r.tile_w,
+               r.value_block, r.value_tile_w, r.full_ms, r.value_ms);
+  std::fclose(f);
+  return CELESTE_OK;
+}
+
+int log2_tile(int w) {
+  for (int k = 3; k <= 6; ++k)
+    if (w == (1 << k)) return k;
+  return -1;
+}
+
+// Minimum over `reps` timed launches (after one untimed) of a launch sequence, in ms.
+template <class F>
+int time_min(hipStream_t st, int reps, F launch, double* best) {
+  hipEvent_t a = nullptr, z = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&z));
+  int rc = CELESTE_OK;
+  *best = 1e300;
+  for (int r = 0; r <= reps && rc == CELESTE_OK; ++r) {
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(z, st);
+    if (e == hipSuccess) e = hipEventSynchronize(z);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, z);
+    if (e != hipSuccess) rc = fail(CELESTE_E_DEVICE, "autotune launch: %s", hipGetErrorString(e));
+    else if (r > 0) *best = std::min(*best, (double)ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  return rc;
+}
+
+int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int64_t sample_px,
+             const char* cache_path, celeste_tune_result* out) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  if (!theta) return fail(CELESTE_E_INVALID, "theta is NULL");
+  Packed P0;
+  CHK(validate_and_pack(ctx, b, &P0));
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const std::string key = tune_key(ctx, P0, b);
+  celeste_tune_result r{};
+  if (cache_path && tune_cache_read(cache_path, key, &r)) {
+    const int tl = log2_tile(r.tile_w), vl = log2_tile(r.value_tile_w);
+    if (tl < 0 || vl < 0 || (r.block != 128 && r.block != 256) || (r.value_block != 128 && r.value_block != 256) ||
+        r.variant < 0 || r.variant > 3 || r.chunk_px < 64 || r.chunk_px > (1 << 24))
+      return fail(CELESTE_E_INVALID, "autotune cache %s: bad entry for %s", cache_path, key.c_str());
+    ctx->chunk_px = r.chunk_px;
+    ctx->block = r.block;
+    ctx->variant = r.variant;
+    ctx->tile_log2 = tl;
+    ctx->vblock = r.value_block;
+    ctx->vtile_log2 = vl;
+    r.from_cache = 1;
+    if (out) *out = r;
+    return CELESTE_OK;
+  }
+  // theta on the host, for the sample
+  const int S = b->n_sources;
+  std::vector<double> th((size_t)S * NP);
+  if (b->mem_kind == CELESTE_MEM_HOST)
+    std::memcpy(th.data(), theta, sizeof(double) * th.size());
+  else {
+    HIPCHK(hipMemcpyAsync(th.data(), theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int s = 0; s < S; ++s) CHK(check_theta(th.data() + (size_t)s * NP, s));
+  // every k-th source, about sample_px pixels
+  if (sample_px <= 0) sample_px = 60000000;
+  int64_t total = 0;
+  for (int64_t i = 0; i < b->image_offsets[S]; ++i) total += (int64_t)b->images[i].h * b->images[i].w;
+  const int64_t stride = std::max<int64_t>(1, total / std::max<int64_t>(1, sample_px));
+  std::vector<int64_t> offs{0};
+  std::vector<celeste_image> imgs;
+  std::vector<double> ths;
+  for (int64_t s = 0; s < S; s += stride) {
+    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) {
+      imgs.push_back(b->images[i]);
+      r.sample_px += (int64_t)b->images[i].h * b->images[i].w;
+    }
+    offs.push_back((int64_t)imgs.size());
+    ths.insert(ths.end(), th.begin() + s * NP, th.begin() + (s + 1) * NP);
+  }
+  r.sample_sources = (int64_t)offs.size() - 1;
+  celeste_batch sub = *b;
+  sub.n_sources = (int32_t)r.sample_sources;
+  sub.image_offsets = offs.data();
+  sub.images = imgs.data();
+  CHK(ensure(ctx->theta, sizeof(double) * ths.size()));
+  HIPCHK(hipMemcpyAsync(ctx->theta.p, ths.data(), sizeof(double) * ths.size(), hipMemcpyHostToDevice, st));
+  const double* th_dev = as<double>(ctx->theta);
+
+  const int saved_chunk = ctx->chunk_px;
+  const int chunks[] = {2048, 4096, 8192, 16384};
+  const int variants[] = {2, 3};
+  double best = 1e300;
+  int rc = CELESTE_OK;
+  for (int chunk : chunks) {
+    ctx->chunk_px = chunk;
+    Packed P;
+    rc = validate_and_pack(ctx, &sub, &P);
+    if (rc == CELESTE_OK) rc = prepare(ctx, &sub, &P, st);
+    if (rc != CELESTE_OK) break;
+    const ImgDev* di = as<ImgDev>(ctx->imgs);
+    float* tables = as<float>(ctx->tables);
+    HIPCHK(launch_setup(di, P.n_img, th_dev, nullptr, P.prof, tables, P.tstride, st));
+    for (int block : {128, 256})
+      for (int variant : variants)
+        for (int tl = 3; tl <= 6 && rc == CELESTE_OK; ++tl) {
+          double ms = 0.0;
+          rc = time_min(st, 3, [&]() {
+            return launch_eval_full(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
+                                    P.prof.n_dev, nullptr, as<double>(ctx->partials), block, variant, tl, st);
+          }, &ms);
+          r.n_candidates += 1;
+          if (chunk == 4096 && block == 256 && variant == 3 && tl == 3) r.default_full_ms = ms;
+          if (rc == CELESTE_OK && ms < best) {
+            best = ms;
+            r.full_ms = ms;
+            r.chunk_px = chunk;
+            r.block = block;
+            r.variant = variant;
+            r.tile_w = 1 << tl;
+          }
+        }
+    if (rc != CELESTE_OK) break;
+  }
+  if (rc != CELESTE_OK) {
+    ctx->chunk_px = saved_chunk;
+    return rc;
+  }
+  // value kernel on the chosen work items
+  ctx->chunk_px = r.chunk_px;
+  {
+    Packed P;
+    CHK(validate_and_pack(ctx, &sub, &P));
+    CHK(prepare(ctx, &sub, &P, st));
+    const ImgDev* di = as<ImgDev>(ctx->imgs);
+    float* tables = as<float>(ctx->tables);
+    HIPCHK(launch_setup(di, P.n_img, th_dev, nullptr, P.prof, tables, P.tstride, st));
+    double vbest = 1e300;
+    for (int vblock : {128, 256})
+      for (int tl = 3; tl <= 6; ++tl) {
+        double ms = 0.0;
+        CHK(time_min(st, 3, [&]() {
+          return launch_eval_value(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
+                                   P.prof.n_dev, nullptr, as<double>(ctx->partials), vblock, r.variant, tl, st);
+        }, &ms));
+        r.n_candidates += 1;
+        if (vblock == 256 && tl == 3 && r.chunk_px == 4096) r.default_value_ms = ms;
+        if (ms < vbest) {
+          vbest = ms;
+          r.value_ms = ms;
+          r.value_block = vblock;
+          r.value_tile_w = 1 << tl;
+        }
+      }
+  }
+  if (r.chunk_px != 4096) {
+    // the default's value-kernel time on its own work items
+    ctx->chunk_px = 4096;
+    Packed P;
+    CHK(validate_and_pack(ctx, &sub, &P));
+    CHK(prepare(ctx, &sub, &P, st));
+    const ImgDev* di = as<ImgDev>(ctx->imgs);
+    float* tables = as<float>(ctx->tables);
+    HIPCHK(launch_setup(di, P.n_img, th_dev, nullptr, P.prof, tables, P.tstride, st));
+    CHK(time_min(st, 3, [&]() {
+      return launch_eval_value(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
+                               P.prof.n_dev, nullptr, as<double>(ctx->partials), 256, 3, 3, st);
+    }, &r.default_value_ms));
+  }
+  ctx->chunk_px = r.chunk_px;
+  ctx->block = r.block;
+  ctx->variant = r.variant;
+  ctx->tile_log2 = log2_tile(r.tile_w);
+  ctx->vblock = r.value_block;
+  ctx->vtile_log2 = log2_tile(r.value_tile_w);
+  if (cache_path) CHK(tune_cache_append(cache_path, key, r));
+  if (out) *out = r;
+  return CELESTE_OK;
+}
+
+}  // namespace
+
+extern "C" int celeste_autotune(celeste_ctx* ctx, const celeste_batch* batch, const double* theta, int64_t sample_px,
+                                const char* cache_path, celeste_tune_result* out) {
+  return autotune(ctx, batch, theta, sample_px, cache_path, out);
+}

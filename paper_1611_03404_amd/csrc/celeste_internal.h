@@ -92,12 +92,13 @@ hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, cons
                         ProfDev prof, float* tables, int tstride, hipStream_t st);
 hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStream_t st);
 hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st);
+// tw_log2: log2 of the pixel-tile width (3..6; tiles hold 64 pixels).
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                            int block, int variant, hipStream_t st);
+                            int block, int variant, int tw_log2, hipStream_t st);
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                              int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                             int block, hipStream_t st);
+                             int block, int variant, int tw_log2, hipStream_t st);
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                               double* elbo, double* grad, double* hess, unsigned long long* px_ctr,

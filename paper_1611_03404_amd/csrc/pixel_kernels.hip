@@ -151,7 +151,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
-                                                     double* __restrict__ partials) {
+                                                     int tw_log2, double* __restrict__ partials) {
   __shared__ double red[BLOCK / 64][80];
   const WorkItem wi = items[blockIdx.x];
   if (src_flag && !src_flag[wi.src]) return;
@@ -167,8 +167,10 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   const float io2 = io * io, io3 = io2 * io;
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tiles_x = (w + TILE - 1) / TILE;
-  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + TILE - 1) / TILE);
+  const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
+  const int tiles_x = (w + tw - 1) >> tw_log2;
+  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + th - 1) >> th_log2);
+  const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
   double val = 0.0;                 // ELBO value, per lane
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // wavefront sums of 5 derivative entries (quad-uniform)
   const int base5 = quad_base(lane);              // first of the 5 entries this lane's quad holds
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
 
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row = wi.row_begin + ty * TILE + (lane >> 3), col = tx * TILE + (lane & 7);
+    const int row = wi.row_begin + (ty << th_log2) + lrow, col = (tx << tw_log2) + lcol;
     const bool live = row < wi.row_end && col < w;
     const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
     const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
@@ -407,12 +409,13 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   }
 }
 
-template <int BLOCK>
+template <int BLOCK, int NE, int ND>
 __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict__ items,
                                                       const ImgDev* __restrict__ imgs,
-                                                      const float* __restrict__ tables, int tstride, int n_exp,
-                                                      int n_dev, const int* __restrict__ src_flag,
-                                                      double* __restrict__ partials) {
+                                                      const float* __restrict__ tables, int tstride, int n_exp_rt,
+                                                      int n_dev_rt, const int* __restrict__ src_flag,
+                                                      int tw_log2, double* __restrict__ partials) {
+  const int n_exp = NE > 0 ? NE : n_exp_rt, n_dev = NE > 0 ? ND : n_dev_rt;
   __shared__ double red[BLOCK / 64];
   const WorkItem wi = items[blockIdx.x];
   if (src_flag && !src_flag[wi.src]) return;
@@ -427,12 +430,14 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   const float ed = T[EDEV];
   const float cs = T[CS], cg = T[CG], Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tiles_x = (w + TILE - 1) / TILE;
-  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + TILE - 1) / TILE);
+  const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
+  const int tiles_x = (w + tw - 1) >> tw_log2;
+  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + th - 1) >> th_log2);
+  const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
   double acc = 0.0;
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row = wi.row_begin + ty * TILE + (lane >> 3), col = tx * TILE + (lane & 7);
+    const int row = wi.row_begin + (ty << th_log2) + lrow, col = (tx << tw_log2) + lcol;
     const bool live = row < wi.row_end && col < w;
     const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
     const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
@@ -446,8 +451,15 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
       const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
       Gs += gal_value(r, dxx, dxy, dyy);
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
-      for (int j = 0; j < n_exp; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
-      for (int j = n_exp; j < ncomp; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+      if constexpr (NE > 0) {
+#pragma unroll
+        for (int j = 0; j < NE; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+#pragma unroll
+        for (int j = NE; j < NE + ND; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+      } else {
+        for (int j = 0; j < n_exp; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+        for (int j = n_exp; j < ncomp; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+      }
     }
     const float Gg = fmaf(ed, gd - gx, gx);
     const float Tv = fmaf(cs, Gs, cg * Gg);
@@ -473,14 +485,14 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
-                            hipStream_t st) {
+                            int tw_log2, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
   const dim3 g(n_items);
 #define CELESTE_LAUNCH_FULL(B, W, E, D) \
   hipLaunchKernelGGL((k_eval_full<B, W, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, partials)
+                     src_flag, tw_log2, partials)
   if (block == 128) {
     if (unroll) {
       if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8); else CELESTE_LAUNCH_FULL(128, 1, 6, 8);
@@ -499,14 +511,20 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
 }
 
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
-                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, hipStream_t st) {
+                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
+                             int tw_log2, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (block == 128)
-    hipLaunchKernelGGL(k_eval_value<128>, dim3(n_items), dim3(128), 0, st, items, imgs, tables, tstride, n_exp,
-                       n_dev, src_flag, partials);
-  else
-    hipLaunchKernelGGL(k_eval_value<256>, dim3(n_items), dim3(256), 0, st, items, imgs, tables, tstride, n_exp,
-                       n_dev, src_flag, partials);
+  const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
+  const dim3 g(n_items);
+#define CELESTE_LAUNCH_VALUE(B, E, D) \
+  hipLaunchKernelGGL((k_eval_value<B, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
+                     src_flag, tw_log2, partials)
+  if (block == 128) {
+    if (unroll) CELESTE_LAUNCH_VALUE(128, 6, 8); else CELESTE_LAUNCH_VALUE(128, 0, 0);
+  } else {
+    if (unroll) CELESTE_LAUNCH_VALUE(256, 6, 8); else CELESTE_LAUNCH_VALUE(256, 0, 0);
+  }
+#undef CELESTE_LAUNCH_VALUE
   return hipGetLastError();
 }
 

@@ -223,3 +223,45 @@ def test_full_size_config2_sampled(cb, ctx):
         _say(tag, el[s], v0, deriv_err(g[s], g0), deriv_err(H[s], H0))
         assert_elbo_close(el[s], v0, what=tag)
         assert_derivs_close(g[s], H[s], g0, H0, what=tag)
+
+
+def test_tile_shapes_and_autotune(cb, ctx, tmp_path):
+    """Every tile width and launch shape gives the oracle's results; the autotuner picks one,
+    applies it, and reads it back from its cache file."""
+    full = synth.make_config(1, n_sources=12)
+    th = perturb_theta(full.theta_truth, 31)
+    b = cb.Batch.from_synth(full)
+    ref = [oracle_eval(full, s, th[s]) for s in (0, 7)]
+    try:
+        for tw in (8, 16, 32, 64):
+            ctx.set_option(cb.OPT_TILE_W, tw)
+            ctx.set_option(cb.OPT_VALUE_TILE_W, 64 // (tw // 8))
+            e, g, H = ctx.elbo_eval(b, th)
+            ev, _, _ = ctx.elbo_eval(b, th, want="value")
+            for k, s in enumerate((0, 7)):
+                assert_elbo_close(e[s], ref[k][0], what=f"tile {tw} source {s}")
+                assert_elbo_close(ev[s], ref[k][0], what=f"value tile {tw} source {s}")
+                assert_derivs_close(g[s], H[s], ref[k][1], ref[k][2], what=f"tile {tw} source {s}")
+        cache = str(tmp_path / "tune.txt")
+        r = ctx.autotune(b, th, sample_px=200000, cache_path=cache)
+        _say("autotune", r)
+        assert r["from_cache"] == 0 and r["n_candidates"] == 72 and r["sample_sources"] >= 1
+        assert r["tile_w"] in (8, 16, 32, 64) and r["value_tile_w"] in (8, 16, 32, 64)
+        assert r["block"] in (128, 256) and r["chunk_px"] in (2048, 4096, 8192, 16384)
+        assert 0 < r["full_ms"] <= r["default_full_ms"] and 0 < r["value_ms"]
+        e, g, H = ctx.elbo_eval(b, th)
+        for k, s in enumerate((0, 7)):
+            assert_elbo_close(e[s], ref[k][0], what=f"tuned source {s}")
+            assert_derivs_close(g[s], H[s], ref[k][1], ref[k][2], what=f"tuned source {s}")
+        r2 = ctx.autotune(b, th, cache_path=cache)
+        assert r2["from_cache"] == 1
+        assert all(r2[k] == r[k] for k in ("chunk_px", "block", "variant", "tile_w", "value_block", "value_tile_w"))
+        with open(cache, "a") as f:
+            key = open(cache).read().split()[0]
+            f.write(f"{key} 4096 100 3 8 256 8 1.0 1.0\n")
+        with pytest.raises(cb.CelesteError):
+            ctx.autotune(b, th, cache_path=cache)
+    finally:
+        for opt, v in ((cb.OPT_CHUNK_PX, 4096), (cb.OPT_BLOCK, 256), (cb.OPT_VARIANT, 3), (cb.OPT_TILE_W, 8),
+                       (cb.OPT_VALUE_BLOCK, 256), (cb.OPT_VALUE_TILE_W, 8)):
+            ctx.set_option(opt, v)
