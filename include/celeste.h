@@ -81,10 +81,11 @@ enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
   CELESTE_OPT_USE_GRAPH = 3,    /* batched fit replays a captured HIP graph per iteration (default 1) */
   CELESTE_OPT_PROFILE = 4,      /* 1: time every kernel phase with HIP events (fits run without a graph) */
-  CELESTE_OPT_VARIANT = 5,      /* pixel-kernel variant 0..3 (default 3): bit 0 = two resident waves per
+  CELESTE_OPT_VARIANT = 5,      /* pixel-kernel variant 0..7 (default 3): bit 0 = two resident waves per
                                    SIMD (value+gradient+Hessian kernel), bit 1 = loops unrolled for
-                                   6 exp + 8 dev components (both kernels); all variants compute the
-                                   same arithmetic */
+                                   6 exp + 8 dev components (both kernels), bit 2 (with bit 1) = the
+                                   J^T W J part of the Hessian summed on the matrix cores; all
+                                   variants compute the same arithmetic */
   CELESTE_OPT_TILE_W = 6,       /* width of the 64-pixel tile a wavefront of the value+gradient+Hessian
                                    kernel takes per step: 8, 16, 32 or 64 (default 8) */
   CELESTE_OPT_VALUE_BLOCK = 7,  /* threads per value-kernel block: 128 or 256 (default 256) */
@@ -318,14 +319,16 @@ typedef struct celeste_tune_result {
   int64_t sample_sources, sample_px;          /* tuning sample */
   double full_ms, value_ms;                   /* best time per launch over the sample */
   double default_full_ms, default_value_ms;   /* the default options' times on the same sample */
+  double vector_full_ms, matrix_full_ms;      /* best value+gradient+Hessian time with J^T W J on the
+                                                 vector units / on the matrix cores */
 } celeste_tune_result;
 
 /* Tile shapes and launch shapes of the pixel kernels, chosen by timing (the batching of
  * the per-source pixel sums of section III-B on this device).  Takes a deterministic
  * sample of the batch (every k-th source, about sample_px pixels; sample_px <= 0 means
  * 6e7), evaluates it at theta (n_sources x 27, batch memory) with the value+gradient+
- * Hessian kernel under every candidate work-item size (2048..16384 px), block size,
- * register budget and tile width, then with the value kernel under every block size and
+ * Hessian kernel under every candidate work-item size (4096..16384 px), block size,
+ * register budget, J^T W J unit (vector or matrix cores) and tile width, then with the value kernel under every block size and
  * tile width, keeps the fastest (minimum of three timed launches each, HIP events on the
  * library's stream) and sets them on the context.  cache_path (may be NULL) names a text
  * file of earlier choices, one per line, keyed by device, compute-unit count, component

@@ -65,7 +65,8 @@ class TuneResult(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("value_block", ctypes.c_int32), ("value_tile_w", ctypes.c_int32),
                 ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("sample_sources", ctypes.c_int64),
                 ("sample_px", ctypes.c_int64), ("full_ms", ctypes.c_double), ("value_ms", ctypes.c_double),
-                ("default_full_ms", ctypes.c_double), ("default_value_ms", ctypes.c_double)]
+                ("default_full_ms", ctypes.c_double), ("default_value_ms", ctypes.c_double),
+                ("vector_full_ms", ctypes.c_double), ("matrix_full_ms", ctypes.c_double)]
 
 
 class CFields(ctypes.Structure):

@@ -504,7 +504,7 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
       c->profile = value ? 1 : 0;
       return CELESTE_OK;
     case CELESTE_OPT_VARIANT:
-      if (value < 0 || value > 3) return fail(CELESTE_E_INVALID, "variant must be in 0..3");
+      if (value < 0 || value > 7) return fail(CELESTE_E_INVALID, "variant must be in 0..7");
       c->variant = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_TILE_W:
@@ -1200,7 +1200,7 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
   if (cache_path && tune_cache_read(cache_path, key, &r)) {
     const int tl = log2_tile(r.tile_w), vl = log2_tile(r.value_tile_w);
     if (tl < 0 || vl < 0 || (r.block != 128 && r.block != 256) || (r.value_block != 128 && r.value_block != 256) ||
-        r.variant < 0 || r.variant > 3 || r.chunk_px < 64 || r.chunk_px > (1 << 24))
+        r.variant < 0 || r.variant > 7 || r.chunk_px < 64 || r.chunk_px > (1 << 24))
       return fail(CELESTE_E_INVALID, "autotune cache %s: bad entry for %s", cache_path, key.c_str());
     ctx->chunk_px = r.chunk_px;
     ctx->block = r.block;
@@ -1248,8 +1248,8 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
   const double* th_dev = as<double>(ctx->theta);
 
   const int saved_chunk = ctx->chunk_px;
-  const int chunks[] = {2048, 4096, 8192, 16384};
-  const int variants[] = {2, 3};
+  const int chunks[] = {4096, 8192, 16384};
+  const int variants[] = {2, 3, 6, 7};
   double best = 1e300;
   int rc = CELESTE_OK;
   for (int chunk : chunks) {
@@ -1271,6 +1271,8 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
           }, &ms);
           r.n_candidates += 1;
           if (chunk == 4096 && block == 256 && variant == 3 && tl == 3) r.default_full_ms = ms;
+          double& unit_best = (variant & 4) ? r.matrix_full_ms : r.vector_full_ms;
+          if (rc == CELESTE_OK && (unit_best == 0.0 || ms < unit_best)) unit_best = ms;
           if (rc == CELESTE_OK && ms < best) {
             best = ms;
             r.full_ms = ms;

@@ -20,11 +20,13 @@
 // image evaluate a point far from every component with a zero count and zero
 // background variance, which makes every one of their terms exactly 0 as well.
 //
-// Accumulation: the ELBO value is accumulated per lane in FP64.  The 77 derivative
-// entries are summed per lane in FP32 over at most FLUSH tile steps, then summed across
-// the wavefront by a pairwise FP32 butterfly and added to FP64 accumulators; so every
-// FP64 addend is a sum of at most 64 * FLUSH pixel terms formed with at most
-// FLUSH - 1 + 6 FP32 roundings.
+// Accumulation: the ELBO value is accumulated per lane in FP64.  The gradient and the
+// Hessian in z (J^T W J + a second-order part per pixel, J = [dT; dU], 2 x 11) are summed
+// per lane in FP32 and every FLUSH tile steps go through a pairwise FP32 butterfly across
+// the wavefront into FP64 accumulators.  Variant MF instead sums J^T W J over the 64
+// pixels of a tile step (a contraction of depth 128) on the matrix cores: FP32 MFMA
+// 16x16x4 in two independent accumulator chains with operands staged through LDS, added
+// to FP64 every JFLUSH steps.
 #include "celeste_internal.h"
 
 namespace celeste {
@@ -37,7 +39,11 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 
 constexpr float E_ZERO = -160.f;   // exp2 below this is exactly 0 in FP32
 constexpr float FAR = 1.0e4f;      // offset used by lanes outside the image
-constexpr int FLUSH = 16;          // tile steps summed per lane in FP32 before a wavefront flush
+constexpr int FLUSH = 16;          // tile steps of lane sums in FP32 before a butterfly into FP64
+constexpr int JFLUSH = 8;          // tile steps of matrix-core sums in FP32 before FP64
+constexpr int JP = 68;             // LDS row pitch (floats) of the staged J^T W J operands
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // True if the predicate holds on some lane of the wavefront (a uniform branch condition).
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
@@ -146,15 +152,23 @@ __device__ __forceinline__ void wave_sum80f(const float* v, float* out5) {
 
 // NE, ND > 0: compile-time component counts (fully unrolled loops); 0: runtime counts.
 // MINW: minimum resident waves per SIMD the register allocation must allow.
-template <int BLOCK, int MINW, int NE, int ND>
+// MF: the J^T W J part on the matrix cores (true) or in the per-lane FP32 sums (false).
+template <int BLOCK, int MINW, int NE, int ND, bool MF>
 __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __restrict__ items,
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
                                                      int tw_log2, double* __restrict__ partials) {
   __shared__ double red[BLOCK / 64][80];
+  // per wavefront: [A rows (dT, dU) | B columns (hT, hU)][T or U part][z index][pixel]
+  __shared__ __align__(16) float jbuf[MF ? BLOCK / 64 : 1][2][2][MF ? NZ : 1][MF ? JP : 4];
+  __shared__ __align__(16) float zrow[64];   // operand row of zeros for the padding rows 11..15
   const WorkItem wi = items[blockIdx.x];
   if (src_flag && !src_flag[wi.src]) return;
+  if (MF) {
+    if (threadIdx.x < 64) zrow[threadIdx.x] = 0.f;
+    __syncthreads();
+  }
   const ImgDev& im = imgs[wi.img];
   const float* __restrict__ T = tables + (size_t)wi.img * tstride;
   const int w = im.w, pitch = im.pitch, npitch = im.nbr_pitch, npsf = im.n_psf;
@@ -178,6 +192,17 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
 #pragma unroll
   for (int i = 0; i < 80; ++i) accf[i] = 0.f;
   int since = 0;                    // tile steps since the last flush (wavefront-uniform)
+  // J^T W J: this lane holds entries (4 * (lane / 16) + r, lane % 16), r = 0..3, of the sum
+  const int mi = lane & 15, kq = lane >> 4;
+  const bool mrow = mi < NZ;
+  double accJ[4] = {0.0, 0.0, 0.0, 0.0};
+  floatx4 C0 = {0.f, 0.f, 0.f, 0.f}, C1 = {0.f, 0.f, 0.f, 0.f};   // two independent MFMA chains
+  auto flushJ = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) accJ[r] += (double)C0[r] + (double)C1[r];
+    C0 = floatx4{0.f, 0.f, 0.f, 0.f};
+    C1 = floatx4{0.f, 0.f, 0.f, 0.f};
+  };
   auto flush = [&]() {
     float part[5];
     wave_sum80f(accf, part);
@@ -370,7 +395,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       }
     }
 
-    // ---- value in FP64 per lane; gradient and Hessian in the per-lane FP32 sums
+    // ---- value in FP64 per lane; gradient and second-order part in the per-lane FP32 sums
     val += (double)lval;
     float hT[NZ], hU[NZ];
 #pragma unroll
@@ -379,16 +404,52 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
       hU[j] = wTU * Tz[j];
     }
+    if constexpr (!MF) {
 #pragma unroll
-    for (int i = 0; i < NZ; ++i) {
+      for (int i = 0; i < NZ; ++i) {
 #pragma unroll
-      for (int j = i; j < NZ; ++j) accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+        for (int j = i; j < NZ; ++j)
+          accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NZ * (NZ + 1) / 2; ++t) accf[NZ + t] += S[t];
+      // ---- J^T W J over the tile: C = sum_k A[:, k] B[k, :], k = 4 m + kq over (pixel, part)
+      float(*J)[2][MF ? NZ : 1][MF ? JP : 4] = jbuf[wv];
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) {
+        J[0][0][i][lane] = Tz[i];
+        J[0][1][i][lane] = Uz[i];
+        J[1][0][i][lane] = hT[i];
+        J[1][1][i][lane] = hU[i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // lane (mi, kq) feeds A[mi][4m + kq] and B[4m + kq][mi]: part kq & 1 of pixel 32 (kq >> 1) + m
+      const float* ar = mrow ? &J[0][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
+      const float* br = mrow ? &J[1][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float4 a = *reinterpret_cast<const float4*>(ar + 4 * q);
+        const float4 b = *reinterpret_cast<const float4*>(br + 4 * q);
+        C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, C0, 0, 0, 0);
+        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, C1, 0, 0, 0);
+        C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, C0, 0, 0, 0);
+        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, C1, 0, 0, 0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (++since == FLUSH) {
+    ++since;
+    if (MF && (since % JFLUSH) == 0) flushJ();
+    if (since == FLUSH) {
       flush();
       since = 0;
     }
   }
+  if (MF && (since % JFLUSH)) flushJ();
   if (since > 0) flush();
 
   // ---- block reduction (deterministic order) and one FP64 partial per work item
@@ -399,6 +460,17 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
 #pragma unroll
     for (int i = 0; i < 5; ++i)
       if (base5 + i < NACC - 1) red[wv][1 + base5 + i] = acc5[i];
+  }
+  if constexpr (MF) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // add the J^T W J sums (symmetric: the upper triangle is kept)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * kq + r;
+      if (mrow && i <= mi) red[wv][1 + NZ + tri(i, mi)] += accJ[r];
+    }
   }
   __syncthreads();
   if (threadIdx.x < NACC) {
@@ -489,21 +561,26 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
+  const bool mf = (variant & 4) != 0 && unroll;
   const dim3 g(n_items);
-#define CELESTE_LAUNCH_FULL(B, W, E, D) \
-  hipLaunchKernelGGL((k_eval_full<B, W, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
+#define CELESTE_LAUNCH_FULL(B, W, E, D, M) \
+  hipLaunchKernelGGL((k_eval_full<B, W, E, D, M>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
                      src_flag, tw_log2, partials)
   if (block == 128) {
-    if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8); else CELESTE_LAUNCH_FULL(128, 1, 6, 8);
+    if (mf) {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true);
+    } else if (unroll) {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false);
     } else {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0); else CELESTE_LAUNCH_FULL(128, 1, 0, 0);
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false);
     }
   } else {
-    if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8); else CELESTE_LAUNCH_FULL(256, 1, 6, 8);
+    if (mf) {
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, true);
+    } else if (unroll) {
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false);
     } else {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0); else CELESTE_LAUNCH_FULL(256, 1, 0, 0);
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false);
     }
   }
 #undef CELESTE_LAUNCH_FULL

@@ -233,21 +233,23 @@ def test_tile_shapes_and_autotune(cb, ctx, tmp_path):
     b = cb.Batch.from_synth(full)
     ref = [oracle_eval(full, s, th[s]) for s in (0, 7)]
     try:
-        for tw in (8, 16, 32, 64):
+        for tw, variant in ((8, 7), (8, 3), (16, 6), (32, 2), (64, 7)):
+            ctx.set_option(cb.OPT_VARIANT, variant)   # 6, 7: J^T W J on the matrix cores
             ctx.set_option(cb.OPT_TILE_W, tw)
             ctx.set_option(cb.OPT_VALUE_TILE_W, 64 // (tw // 8))
             e, g, H = ctx.elbo_eval(b, th)
             ev, _, _ = ctx.elbo_eval(b, th, want="value")
             for k, s in enumerate((0, 7)):
-                assert_elbo_close(e[s], ref[k][0], what=f"tile {tw} source {s}")
-                assert_elbo_close(ev[s], ref[k][0], what=f"value tile {tw} source {s}")
-                assert_derivs_close(g[s], H[s], ref[k][1], ref[k][2], what=f"tile {tw} source {s}")
+                what = f"tile {tw} variant {variant} source {s}"
+                assert_elbo_close(e[s], ref[k][0], what=what)
+                assert_elbo_close(ev[s], ref[k][0], what="value " + what)
+                assert_derivs_close(g[s], H[s], ref[k][1], ref[k][2], what=what)
         cache = str(tmp_path / "tune.txt")
         r = ctx.autotune(b, th, sample_px=200000, cache_path=cache)
         _say("autotune", r)
-        assert r["from_cache"] == 0 and r["n_candidates"] == 72 and r["sample_sources"] >= 1
+        assert r["from_cache"] == 0 and r["n_candidates"] == 104 and r["sample_sources"] >= 1
         assert r["tile_w"] in (8, 16, 32, 64) and r["value_tile_w"] in (8, 16, 32, 64)
-        assert r["block"] in (128, 256) and r["chunk_px"] in (2048, 4096, 8192, 16384)
+        assert r["block"] in (128, 256) and r["chunk_px"] in (4096, 8192, 16384) and r["variant"] in (2, 3, 6, 7)
         assert 0 < r["full_ms"] <= r["default_full_ms"] and 0 < r["value_ms"]
         e, g, H = ctx.elbo_eval(b, th)
         for k, s in enumerate((0, 7)):
