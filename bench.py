@@ -34,6 +34,30 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz, one FM
 PEAK_HBM_GBS = 8000.0
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_eval_full_batched_uneven_20k.json")
+
+
+def pmc_traffic(px_per_launch):
+    """HBM bytes per launch of the value+gradient+Hessian kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated, per pixel-eval), scaled to the launch's
+    pixel count; None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        d = json.load(open(PMC_SUMMARY))
+        src = open(os.path.join(ROOT, "paper_1611_03404_amd", "csrc", "pixel_kernels.hip"), "rb").read()
+    except OSError:
+        return None, None
+    if hashlib.sha256(src).hexdigest() != d["pixel_kernels_sha256"]:
+        return None, None
+    k = d["kernels"]["k_eval_full"]
+    per_px = (k["fetch_bytes"] + k["write_bytes"]) / d["n_pixels"]
+    sq = k["sq"]
+    util = sq["SQ_INSTS_VALU"] / (1024 * sq["GRBM_GUI_ACTIVE"] / 8 / 4)
+    return per_px * px_per_launch, {"bytes_per_pixel_eval": per_px, "valu_issue_utilisation": util,
+                                    "valu_insts_per_pixel_eval": sq["SQ_INSTS_VALU"] * 64 / d["n_pixels"],
+                                    "source": "profiles/pmc_eval_full_batched_uneven_20k.md"}
+
+
 def flop_full_per_px(K, E, D):
     """Algorithmic FLOPs of one value+gradient+Hessian pixel evaluation (add/mul 1, FMA 2,
     exp/log/rcp 1, FP64 accumulate 1), counted from the formulation: star components
@@ -211,6 +235,36 @@ def field_cpu_baseline(sb, theta, res, nbr, gpu_full_px_per_step, gpu_value_px_p
     }
 
 
+def probe(args, ctx, log):
+    """A short program for hardware-counter runs: the dominant kernels on the batched workload
+    (launch shapes from the autotuner, as in the benchmark) and a plain copy of known size
+    whose counters calibrate the byte counts."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1611_03404_amd import celeste as cb
+    sb = synth.make_config(2, n_sources=args.sources, device="cuda")
+    batch = cb.Batch.from_synth(sb)
+    theta0 = np.zeros((sb.n_sources, 27))
+    theta0[:, 0:2] = sb.u_cat
+    th, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+    tune = None if args.no_autotune else ctx.autotune(batch, th)
+    log(f"probe: {sb.n_sources} sources, {sb.n_pixels} px, autotune {tune}")
+    for _ in range(2):
+        ctx.elbo_eval(batch, th)
+    for _ in range(2):
+        ctx.elbo_eval(batch, th, want="value")
+    n = 1 << 28   # 1 GiB of float32
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": True, "n_pixels": sb.n_pixels, "n_images": sb.n_images, "copy_bytes": 4 * n,
+                      "autotune": tune}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,7 +279,13 @@ def main():
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps")
     ap.add_argument("--sweeps", type=int, default=3)
+    ap.add_argument("--schedule", choices=("jacobi", "colour"), default="jacobi",
+                    help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
+                         "sweeps over conflict-free colours")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter-collection target: two value+gradient+Hessian and two value evaluations of the "
+                         "batched workload at the plain start, then two 1 GiB device copies; no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported in this build "
@@ -244,6 +304,8 @@ def main():
         print("[bench]", *a, file=sys.stderr, flush=True)
 
     ctx = cb.Context(0)
+    if args.probe:
+        return probe(args, ctx, log)
     ctx.set_option(cb.OPT_PROFILE, 1)
     sur_info = None
     net = None
@@ -318,6 +380,7 @@ def main():
     full_s = st["ms_full"] / 1e3
     achieved = f_full * st["full_px"] / full_s / 1e12 if full_s > 0 else 0.0
     hbm_bytes = 4.0 * st["full_px"]
+    traffic, counters = pmc_traffic(st["full_px"] / max(1, st["full_launches"]))
     res = H["res"]
     iters = res["iters"]
     status_counts = {name: int(np.sum(res["status"] == code)) for name, code in
@@ -374,7 +437,8 @@ def main():
             "avg_launch_ms": st["ms_full"] / max(1, st["full_launches"]),
             "launches": st["full_launches"],
             "hbm_algorithmic_GBs": hbm_bytes / full_s / 1e9 if full_s > 0 else None,
-            "traffic": None,
+            "traffic": traffic,
+            "counters": counters,
         },
     }
     if "plain" in runs and net is not None:
@@ -419,7 +483,7 @@ def field_bench(args, ctx, net, sur_info, log):
         del b0
     for w in range(args.warmup):
         t = time.perf_counter()
-        field.bca(ctx, sb, meta, sweeps=1, start_mode=mode)
+        field.bca(ctx, sb, meta, sweeps=1, start_mode=mode, schedule=args.schedule)
         log(f"warmup {w}: {time.perf_counter() - t:.2f} s")
     ctx.stats(reset=True)
     torch.cuda.synchronize()
@@ -427,7 +491,8 @@ def field_bench(args, ctx, net, sur_info, log):
     conv = 0
     info = res = None
     for k in range(args.steps):
-        theta, res, info = field.bca(ctx, sb, meta, sweeps=args.sweeps, start_mode=mode, log=log)
+        theta, res, info = field.bca(ctx, sb, meta, sweeps=args.sweeps, start_mode=mode, log=log,
+                                     schedule=args.schedule, field_pixels=sf.fields, field_sky=sf.field_sky)
         conv += int(np.sum(res["status"] == cb.CONVERGED))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -443,9 +508,11 @@ def field_bench(args, ctx, net, sur_info, log):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve, bf16 network", "data": "synthetic",
         "config": {"workload": f"crowded field {sf.W}x{sf.H} px, {sf.n_fields} images (5 bands x 4 epochs), "
-                               f"{sb.n_sources} sources, {args.sweeps} Jacobi sweeps",
+                               f"{sb.n_sources} sources, {args.sweeps} "
+                               f"{'Jacobi' if args.schedule == 'jacobi' else 'colour (Gauss-Seidel)'} sweeps",
                    "n_patch_pixels": sb.n_pixels, "start": "surrogate" if net is not None else "plain"},
         "converged_last_sweep": int(np.sum(res["status"] == cb.CONVERGED)),
+        "schedule": args.schedule, "start_joint_elbo": info["start_joint_elbo"],
         "autotune": tune,
         "sweeps": info["history"], "timings_s_per_step": {k: v / args.steps for k, v in info["timings"].items()},
         "pixel_evals_per_s": st["full_px"] / wall,
@@ -454,7 +521,7 @@ def field_bench(args, ctx, net, sur_info, log):
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                      "avg_launch_ms": st["ms_full"] / max(1, st["full_launches"]), "launches": st["full_launches"],
-                     "traffic": None},
+                     "traffic": None},   # counters were taken on the batched workload only
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) and ELBO check on a 1% sample ...")

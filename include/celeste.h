@@ -302,6 +302,32 @@ int celeste_neighbour_arrays(celeste_ctx* ctx, const celeste_batch* batch, const
                              const celeste_fields* fields, const int64_t* nbr_off, float* nbr_mean,
                              float* nbr_var);
 
+/* Colours for Gauss-Seidel block sweeps over a crowded field (host only, no device work).
+ * Section III-B optimises one source with the others held fixed; sources that share no pixel
+ * can take that step at the same time and the result is a block coordinate step on the joint
+ * ELBO.  Sources whose bounding boxes (union of their images' rectangles [origin, origin +
+ * (w, h)) in image-frame coordinates) intersect get different colours, so no two sources of
+ * one colour touch a common pixel of any field image.  Greedy in source order, smallest free
+ * colour.  colour: host, n_sources (out); n_colours: host (out).  Errors: E_INVALID. */
+int celeste_colour_sources(const celeste_batch* batch, int32_t* colour, int32_t* n_colours);
+
+/* Moves rendered fields (celeste_render_fields) of the batch's sources from theta_old to
+ * theta_new (device, n_sources x 27 each): every pixel of every patch gets the difference of
+ * its source's two contributions, clamped at 0.  The batch's patches must not overlap within a
+ * field (one colour of celeste_colour_sources; checked, E_INVALID otherwise), so each field
+ * pixel has one writer and the update is deterministic. */
+int celeste_update_fields(celeste_ctx* ctx, const celeste_batch* batch, const double* theta_old,
+                          const double* theta_new, const celeste_fields* fields);
+
+/* Joint ELBO of a crowded field (the objective that section III-B's per-source steps
+ * increase): the delta-method expected log-likelihood of every pixel of every field image, with
+ * E = sky + fields->mean and Var = fields->var (rendered at theta), plus the prior terms (minus
+ * KL) of all sources at theta (device, n_sources x 27).  field_pixels: device counts, n_fields x
+ * height x width; field_sky: host, n_fields, > 0.  elbo_out: host.  FP64, fixed summation order. */
+int celeste_field_elbo(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                       const celeste_fields* fields, const float* field_pixels, const double* field_sky,
+                       double* elbo_out);
+
 /* The start a fit with these options would use (plain or surrogate-with-fallback, clipped
  * into the boxes), without fitting; elbo_out (n_sources, batch memory, may be NULL) gets its
  * ELBO.  opts->max_iter is ignored. */

@@ -122,11 +122,15 @@ def load():
     lib.celeste_start.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_psi_to_theta.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     lib.celeste_autotune.argtypes = [vp, ctypes.POINTER(CBatch), vp, i64, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+    lib.celeste_colour_sources.argtypes = [ctypes.POINTER(CBatch), vp, vp]
+    lib.celeste_update_fields.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, ctypes.POINTER(CFields)]
+    lib.celeste_field_elbo.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields), vp, vp, vp]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
                  "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
                  "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
                  "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta",
-                 "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start", "celeste_autotune"):
+                 "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start", "celeste_autotune",
+                 "celeste_colour_sources", "celeste_update_fields", "celeste_field_elbo"):
         getattr(lib, name).restype = ctypes.c_int
     sizes = [lib.celeste_struct_size(k) for k in range(8)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
@@ -140,6 +144,14 @@ def load():
 def _check(code):
     if code != OK:
         raise CelesteError(code, load().celeste_last_error().decode())
+
+
+def colour_sources(batch: Batch):
+    """Conflict-free colours (celeste_colour_sources): returns (colour per source, number of colours)."""
+    col = np.zeros(batch.n_sources, dtype=np.int32)
+    n = ctypes.c_int32()
+    _check(load().celeste_colour_sources(ctypes.byref(batch.c), col.ctypes.data, ctypes.byref(n)))
+    return col, n.value
 
 
 def default_opts(**kw):
@@ -230,6 +242,39 @@ class Batch:
         return cls(sb.src_img_off, sb.img_band, sb.img_h, sb.img_w, sb.img_pitch, sb.img_origin, sb.img_wcs,
                    sb.img_sky, sb.img_calib, sb.img_psf, sb.img_npsf, sb.pixels, sb.img_pix_off, sb.prior,
                    sb.profiles, **kw)
+
+    def subset(self, idx):
+        """A batch of the sources idx (in that order) sharing this batch's pixel memory, and
+        the indices of their images in this batch."""
+        idx = np.asarray(idx, dtype=np.int64)
+        counts = self.offsets[idx + 1] - self.offsets[idx]
+        img_idx = (np.repeat(self.offsets[idx] - np.concatenate([[0], np.cumsum(counts)[:-1]]), counts)
+                   + np.arange(int(counts.sum())))
+        b = Batch.__new__(Batch)
+        b.device, b.torch_device, b._keep = self.device, self.torch_device, list(self._keep)
+        b.images = np.ascontiguousarray(self.images[img_idx])
+        b.prior, b.profiles = self.prior, self.profiles
+        b.offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        b.n_sources = len(idx)
+        b.c = CBatch(b.n_sources, self.c.mem_kind, b.offsets.ctypes.data, b.images.ctypes.data,
+                     b.prior.ctypes.data, b.profiles.ctypes.data)
+        return b, img_idx
+
+    def with_nbr(self, nbr_mean, nbr_var, nbr_off):
+        """This batch with per-image neighbour arrays at element offsets nbr_off (one per image,
+        rows of w elements) of nbr_mean / nbr_var."""
+        b = Batch.__new__(Batch)
+        b.device, b.torch_device = self.device, self.torch_device
+        b._keep = list(self._keep) + [nbr_mean, nbr_var]
+        b.images = self.images.copy()
+        off = np.asarray(nbr_off, dtype=np.uint64)
+        b.images["nbr_mean"] = _ptr(nbr_mean) + 4 * off
+        b.images["nbr_var"] = _ptr(nbr_var) + 4 * off
+        b.images["nbr_pitch"] = b.images["w"]
+        b.prior, b.profiles, b.offsets, b.n_sources = self.prior, self.profiles, self.offsets, self.n_sources
+        b.c = CBatch(b.n_sources, self.c.mem_kind, b.offsets.ctypes.data, b.images.ctypes.data,
+                     b.prior.ctypes.data, b.profiles.ctypes.data)
+        return b
 
     def array(self, shape):
         """An output array of the batch's memory kind."""
@@ -364,6 +409,24 @@ class Context:
         self._stream(batch)
         _check(load().celeste_neighbour_arrays(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(f),
                                                off.ctypes.data, _ptr(nbr_mean), _ptr(nbr_var)))
+
+    def update_fields(self, batch: Batch, theta_old, theta_new, img_field, n_fields, height, width, fields):
+        """Move the rendered fields of the batch's sources (one colour) from theta_old to theta_new."""
+        to, tn = batch.as_input(theta_old), batch.as_input(theta_new)
+        f, keep = self._fields(img_field, n_fields, height, width, fields)
+        self._stream(batch)
+        _check(load().celeste_update_fields(self._h, ctypes.byref(batch.c), _ptr(to), _ptr(tn), ctypes.byref(f)))
+
+    def field_elbo(self, batch: Batch, theta, img_field, n_fields, height, width, fields, field_pixels, field_sky):
+        """Joint ELBO of the field at theta (fields rendered at theta)."""
+        th = batch.as_input(theta)
+        f, keep = self._fields(img_field, n_fields, height, width, fields)
+        sky = np.ascontiguousarray(field_sky, dtype=np.float64)
+        out = ctypes.c_double()
+        self._stream(batch)
+        _check(load().celeste_field_elbo(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(f),
+                                         _ptr(field_pixels), sky.ctypes.data, ctypes.byref(out)))
+        return out.value
 
     @staticmethod
     def _fields(img_field, n_fields, height, width, arrays):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "celeste_internal.h"
@@ -78,6 +79,7 @@ struct celeste_ctx {
   celeste_net* net = nullptr;   // surrogate network (not owned)
   DevBuf sur;                   // surrogate predictions (float, S x 27)
   DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
+  DevBuf tables2, fsky;                            // second setup table (field updates), field skies
 };
 
 namespace celeste {
@@ -993,6 +995,66 @@ int celeste_psi_to_theta(const double* psi, const double* u0, int64_t n, double 
 
 namespace {
 
+// Bounding boxes [x0, x1) x [y0, y1) of each source's patches (union over its images, in
+// image-frame coordinates), for the colouring.
+struct Box {
+  int64_t x0, x1, y0, y1;
+};
+constexpr int64_t CELL = 128;   // grid cell of the colouring (>= the usual patch side)
+
+bool overlap(const Box& a, const Box& b) { return a.x0 < b.x1 && b.x0 < a.x1 && a.y0 < b.y1 && b.y0 < a.y1; }
+
+int64_t cell_key(int64_t cx, int64_t cy) { return (cx << 32) ^ (cy & 0xffffffffLL); }
+
+int source_boxes(const celeste_batch* b, std::vector<Box>* out) {
+  const int S = b->n_sources;
+  if (b->image_offsets[0] != 0) return fail(CELESTE_E_INVALID, "image_offsets[0] must be 0");
+  out->resize(S);
+  for (int s = 0; s < S; ++s) {
+    if (b->image_offsets[s + 1] <= b->image_offsets[s]) return fail(CELESTE_E_INVALID, "source %d has no images", s);
+    Box bx{INT64_MAX, INT64_MIN, INT64_MAX, INT64_MIN};
+    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) {
+      const celeste_image& im = b->images[i];
+      const double ox = im.origin[0], oy = im.origin[1];
+      if (!std::isfinite(ox) || !std::isfinite(oy) || std::fabs(ox) > 1e9 || std::fabs(oy) > 1e9 || im.h < 1 ||
+          im.w < 1)
+        return fail(CELESTE_E_INVALID, "image %lld: bad origin or shape", (long long)i);
+      // non-negative cell coordinates: shift by 2^31 before the grid division
+      const int64_t x0 = (int64_t)std::floor(ox) + ((int64_t)1 << 31), y0 = (int64_t)std::floor(oy) + ((int64_t)1 << 31);
+      bx.x0 = std::min(bx.x0, x0);
+      bx.y0 = std::min(bx.y0, y0);
+      bx.x1 = std::max(bx.x1, x0 + im.w + (ox != std::floor(ox) ? 1 : 0));
+      bx.y1 = std::max(bx.y1, y0 + im.h + (oy != std::floor(oy) ? 1 : 0));
+    }
+    (*out)[s] = bx;
+  }
+  return CELESTE_OK;
+}
+
+// No two images of the batch on the same field may overlap (single writer per field pixel).
+int check_disjoint(const celeste_batch* b, const celeste_fields* f) {
+  const int64_t n = b->image_offsets[b->n_sources];
+  std::unordered_map<int64_t, std::vector<int64_t>> grid;
+  for (int64_t i = 0; i < n; ++i) {
+    const celeste_image& a = b->images[i];
+    const int64_t ax = (int64_t)a.origin[0], ay = (int64_t)a.origin[1];
+    const int64_t fkey = (int64_t)f->img_field[i] << 40;
+    for (int64_t cy = ay / CELL; cy <= (ay + a.h - 1) / CELL; ++cy)
+      for (int64_t cx = ax / CELL; cx <= (ax + a.w - 1) / CELL; ++cx) {
+        auto& v = grid[fkey ^ (cx << 20) ^ cy];
+        for (int64_t j : v) {
+          const celeste_image& c = b->images[j];
+          const int64_t bx = (int64_t)c.origin[0], by = (int64_t)c.origin[1];
+          if (f->img_field[j] == f->img_field[i] && ax < bx + c.w && bx < ax + a.w && ay < by + c.h && by < ay + a.h)
+            return fail(CELESTE_E_INVALID, "images %lld and %lld overlap in field %d", (long long)j, (long long)i,
+                        f->img_field[i]);
+        }
+        v.push_back(i);
+      }
+  }
+  return CELESTE_OK;
+}
+
 int check_fields(const celeste_batch* b, const Packed& P, const celeste_fields* f) {
   if (!f || !f->img_field || !f->mean || !f->var) return fail(CELESTE_E_INVALID, "fields and its arrays must not be NULL");
   if (b->mem_kind != CELESTE_MEM_DEVICE) return fail(CELESTE_E_INVALID, "crowded fields need CELESTE_MEM_DEVICE");
@@ -1095,6 +1157,102 @@ int celeste_neighbour_arrays(celeste_ctx* ctx, const celeste_batch* b, const dou
                            P.prof.n_dev, f->height, f->width, f->mean, f->var, as<long long>(ctx->nbr_off), nbr_mean,
                            nbr_var, st));
   HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+int celeste_colour_sources(const celeste_batch* b, int32_t* colour, int32_t* n_colours) {
+  if (!b || !b->image_offsets || !b->images) return fail(CELESTE_E_INVALID, "batch is NULL or incomplete");
+  if (!colour || !n_colours) return fail(CELESTE_E_INVALID, "colour and n_colours must not be NULL");
+  if (b->n_sources < 1) return fail(CELESTE_E_INVALID, "n_sources must be >= 1");
+  std::vector<Box> box;
+  CHK(source_boxes(b, &box));
+  const int S = b->n_sources;
+  std::unordered_map<int64_t, std::vector<int>> grid;
+  std::vector<int> stamp;   // stamp[c] == s: colour c is taken by a neighbour of s
+  int nc = 0;
+  for (int s = 0; s < S; ++s) {
+    const Box& a = box[s];
+    for (int64_t cy = a.y0 / CELL; cy <= (a.y1 - 1) / CELL; ++cy)
+      for (int64_t cx = a.x0 / CELL; cx <= (a.x1 - 1) / CELL; ++cx) {
+        auto it = grid.find(cell_key(cx, cy));
+        if (it == grid.end()) continue;
+        for (int t : it->second)
+          if (overlap(a, box[t])) stamp[colour[t]] = s;
+      }
+    int c = 0;
+    while (c < nc && stamp[c] == s) ++c;
+    if (c == nc) {
+      ++nc;
+      stamp.push_back(-1);
+    }
+    colour[s] = c;
+    for (int64_t cy = a.y0 / CELL; cy <= (a.y1 - 1) / CELL; ++cy)
+      for (int64_t cx = a.x0 / CELL; cx <= (a.x1 - 1) / CELL; ++cx) grid[cell_key(cx, cy)].push_back(s);
+  }
+  *n_colours = nc;
+  return CELESTE_OK;
+}
+
+int celeste_update_fields(celeste_ctx* ctx, const celeste_batch* b, const double* theta_old, const double* theta_new,
+                          const celeste_fields* f) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_fields(b, P, f));
+  CHK(check_disjoint(b, f));
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const double *th_old = nullptr, *th_new = nullptr;
+  CHK(upload_theta(ctx, b, P, theta_old, &th_old, st));
+  CHK(upload_theta(ctx, b, P, theta_new, &th_new, st));
+  CHK(prepare(ctx, b, &P, st, false));
+  CHK(ensure(ctx->tables2, sizeof(float) * (size_t)P.tstride * P.n_img));
+  CHK(ensure(ctx->img_field, sizeof(int) * P.n_img));
+  HIPCHK(hipMemcpyAsync(ctx->img_field.p, f->img_field, sizeof(int) * P.n_img, hipMemcpyHostToDevice, st));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  HIPCHK(launch_setup(imgs, P.n_img, th_old, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  HIPCHK(launch_setup(imgs, P.n_img, th_new, nullptr, P.prof, as<float>(ctx->tables2), P.tstride, st));
+  HIPCHK(launch_update_fields(imgs, P.n_img, as<int>(ctx->img_field), as<float>(ctx->tables),
+                              as<float>(ctx->tables2), P.tstride, P.prof.n_exp, P.prof.n_dev, f->height, f->width,
+                              f->mean, f->var, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CELESTE_OK;
+}
+
+int celeste_field_elbo(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const celeste_fields* f,
+                       const float* field_pixels, const double* field_sky, double* elbo_out) {
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_fields(b, P, f));
+  if (!field_pixels || !field_sky || !elbo_out)
+    return fail(CELESTE_E_INVALID, "field_pixels, field_sky and elbo_out must not be NULL");
+  for (int k = 0; k < f->n_fields; ++k)
+    if (!(field_sky[k] > 0.0) || !std::isfinite(field_sky[k]))
+      return fail(CELESTE_E_INVALID, "field %d: sky must be finite and > 0", k);
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = ctx->stream;
+  const double* th = nullptr;
+  CHK(upload_theta(ctx, b, P, theta, &th, st));
+  const int S = P.n_src;
+  const int64_t n = (int64_t)f->n_fields * f->height * f->width;
+  const int per_block = 8192;
+  const int64_t nb64 = (n + per_block - 1) / per_block;
+  if (nb64 > INT32_MAX / 2) return fail(CELESTE_E_INVALID, "fields too large");
+  const int nb = (int)nb64;
+  CHK(ensure(ctx->fsky, sizeof(double) * f->n_fields));
+  CHK(ensure(ctx->o_elbo, sizeof(double) * S));
+  CHK(ensure(ctx->partials, sizeof(double) * (size_t)nb));
+  HIPCHK(hipMemcpyAsync(ctx->fsky.p, field_sky, sizeof(double) * f->n_fields, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_prior_term(th, S, P.prior, as<double>(ctx->o_elbo), st));
+  HIPCHK(launch_field_terms(field_pixels, f->mean, f->var, as<double>(ctx->fsky), f->height, f->width, f->n_fields,
+                            per_block, nb, as<double>(ctx->partials), st));
+  std::vector<double> pri(S), part(nb);
+  HIPCHK(hipMemcpyAsync(pri.data(), ctx->o_elbo.p, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(part.data(), ctx->partials.p, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double tot = 0.0;
+  for (double v : part) tot += v;
+  for (double v : pri) tot += v;
+  *elbo_out = tot;
   return CELESTE_OK;
 }
 

@@ -114,6 +114,13 @@ hipError_t launch_neighbours(const ImgDev* imgs, int n_img, const int* img_field
                              int n_exp, int n_dev, int H, int W, const float* mean, const float* var,
                              const long long* nbr_off, float* nbr_mean, float* nbr_var, hipStream_t st);
 
+hipError_t launch_update_fields(const ImgDev* imgs, int n_img, const int* img_field, const float* t_old,
+                                const float* t_new, int tstride, int n_exp, int n_dev, int H, int W, float* mean,
+                                float* var, hipStream_t st);
+hipError_t launch_field_terms(const float* x, const float* mean, const float* var, const double* sky, int H, int W,
+                              int n_fields, int per_block, int n_blocks, double* partials, hipStream_t st);
+hipError_t launch_prior_term(const double* theta, int n_src, PriorDev prior, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- trust-region state
 struct FitDev {
   double* theta;        // S x 27 current (natural)

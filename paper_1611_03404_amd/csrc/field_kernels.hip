@@ -115,7 +115,69 @@ __global__ __launch_bounds__(256) void k_neighbours(const ImgDev* __restrict__ i
   }
 }
 
+// Moves the field images from one estimate of the batch's sources to another: each pixel of
+// each patch gets (new - old) contribution of its source.  Patches of one launch must not
+// overlap within a field, so every pixel has a single writer.
+__global__ __launch_bounds__(256) void k_update(const ImgDev* __restrict__ imgs, const int* __restrict__ img_field,
+                                                const float* __restrict__ t_old, const float* __restrict__ t_new,
+                                                int tstride, int n_exp, int n_dev, int H, int W,
+                                                float* __restrict__ mean, float* __restrict__ var) {
+  const int i = blockIdx.x;
+  const ImgDev& im = imgs[i];
+  const float* __restrict__ To = t_old + (size_t)i * tstride;
+  const float* __restrict__ Tn = t_new + (size_t)i * tstride;
+  const int c0 = (int)im.origin[0], r0 = (int)im.origin[1];
+  const int f = img_field[i];
+  const int n = im.h * im.w;
+  for (int m = threadIdx.x; m < n; m += 256) {
+    const int r = m / im.w, c = m - r * im.w;
+    float eo, vo, en, vn;
+    source_rate(To, (float)c - To[PSX], (float)r - To[PSY], im.n_psf, n_exp, n_exp + n_dev, &eo, &vo);
+    source_rate(Tn, (float)c - Tn[PSX], (float)r - Tn[PSY], im.n_psf, n_exp, n_exp + n_dev, &en, &vn);
+    const size_t o = ((size_t)f * H + (r0 + r)) * W + (c0 + c);
+    mean[o] = fmaxf(mean[o] + (en - eo), 0.f);
+    var[o] = fmaxf(var[o] + (vn - vo), 0.f);
+  }
+}
+
+// Delta-method expected log-likelihood of every field pixel in FP64 (E = sky + mean,
+// Var = var), one partial sum per block.
+__global__ __launch_bounds__(256) void k_field_terms(const float* __restrict__ x, const float* __restrict__ mean,
+                                                     const float* __restrict__ var,
+                                                     const double* __restrict__ sky, int H, int W, int n_fields,
+                                                     int per_block, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const size_t npf = (size_t)H * W, n = npf * n_fields;
+  const size_t b0 = (size_t)blockIdx.x * per_block;
+  double acc = 0.0;
+  for (size_t k = b0 + threadIdx.x; k < b0 + per_block && k < n; k += 256) {
+    const double xv = x[k], E = sky[k / npf] + (double)mean[k], V = var[k];
+    acc += xv * (log(E) - V / (2.0 * E * E)) - E - lgamma(xv + 1.0);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 }  // namespace
+
+hipError_t launch_update_fields(const ImgDev* imgs, int n_img, const int* img_field, const float* t_old,
+                                const float* t_new, int tstride, int n_exp, int n_dev, int H, int W, float* mean,
+                                float* var, hipStream_t st) {
+  if (n_img <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update, dim3(n_img), dim3(256), 0, st, imgs, img_field, t_old, t_new, tstride, n_exp, n_dev, H,
+                     W, mean, var);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_terms(const float* x, const float* mean, const float* var, const double* sky, int H, int W,
+                              int n_fields, int per_block, int n_blocks, double* partials, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_field_terms, dim3(n_blocks), dim3(256), 0, st, x, mean, var, sky, H, W, n_fields, per_block,
+                     partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_render(const int* tile_off, const int* tile_img, int n_tiles, const ImgDev* imgs,
                          const float* tables, int tstride, int n_exp, int n_dev, int H, int W, int tiles_x,

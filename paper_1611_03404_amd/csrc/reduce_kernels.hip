@@ -205,7 +205,23 @@ __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict_
   if (px_ctr) atomicAdd(px_ctr, (unsigned long long)sr.npix);
 }
 
+// Prior part of the ELBO (minus the KL terms) per source.
+__global__ __launch_bounds__(64) void k_prior_term(const double* __restrict__ theta, int n_src, PriorDev prior,
+                                                   double* __restrict__ out) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= n_src) return;
+  KL k;
+  kl_value_grad(theta + (size_t)s * NP, prior, k);
+  out[s] = k.val;
+}
+
 }  // namespace
+
+hipError_t launch_prior_term(const double* theta, int n_src, PriorDev prior, double* out, hipStream_t st) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prior_term, dim3((n_src + 63) / 64), dim3(64), 0, st, theta, n_src, prior, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
