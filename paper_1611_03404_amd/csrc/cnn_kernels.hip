@@ -295,6 +295,38 @@ __global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dz,
   if (threadIdx.x == 0) db[c] = sh[0];
 }
 
+// Conv-layer bias gradient in two fixed-order passes: block (c, q) sums the q-th of BP_PARTS
+// slices of channel c over images and positions; then one thread per channel sums its slices.
+constexpr int BP_PARTS = 64;
+
+__global__ __launch_bounds__(256) void k_bias_part(const float* __restrict__ dz, int B, int Cch, int HW,
+                                                   float* __restrict__ part) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x, q = blockIdx.y;
+  const int n = B * HW, per = (n + BP_PARTS - 1) / BP_PARTS;
+  const int i0 = q * per, i1 = min(n, i0 + per);
+  float s = 0.f;
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    const int img = i / HW, p = i - img * HW;
+    s += dz[((size_t)img * Cch + c) * HW + p];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[c * BP_PARTS + q] = sh[0];
+}
+
+__global__ __launch_bounds__(128) void k_bias_fin(const float* __restrict__ part, int Cch, float* __restrict__ db) {
+  const int c = blockIdx.x * 128 + threadIdx.x;
+  if (c >= Cch) return;
+  float s = 0.f;
+  for (int q = 0; q < BP_PARTS; ++q) s += part[c * BP_PARTS + q];
+  db[c] = s;
+}
+
 // MSE loss over the batch: dy = 2 (y - t) / (B*27); loss written by one block
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t, int n,
                                              float* __restrict__ dy, bf16* __restrict__ dyb,
@@ -445,6 +477,7 @@ struct NetState {
   // activations (BF16) and gradients for cap_batch images
   bf16 *x = nullptr, *r[4] = {}, *p[4] = {}, *h = nullptr, *dyb = nullptr, *dzb = nullptr, *dhb = nullptr;
   float *y = nullptr, *t = nullptr, *dy = nullptr, *dz = nullptr, *dh = nullptr, *C = nullptr, *loss = nullptr;
+  float* bpart = nullptr;   // conv bias-gradient slices (128 channels x BP_PARTS)
   size_t c_cap = 0;
 };
 
@@ -458,6 +491,7 @@ hipError_t net_alloc(NetState* n) {
   if ((e = hipMalloc(&n->wb, P * 2)) != hipSuccess) return e;
   if ((e = hipMemset(n->m, 0, P * 4)) != hipSuccess) return e;
   if ((e = hipMemset(n->v, 0, P * 4)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->bpart, sizeof(float) * 128 * BP_PARTS)) != hipSuccess) return e;
   return hipMalloc(&n->loss, 16);
 }
 
@@ -477,7 +511,7 @@ void net_free_work(NetState* n) {
 
 void net_free(NetState* n) {
   net_free_work(n);
-  float* ff[] = {n->w, n->m, n->v, n->g, n->loss};
+  float* ff[] = {n->w, n->m, n->v, n->g, n->loss, n->bpart};
   for (float* q : ff)
     if (q) (void)hipFree(q);
   if (n->wb) (void)hipFree(n->wb);
@@ -606,7 +640,9 @@ hipError_t net_backward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
       LdConvWgrad ld{n->dzb, xin, L.cin[l], L.cout[l], L.hw[l], L.hw[l]};
       if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_ep_sum, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, (int)(M * N), n->g + L.off[2 * l]);
-      hipLaunchKernelGGL(k_bias_grad, dim3(L.cout[l]), dim3(256), 0, st, n->dz, B, L.cout[l], HW,
+      hipLaunchKernelGGL(k_bias_part, dim3(L.cout[l], BP_PARTS), dim3(256), 0, st, n->dz, B, L.cout[l], HW,
+                         n->bpart);
+      hipLaunchKernelGGL(k_bias_fin, dim3((L.cout[l] + 127) / 128), dim3(128), 0, st, n->bpart, L.cout[l],
                          n->g + L.off[2 * l + 1]);
     }
     if (l == 0) break;
