@@ -279,7 +279,7 @@ def main():
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps")
     ap.add_argument("--sweeps", type=int, default=3)
-    ap.add_argument("--schedule", choices=("jacobi", "colour"), default="jacobi",
+    ap.add_argument("--schedule", choices=("jacobi", "colour"), default="colour",
                     help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
                          "sweeps over conflict-free colours")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")

@@ -22,7 +22,7 @@ import numpy as np
 from . import celeste as cb
 
 
-def bca(ctx, batch_arrays, fields_meta, sweeps=3, start_mode=cb.INIT_SURROGATE, log=None, schedule="jacobi",
+def bca(ctx, batch_arrays, fields_meta, sweeps=3, start_mode=cb.INIT_SURROGATE, log=None, schedule="colour",
         field_pixels=None, field_sky=None):
     """batch_arrays: object with the SoA fields of Batch.from_synth (device pixels);
     fields_meta: (img_field, n_fields, height, width).  With field_pixels (device, the field

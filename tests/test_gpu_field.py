@@ -101,7 +101,7 @@ def test_block_coordinate_ascent(env):
     cb, ctx, sf = env
     sb = sf.batch
     theta, res, info = field.bca(ctx, sb, (sf.img_field, sf.n_fields, sf.H, sf.W), sweeps=2,
-                                 start_mode=cb.INIT_PLAIN, log=_say)
+                                 start_mode=cb.INIT_PLAIN, log=_say, schedule="jacobi")
     theta = theta.cpu().numpy()
     assert np.mean(res["status"] == cb.CONVERGED) > 0.95
     nm, nv, off = (x.cpu().numpy() if hasattr(x, "cpu") else x for x in info["nbr"])
