@@ -111,9 +111,11 @@ __device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, 
   A.b4[4] = fmaf(Nn2, h44, A.b4[4]);
 }
 
-__device__ __forceinline__ float gal_value(const float* __restrict__ r, float dxx, float dxy, float dyy) {
-  const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
-  return wave_any(e >= E_ZERO) ? ex2(e) : 0.f;
+// acc += density of one component (value path).  No exact-zero skip here: one exp costs less
+// than the wavefront test and branch (measured: 24.7 ms without, 29.7 ms as a select, 42.4 ms as
+// a branch, for one value pass over 1.9e9 pixels).
+__device__ __forceinline__ void gal_value(const float* __restrict__ r, float dxx, float dxy, float dyy, float& acc) {
+  acc += ex2(fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0]))));
 }
 
 constexpr int tri(int i, int j) { return i * NZ - (i * (i - 1)) / 2 + (j - i); }
@@ -521,16 +523,16 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
       const float* __restrict__ r = T + STAR + k * STAR_REC;
       const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
       const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
-      Gs += gal_value(r, dxx, dxy, dyy);
+      gal_value(r, dxx, dxy, dyy, Gs);
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
       if constexpr (NE > 0) {
 #pragma unroll
-        for (int j = 0; j < NE; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+        for (int j = 0; j < NE; ++j) gal_value(base + j * GAL_REC, dxx, dxy, dyy, gx);
 #pragma unroll
-        for (int j = NE; j < NE + ND; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+        for (int j = NE; j < NE + ND; ++j) gal_value(base + j * GAL_REC, dxx, dxy, dyy, gd);
       } else {
-        for (int j = 0; j < n_exp; ++j) gx += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
-        for (int j = n_exp; j < ncomp; ++j) gd += gal_value(base + j * GAL_REC, dxx, dxy, dyy);
+        for (int j = 0; j < n_exp; ++j) gal_value(base + j * GAL_REC, dxx, dxy, dyy, gx);
+        for (int j = n_exp; j < ncomp; ++j) gal_value(base + j * GAL_REC, dxx, dxy, dyy, gd);
       }
     }
     const float Gg = fmaf(ed, gd - gx, gx);
