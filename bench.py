@@ -272,7 +272,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sources", type=int, default=None, help="first N sources only (default: all 20,000)")
     ap.add_argument("--train-sources", type=int, default=200000, help="surrogate training sources")
-    ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs")
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--no-surrogate", action="store_true", help="plain start only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("batched", "field"), default="batched",

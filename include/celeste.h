@@ -102,6 +102,10 @@ typedef struct celeste_stats {
   /* milliseconds per phase, measured with HIP events on the library's stream; only
    * accumulated while CELESTE_OPT_PROFILE is set */
   double ms_setup, ms_full, ms_reduce_full, ms_tr, ms_value, ms_reduce_value, ms_accept;
+  /* host wall-clock milliseconds of the fits' other stages (CELESTE_OPT_PROFILE only): packing and
+   * validating the batch on the host, uploading metadata and checking pixels, choosing the start
+   * (network, start evaluations), and the iterations' polling and result download */
+  double ms_host_pack, ms_prepare, ms_start, ms_loop, ms_results;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

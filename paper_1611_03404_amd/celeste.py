@@ -57,7 +57,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("full_px", ctypes.c_int64), ("value_px", ctypes.c_int64), ("full_launches", ctypes.c_int64),
                 ("value_launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("ms_setup", ctypes.c_double),
                 ("ms_full", ctypes.c_double), ("ms_reduce_full", ctypes.c_double), ("ms_tr", ctypes.c_double),
-                ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double)]
+                ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double),
+                ("ms_host_pack", ctypes.c_double), ("ms_prepare", ctypes.c_double), ("ms_start", ctypes.c_double),
+                ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -723,6 +724,16 @@ void accumulate_phases(celeste_ctx* ctx, PhaseTimer& T) {
 int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
             celeste_fit_result* res, hipStream_t st, bool batched, double* start_elbo = nullptr,
             bool start_only = false) {
+  // host stage clock (profile mode): stage k ends at mark(k); the stream is drained first
+  const bool prof = ctx->profile != 0;
+  auto t_last = std::chrono::steady_clock::now();
+  auto stage = [&](double& acc, hipStream_t s) {
+    if (!prof) return;
+    (void)hipStreamSynchronize(s);
+    const auto now = std::chrono::steady_clock::now();
+    acc += std::chrono::duration<double, std::milli>(now - t_last).count();
+    t_last = now;
+  };
   Packed P;
   CHK(validate_and_pack(ctx, b, &P));
   if (start_only) {
@@ -753,7 +764,9 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
       CHK(check_theta(th.data() + (size_t)s * NP, s));
     }
   }
+  stage(ctx->stats.ms_host_pack, st);
   CHK(prepare(ctx, b, &P, st));
+  stage(ctx->stats.ms_prepare, st);
   FitDev F;
   CHK(alloc_fit(ctx, S, &F));
   FitParams fp;
@@ -811,6 +824,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     HIPCHK(hipStreamSynchronize(st));
     return CELESTE_OK;
   }
+  stage(ctx->stats.ms_start, st);
   PhaseTimer T;
   CHK(T.init(ctx->profile != 0));
 
@@ -859,6 +873,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != CELESTE_OK) return rc;
+  stage(ctx->stats.ms_loop, st);
   // results
   std::vector<double> fv(S), pred(S), delta(S);
   std::vector<int> iter(S), status(S), nfull(S), flags(S);
@@ -877,6 +892,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  stage(ctx->stats.ms_results, st);
   for (int s = 0; s < S; ++s) {
     res[s].elbo = fv[s];
     res[s].pred_gain = pred[s];
