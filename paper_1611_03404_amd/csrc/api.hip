@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -81,6 +82,7 @@ struct celeste_ctx {
   DevBuf sur;                   // surrogate predictions (float, S x 27)
   DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
   DevBuf tables2, fsky;                            // second setup table (field updates), field skies
+  DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
 
 namespace celeste {
@@ -101,6 +103,23 @@ int ensure(DevBuf& b, size_t bytes) {
     return fail(CELESTE_E_NOMEM, "device allocation of %zu bytes failed", bytes);
   }
   b.cap = bytes;
+  return CELESTE_OK;
+}
+
+// Pinned host buffer of at least `bytes` (contents not kept on growth).
+int ensure_host(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (bytes <= b.cap) return CELESTE_OK;
+  const size_t cap = std::max(bytes, b.cap + b.cap / 2);
+  if (b.p) (void)hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  if (hipHostMalloc(&b.p, cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(CELESTE_E_NOMEM, "pinned host allocation of %zu bytes failed", cap);
+  }
+  b.cap = cap;
   return CELESTE_OK;
 }
 
@@ -236,15 +255,38 @@ int check_theta(const double* th, int64_t s) {
   return CELESTE_OK;
 }
 
+// Host-side packed metadata; the arrays live in the context's pinned staging buffers (valid
+// until the context packs the next batch).
 struct Packed {
-  std::vector<ImgDev> imgs;
-  std::vector<WorkItem> items;
-  std::vector<SrcDev> srcs;
+  ImgDev* imgs = nullptr;
+  WorkItem* items = nullptr;
+  SrcDev* srcs = nullptr;
   PriorDev prior;
   ProfDev prof;
   int tstride = 0;
   int n_src = 0, n_img = 0, n_items = 0;
 };
+
+// fn(begin, end) over [0, n) in contiguous slices on up to 16 host threads (serial when small).
+template <class F>
+void parallel_for(int64_t n, F fn) {
+  const int64_t per_thread_min = 8192;
+  int nt = (int)std::min<int64_t>(16, std::max<int64_t>(1, n / per_thread_min));
+  nt = std::min<int>(nt, std::max(1u, std::thread::hardware_concurrency()));
+  if (nt <= 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+  for (auto& x : th) x.join();
+}
+
+int items_of(const celeste_image& im, int chunk) {
+  // bands of whole 8-row tile rows holding about `chunk` pixels
+  const int band = std::max(TILE, (chunk / std::max(1, im.w)) / TILE * TILE);
+  return (im.h + band - 1) / band;
+}
 
 int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
   if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
@@ -264,25 +306,50 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
   if (n_img > (int64_t)1 << 30) return fail(CELESTE_E_INVALID, "too many images");
   CHK(make_prior(b->prior, &P->prior));
   CHK(make_profiles(b->profiles, &P->prof));
-  int max_psf = 1;
-  for (int64_t i = 0; i < n_img; ++i) {
-    CHK(check_image(b->images[i], i));
-    max_psf = std::max(max_psf, b->images[i].n_psf);
+  // image checks in parallel; the message comes from re-checking the first bad image here
+  const int nslot = 16;
+  std::vector<int64_t> first_bad(nslot, INT64_MAX);
+  std::vector<int> slot_psf(nslot, 1);
+  {
+    parallel_for(n_img, [&](int64_t i0, int64_t i1) {
+      const int slot = (int)((i0 * nslot) / std::max<int64_t>(1, n_img));
+      int64_t bad = INT64_MAX;
+      int mp = 1;
+      for (int64_t i = i0; i < i1; ++i) {
+        if (check_image(b->images[i], i) != CELESTE_OK) {
+          bad = i;
+          break;
+        }
+        mp = std::max(mp, b->images[i].n_psf);
+      }
+      first_bad[slot] = std::min(first_bad[slot], bad);
+      slot_psf[slot] = std::max(slot_psf[slot], mp);
+    });
   }
+  const int64_t bad = *std::min_element(first_bad.begin(), first_bad.end());
+  if (bad != INT64_MAX) return check_image(b->images[bad], bad);
+  const int max_psf = *std::max_element(slot_psf.begin(), slot_psf.end());
   P->tstride = table_stride(max_psf, P->prof.n_exp, P->prof.n_dev);
   P->n_src = b->n_sources;
   P->n_img = (int)n_img;
-  P->imgs.resize(n_img);
-  P->srcs.resize(b->n_sources);
-  P->items.clear();
+  CHK(ensure_host(ctx->h_imgs, sizeof(ImgDev) * n_img));
+  CHK(ensure_host(ctx->h_srcs, sizeof(SrcDev) * b->n_sources));
+  P->imgs = as<ImgDev>(ctx->h_imgs);
+  P->srcs = as<SrcDev>(ctx->h_srcs);
   const int chunk = std::max(64, ctx->chunk_px);
-  for (int s = 0; s < b->n_sources; ++s) {
-    SrcDev sd;
-    sd.img_begin = (int)b->image_offsets[s];
-    sd.img_end = (int)b->image_offsets[s + 1];
-    sd.item_begin = (int)P->items.size();
-    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) {
+  // work-item offsets per image (items in image order, so per source contiguous)
+  std::vector<int64_t> first_item(n_img + 1, 0);
+  for (int64_t i = 0; i < n_img; ++i) first_item[i + 1] = first_item[i] + items_of(b->images[i], chunk);
+  if (first_item[n_img] > (int64_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
+  CHK(ensure_host(ctx->h_items, sizeof(WorkItem) * first_item[n_img]));
+  P->items = as<WorkItem>(ctx->h_items);
+  std::vector<int> src_of(n_img);
+  for (int s = 0; s < b->n_sources; ++s)
+    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) src_of[i] = s;
+  parallel_for(n_img, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
       const celeste_image& im = b->images[i];
+      const int s = src_of[i];
       ImgDev& d = P->imgs[i];
       std::memset(&d, 0, sizeof(d));
       d.pix = im.pixels;
@@ -302,20 +369,24 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
       d.calib = im.calib;
       for (int k = 0; k < CELESTE_MAX_PSF; ++k)
         for (int j = 0; j < 6; ++j) d.psf[k][j] = k < im.n_psf ? im.psf[k][j] : 0.0;
-      d.item_begin = (int)P->items.size();
-      // bands of whole 8-row tile rows holding about `chunk` pixels
+      d.item_begin = (int)first_item[i];
+      d.item_end = (int)first_item[i + 1];
       const int band = std::max(TILE, (chunk / std::max(1, im.w)) / TILE * TILE);
-      for (int r = 0; r < im.h; r += band) P->items.push_back(WorkItem{(int)i, s, r, std::min(im.h, r + band)});
-      d.item_end = (int)P->items.size();
+      int64_t it = first_item[i];
+      for (int r = 0; r < im.h; r += band) P->items[it++] = WorkItem{(int)i, s, r, std::min(im.h, r + band)};
     }
-    sd.item_end = (int)P->items.size();
+  });
+  for (int s = 0; s < b->n_sources; ++s) {
+    SrcDev sd;
+    sd.img_begin = (int)b->image_offsets[s];
+    sd.img_end = (int)b->image_offsets[s + 1];
+    sd.item_begin = (int)first_item[sd.img_begin];
+    sd.item_end = (int)first_item[sd.img_end];
     sd.npix = 0;
-    for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i)
-      sd.npix += (int64_t)b->images[i].h * b->images[i].w;
+    for (int64_t i = sd.img_begin; i < sd.img_end; ++i) sd.npix += (int64_t)b->images[i].h * b->images[i].w;
     P->srcs[s] = sd;
   }
-  if (P->items.size() > (size_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
-  P->n_items = (int)P->items.size();
+  P->n_items = (int)first_item[n_img];
   return CELESTE_OK;
 }
 
@@ -367,9 +438,9 @@ int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st,
   CHK(ensure(ctx->tables, sizeof(float) * (size_t)P->tstride * P->n_img));
   CHK(ensure(ctx->partials, sizeof(double) * (size_t)NACC * P->n_items));
   CHK(ensure(ctx->flag, sizeof(int) * 4));
-  HIPCHK(hipMemcpyAsync(ctx->imgs.p, P->imgs.data(), sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ctx->items.p, P->items.data(), sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ctx->srcs.p, P->srcs.data(), sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->imgs.p, P->imgs, sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->items.p, P->items, sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->srcs.p, P->srcs, sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
   if (!pixels) {
     HIPCHK(hipStreamSynchronize(st));
     return CELESTE_OK;
@@ -482,9 +553,11 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
-                    &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off};
+                    &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
+    if (b->p) (void)hipHostFree(b->p);
   (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -804,14 +877,19 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
   }
   HIPCHK(launch_fit_init(F, S, fp, st));
-  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
-  HIPCHK(launch_setup(imgs, P.n_img, F.theta, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
-  HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                           P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
-                             ctx->vtile_log2, st));
-  HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs, as<double>(ctx->partials), as<double>(ctx->img_const),
-                             F.theta, P.prior, nullptr, F.f, ctr_value(ctx), st));
-  ctx->stats.value_launches += 1;
+  if (o->init_mode != CELESTE_INIT_SURROGATE) {
+    // the start's ELBO (the surrogate path has it from choosing between the two starts: both lie
+    // inside the boxes, where the transform round trip of the fit set-up moves a parameter by
+    // rounding, or by at most 1e-9 of its box where a start sits on the box edge)
+    const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+    HIPCHK(launch_setup(imgs, P.n_img, F.theta, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+    HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock,
+                             ctx->variant, ctx->vtile_log2, st));
+    HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), S, imgs, as<double>(ctx->partials),
+                               as<double>(ctx->img_const), F.theta, P.prior, nullptr, F.f, ctr_value(ctx), st));
+    ctx->stats.value_launches += 1;
+  }
   HIPCHK(launch_fit_start(F, S, st));
   if (start_only) {
     if (b->mem_kind == CELESTE_MEM_HOST) {

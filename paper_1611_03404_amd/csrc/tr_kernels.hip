@@ -104,6 +104,7 @@ __global__ void k_choose_start(FitDev st, int n_src) {
   const double fs = st.f_trial[s], fp = st.f[s];
   if (isfinite(fs) && (!isfinite(fp) || fs > fp)) {
     for (int i = 0; i < NP; ++i) st.theta[(size_t)s * NP + i] = st.theta_trial[(size_t)s * NP + i];
+    st.f[s] = fs;
     st.flags[s] = 0;
   } else {
     st.flags[s] = CELESTE_FLAG_FALLBACK_USED;
