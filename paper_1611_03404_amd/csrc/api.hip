@@ -701,7 +701,7 @@ struct FitBufs {
 };
 
 int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
-  const size_t nd = (size_t)S * (NP * 5 + NP * NP + 2 + 7);
+  const size_t nd = (size_t)S * (NP * 5 + 2 * NP * NP + 2 + 7);
   const size_t ni = (size_t)S * 6 + 1;
   CHK(ensure(ctx->st_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
   double* d = as<double>(ctx->st_buf);
@@ -716,6 +716,7 @@ int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   f->g = take((size_t)S * NP);
   f->p = take((size_t)S * NP);
   f->H = take((size_t)S * NP * NP);
+  f->V = take((size_t)S * NP * NP);
   f->u0 = take((size_t)S * 2);
   f->f = take(S);
   f->f_full = take(S);

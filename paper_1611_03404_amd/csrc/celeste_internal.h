@@ -129,6 +129,7 @@ struct FitDev {
   double* theta_trial;  // S x 27
   double* g;            // S x 27 natural gradient at current
   double* H;            // S x 729 natural Hessian at current
+  double* V;            // S x 729 eigenvectors of the previous trust-region model (warm start)
   double* p;            // S x 27 step (psi)
   double* f;            // S current ELBO (value pass)
   double* f_full;       // S ELBO from the full pass

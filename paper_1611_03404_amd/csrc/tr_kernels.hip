@@ -75,6 +75,8 @@ __global__ void k_fit_init(FitDev st, int n_src, FitParams fp) {
     double d1, d2;
     th[i] = to_theta1(ps[i], b, &d1, &d2);
   }
+  double* V = st.V + (size_t)s * NP * NP;
+  for (int i = 0; i < NP * NP; ++i) V[i] = (i % (NP + 1) == 0) ? 1.0 : 0.0;
   st.delta[s] = fp.delta0;
   st.iter[s] = 0;
   st.status[s] = CELESTE_MAX_ITER;
@@ -137,6 +139,7 @@ __device__ inline void pair_of(int round, int k, int* p, int* q) {
 __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __shared__ double B[NPAD][NPAD + 1];
   __shared__ double V[NPAD][NPAD + 1];
+  __shared__ double W[NPAD][NPAD + 1];
   __shared__ double g[NPAD], gt[NPAD], lam[NPAD], pt[NPAD], d1s[NP];
   __shared__ double rc[NPAD / 2], rs[NPAD / 2], rt[NPAD / 2], rapq[NPAD / 2], rapp[NPAD / 2], raqq[NPAD / 2];
   __shared__ int rp[NPAD / 2], rq[NPAD / 2];
@@ -169,9 +172,26 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
       if (i == j) b -= d2s[i] * gn[i];
     }
     B[i][j] = b;
-    V[i][j] = (i == j) ? 1.0 : 0.0;
+    // warm start: the eigenvectors of the previous model (identity at the first iteration)
+    V[i][j] = (i < NP && j < NP) ? st.V[(size_t)s * NP * NP + i * NP + j] : (i == j ? 1.0 : 0.0);
   }
   if (t < NPAD) g[t] = t < NP ? d1s[t] * gn[t] : 0.0;
+  __syncthreads();
+  // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
+  // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model
+  for (int k = t; k < NPAD * NPAD; k += 64) {
+    const int i = k / NPAD, j = k - i * NPAD;
+    double a = 0.0;
+    for (int r = 0; r < NPAD; ++r) a += B[i][r] * V[r][j];
+    W[i][j] = a;
+  }
+  __syncthreads();
+  for (int k = t; k < NPAD * NPAD; k += 64) {
+    const int i = k / NPAD, j = k - i * NPAD;
+    double a = 0.0;
+    for (int r = 0; r < NPAD; ++r) a += V[r][i] * W[r][j];
+    B[i][j] = a;
+  }
   __syncthreads();
   // symmetrise (the Hessian is assembled symmetrically; this removes rounding asymmetry)
   for (int k = t; k < NPAD * NPAD; k += 64) {
@@ -261,13 +281,14 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
     }
   }
 
-  // ---- eigen-coordinates of g
+  // ---- eigen-coordinates of g; the eigenvectors are kept for the next iteration's start
   if (t < NP) {
     lam[t] = B[t][t];
     double a = 0.0;
     for (int r = 0; r < NP; ++r) a += V[r][t] * g[r];
     gt[t] = a;
   }
+  for (int k = t; k < NP * NP; k += 64) st.V[(size_t)s * NP * NP + k] = V[k / NP][k % NP];
   __syncthreads();
 
   // ---- secular equation (one lane)
