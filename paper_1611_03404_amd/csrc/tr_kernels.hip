@@ -291,59 +291,56 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   for (int k = t; k < NP * NP; k += 64) st.V[(size_t)s * NP * NP + k] = V[k / NP][k % NP];
   __syncthreads();
 
-  // ---- secular equation (one lane)
-  if (t == 0) {
-    const double delta = st.delta[s];
-    double lam0 = lam[0], lmax = fabs(lam[0]), gn2 = 0.0;
-    int i0 = 0;
-    for (int i = 0; i < NP; ++i) {
-      if (lam[i] < lam0) {
-        lam0 = lam[i];
-        i0 = i;
-      }
-      lmax = fmax(lmax, fabs(lam[i]));
-      gn2 += gt[i] * gt[i];
-    }
-    const double scale = fmax(1.0, lmax);
-    auto pnorm2 = [&](double sv) {
-      double a = 0.0;
-      for (int i = 0; i < NP; ++i) {
-        const double q = gt[i] / (lam[i] + sv);
-        a += q * q;
-      }
-      return a;
+  // ---- secular equation, one eigen-coordinate per lane (lanes >= NP hold neutral values);
+  // every reduction is broadcast from lane 0 so all lanes take the same decisions
+  {
+    const bool on = t < NP;
+    const double li = on ? lam[t] : 0.0, gi = on ? gt[t] : 0.0;
+    auto wsum = [](double x) {
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      return __shfl(x, 0);
     };
-    double sv = 0.0;
+    auto wmin = [](double x) {
+      for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+      return __shfl(x, 0);
+    };
+    auto wmax = [](double x) {
+      for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+      return __shfl(x, 0);
+    };
+    const double delta = st.delta[s];
+    const double lam0 = wmin(on ? li : INFINITY);
+    // first index holding the smallest eigenvalue
+    const unsigned long long at_min = __ballot(on && li == lam0);
+    const int i0 = __ffsll((long long)at_min) - 1;
+    const double scale = fmax(1.0, wmax(on ? fabs(li) : 0.0));
+    const double gn2 = wsum(gi * gi);
+    auto pnorm2 = [&](double sv) {
+      const double q = on ? gi / (li + sv) : 0.0;
+      return wsum(q * q);
+    };
+    double sv = 0.0, pti = 0.0;
     bool hard = false;
     if (!(lam0 > 1e-14 * scale && pnorm2(0.0) <= delta * delta)) {
       const double slo = fmax(0.0, -lam0);
-      double gbot2 = 0.0, prest2 = 0.0;
-      for (int i = 0; i < NP; ++i) {
-        if (fabs(lam[i] - lam0) <= 1e-12 * scale) {
-          gbot2 += gt[i] * gt[i];
-        } else {
-          const double q = gt[i] / (lam[i] + slo);
-          prest2 += q * q;
-        }
-      }
+      const bool bottom = on && fabs(li - lam0) <= 1e-12 * scale;
+      const double gbot2 = wsum(bottom ? gi * gi : 0.0);
+      const double qrest = (on && !bottom) ? gi / (li + slo) : 0.0;
+      const double prest2 = wsum(qrest * qrest);
       if (sqrt(gbot2) <= 1e-12 * fmax(1.0, sqrt(gn2)) && prest2 <= delta * delta) {
         hard = true;
         sv = slo;
-        for (int i = 0; i < NP; ++i)
-          pt[i] = (fabs(lam[i] - lam0) <= 1e-12 * scale) ? 0.0 : gt[i] / (lam[i] + slo);
-        pt[i0] += sqrt(fmax(delta * delta - prest2, 0.0));
+        pti = bottom ? 0.0 : qrest;
+        if (t == i0) pti += sqrt(fmax(delta * delta - prest2, 0.0));
       } else {
         double lo = slo, hi = slo + sqrt(gn2) / delta + 1.0;
         sv = (slo > 0.0) ? slo + 1e-12 * scale : 0.0;
         if (pnorm2(sv) > delta * delta) {
           for (int it = 0; it < 200; ++it) {
-            double a2 = 0.0, b3 = 0.0;
-            for (int i = 0; i < NP; ++i) {
-              const double den = lam[i] + sv;
-              const double q = gt[i] / den;
-              a2 += q * q;
-              b3 += q * q / den;
-            }
+            const double den = li + sv;
+            const double q = on ? gi / den : 0.0;
+            const double a2 = wsum(q * q);
+            const double b3 = wsum(on ? q * q / den : 0.0);
             const double pn = sqrt(a2);
             if (fabs(pn - delta) <= 1e-13 * delta) break;
             if (pn > delta) lo = fmax(lo, sv); else hi = fmin(hi, sv);
@@ -357,23 +354,24 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         // else: |p| <= Delta just above the pole (nearly the hard case): keep sv
       }
     }
-    if (!hard)
-      for (int i = 0; i < NP; ++i) pt[i] = gt[i] / (lam[i] + sv);
-    double pred = 0.0;
-    for (int i = 0; i < NP; ++i) pred += gt[i] * pt[i] - 0.5 * lam[i] * pt[i] * pt[i];
-    // convergence and iteration cap
-    const double f = st.f[s];
-    int d = 0;
-    if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
-      st.status[s] = CELESTE_CONVERGED;
-      d = 1;
-    } else if (st.iter[s] >= fp.max_iter) {
-      st.status[s] = CELESTE_MAX_ITER;
-      d = 1;
+    if (!hard) pti = on ? gi / (li + sv) : 0.0;
+    if (on) pt[t] = pti;
+    const double pred = wsum(on ? gi * pti - 0.5 * li * pti * pti : 0.0);
+    if (t == 0) {
+      // convergence and iteration cap
+      const double f = st.f[s];
+      int d = 0;
+      if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
+        st.status[s] = CELESTE_CONVERGED;
+        d = 1;
+      } else if (st.iter[s] >= fp.max_iter) {
+        st.status[s] = CELESTE_MAX_ITER;
+        d = 1;
+      }
+      st.pred[s] = pred;
+      if (d) st.active[s] = 0;
+      done = d;
     }
-    st.pred[s] = pred;
-    if (d) st.active[s] = 0;
-    done = d;
   }
   __syncthreads();
   if (done) return;
