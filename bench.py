@@ -278,7 +278,9 @@ def main():
     ap.add_argument("--workload", choices=("batched", "field"), default="batched",
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps")
-    ap.add_argument("--sweeps", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=3, help="field workload: sweeps (the maximum with --until-rtol)")
+    ap.add_argument("--until-rtol", type=float, default=None,
+                    help="field workload: sweep until a sweep raises the joint ELBO by at most this fraction")
     ap.add_argument("--schedule", choices=("jacobi", "colour"), default="colour",
                     help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
                          "sweeps over conflict-free colours")
@@ -496,7 +498,8 @@ def field_bench(args, ctx, net, sur_info, log):
     info = res = None
     for k in range(args.steps):
         theta, res, info = field.bca(ctx, sb, meta, sweeps=args.sweeps, start_mode=mode, log=log,
-                                     schedule=args.schedule, field_pixels=sf.fields, field_sky=sf.field_sky)
+                                     schedule=args.schedule, field_pixels=sf.fields, field_sky=sf.field_sky,
+                                     until_rtol=args.until_rtol)
         conv += int(np.sum(res["status"] == cb.CONVERGED))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -512,11 +515,14 @@ def field_bench(args, ctx, net, sur_info, log):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve, bf16 network", "data": "synthetic",
         "config": {"workload": f"crowded field {sf.W}x{sf.H} px, {sf.n_fields} images (5 bands x 4 epochs), "
-                               f"{sb.n_sources} sources, {args.sweeps} "
-                               f"{'Jacobi' if args.schedule == 'jacobi' else 'colour (Gauss-Seidel)'} sweeps",
+                               f"{sb.n_sources} sources, "
+                               + (f"{args.sweeps} " if args.until_rtol is None else
+                                  f"up to {args.sweeps} (until a sweep gains <= {args.until_rtol:g} of the joint ELBO) ")
+                               + f"{'Jacobi' if args.schedule == 'jacobi' else 'colour (Gauss-Seidel)'} sweeps",
                    "n_patch_pixels": sb.n_pixels, "start": "surrogate" if net is not None else "plain"},
         "converged_last_sweep": int(np.sum(res["status"] == cb.CONVERGED)),
-        "schedule": args.schedule, "start_joint_elbo": info["start_joint_elbo"],
+        "schedule": args.schedule, "start_joint_elbo": info["start_joint_elbo"], "stopped": info["stopped"],
+        "until_rtol": args.until_rtol,
         "autotune": tune,
         "sweeps": info["history"], "timings_s_per_step": {k: v / args.steps for k, v in info["timings"].items()},
         "pixel_evals_per_s": st["full_px"] / wall,

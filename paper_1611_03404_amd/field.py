@@ -23,15 +23,19 @@ from . import celeste as cb
 
 
 def bca(ctx, batch_arrays, fields_meta, sweeps=3, start_mode=cb.INIT_SURROGATE, log=None, schedule="colour",
-        field_pixels=None, field_sky=None):
+        field_pixels=None, field_sky=None, until_rtol=None):
     """batch_arrays: object with the SoA fields of Batch.from_synth (device pixels);
     fields_meta: (img_field, n_fields, height, width).  With field_pixels (device, the field
     images) and field_sky, the joint ELBO of the field is evaluated at the start and after every
-    sweep (history[k]["joint_elbo"]).  Returns theta, last results, dict(timings, history, nbr,
-    fields)."""
+    sweep (history[k]["joint_elbo"]).  With until_rtol, sweeps run (at most `sweeps` of them)
+    until one raises the joint ELBO by no more than until_rtol * |joint ELBO|: a stationary point
+    of block coordinate ascent.  Returns theta, last results, dict(timings, history, nbr, fields,
+    start_joint_elbo, stopped)."""
     import torch
     if schedule not in ("jacobi", "colour"):
         raise ValueError("schedule must be 'jacobi' or 'colour'")
+    if until_rtol is not None and field_pixels is None:
+        raise ValueError("until_rtol needs field_pixels and field_sky (the joint ELBO)")
     img_field, n_fields, H, W = fields_meta
     img_field = np.asarray(img_field, dtype=np.int32)
     base = cb.Batch.from_synth(batch_arrays)
@@ -131,5 +135,12 @@ def bca(ctx, batch_arrays, fields_meta, sweeps=3, start_mode=cb.INIT_SURROGATE, 
             log(f"sweep {k} ({schedule}): fit {fit_s:.2f} s, converged {h['converged']}, "
                 f"iterations {h['iters_mean']:.2f}" +
                 (f", joint ELBO {h['joint_elbo']:.6e}" if "joint_elbo" in h else ""))
+        if until_rtol is not None:
+            prev = start_elbo if k == 0 else history[-2]["joint_elbo"]
+            if h["joint_elbo"] - prev <= until_rtol * abs(h["joint_elbo"]):
+                stopped = "stationary"
+                break
+    else:
+        stopped = "sweeps"
     return theta, res, dict(timings=timings, history=history, nbr=(nbr_mean, nbr_var, nbr_off), fields=fields,
-                            start_joint_elbo=start_elbo)
+                            start_joint_elbo=start_elbo, stopped=stopped)

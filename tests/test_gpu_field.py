@@ -285,3 +285,20 @@ def test_colour_sweeps_increase_joint_elbo(env):
             nbr[j] = (nm[off[i]:off[i] + h * w].reshape(h, w), nv[off[i]:off[i] + h * w].reshape(h, w))
         v = model.elbo_value(theta[s], model.source_images(sub, 0, nbr=nbr), sub.prior, sub.profiles)
         assert abs(v - res["elbo"][s]) <= ELBO_RTOL * abs(v)
+
+
+def test_colour_sweeps_to_a_stationary_point(env):
+    """Sweeping until the joint ELBO stops rising (a stationary point of block coordinate
+    ascent) ends early, with a monotone joint ELBO, and (almost) every source's last fit converged."""
+    from paper_1611_03404_amd import field
+    cb, ctx, sf = env
+    theta, res, info = field.bca(ctx, sf.batch, (sf.img_field, sf.n_fields, sf.H, sf.W), sweeps=12,
+                                 start_mode=cb.INIT_PLAIN, log=_say, schedule="colour", field_pixels=sf.fields,
+                                 field_sky=sf.field_sky, until_rtol=1e-7)
+    seq = [info["start_joint_elbo"]] + [h["joint_elbo"] for h in info["history"]]
+    _say("stopped", info["stopped"], "after", len(info["history"]), "sweeps; joint ELBO", seq)
+    assert info["stopped"] == "stationary" and len(info["history"]) < 12
+    for a, b in zip(seq, seq[1:]):
+        assert b >= a - 1e-9 * abs(a)
+    assert seq[-1] - seq[-2] <= 1e-7 * abs(seq[-1])
+    assert np.mean(res["status"] == cb.CONVERGED) > 0.99
