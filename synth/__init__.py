@@ -8,6 +8,7 @@ no derivatives, no Kullback-Leibler terms.  Pixels are made by shooting
 photons (Poisson count per band, positions drawn from the PSF and the galaxy
 prototype mixtures, binned into unit pixels) on top of Poisson sky.
 """
+from . import subsample  # noqa: F401
 from .generate import (  # noqa: F401
     PRIOR, load_profiles, SynthBatch, SynthField, make_config, make_field, CONFIG_SEED_BASE, N_PARAMS,
 )
