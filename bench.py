@@ -145,6 +145,53 @@ def cpu_baseline(sb, theta0, gpu_full_px_per_step, gpu_value_px_per_step, conver
     }
 
 
+_SAMPLED_JOB = None   # (subset, keep, off, keep_prob, thetas): inherited by forked workers
+
+
+def _sampled_oracle_worker(k):
+    import numpy as np
+    from oracle import model
+    sub, keep, off, p, th = _SAMPLED_JOB
+    imgs = []
+    for j, img in enumerate(model.source_images(sub, k)):
+        i = sub.src_img_off[k] + j
+        w = np.repeat(keep[off[i]:off[i + 1]].astype(np.float64) / p, 8)[: img["h"]]
+        imgs.append(dict(img, weights=np.repeat(w[:, None], img["w"], axis=1)))
+    t0 = time.perf_counter()
+    model.elbo(th[k], imgs, sub.prior, sub.profiles)
+    return time.perf_counter() - t0
+
+
+def sampled_cpu_baseline(sb, theta, keep_prob, seed, budget_s=20.0):
+    """The oracle's subsampled estimate (value, gradient, Hessian) of random sources of the
+    same workload with their own masks, timed on the host cores: source evaluations/s."""
+    global _SAMPLED_JOB
+    import multiprocessing as mp
+    import numpy as np
+    from synth.subsample import block_masks
+    cores = max(1, min(16, os.cpu_count() or 1))
+    rng = np.random.default_rng(161103407)
+    order = rng.permutation(sb.n_sources)
+    pick, est = [], 0.0
+    for s in order:
+        if est > budget_s * cores or len(pick) >= 4 * cores:
+            break
+        pick.append(int(s))
+        est += 7e-5 * int(np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64) ** 2))
+    sub = sb.subset(pick)
+    keep, off = block_masks(sub.img_h, keep_prob, seed)
+    _SAMPLED_JOB = (sub, keep, off, keep_prob, theta[pick])
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores, initializer=_one_thread) as pool:
+        ts = pool.map(_sampled_oracle_worker, range(sub.n_sources), chunksize=1)
+    wall = time.perf_counter() - t0
+    _SAMPLED_JOB = None
+    return {"value": len(pick) / sum(ts) * cores, "unit": "source evaluations/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{len(pick)} random sources of the same workload, one subsampled value+gradient+Hessian "
+                       f"estimate each at the plain start, keep_prob {keep_prob}, on {cores} processes "
+                       f"({wall:.1f} s wall)")}
+
+
 _FIELD_JOB = None   # (subset, per-source neighbour dicts, thetas, n_full): inherited by forked workers
 
 
@@ -275,9 +322,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--no-surrogate", action="store_true", help="plain start only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("batched", "field"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "field", "sampled"), default="batched",
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
-                         "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps")
+                         "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps; sampled: pixel-subsampled "
+                         "evaluations of the batched workload")
+    ap.add_argument("--keep-prob", type=float, default=0.25,
+                    help="sampled workload: probability of keeping each 8-row block of an image")
     ap.add_argument("--sweeps", type=int, default=3, help="field workload: sweeps (the maximum with --until-rtol)")
     ap.add_argument("--until-rtol", type=float, default=None,
                     help="field workload: sweep until a sweep raises the joint ELBO by at most this fraction")
@@ -308,6 +358,10 @@ def main():
     ctx = cb.Context(0)
     if args.probe:
         return probe(args, ctx, log)
+    if args.workload == "sampled":
+        if not 0.0 < args.keep_prob <= 1.0:
+            sys.exit("--keep-prob must be in (0, 1]")
+        return sampled_bench(args, ctx, log)
     ctx.set_option(cb.OPT_PROFILE, 1)
     sur_info = None
     net = None
@@ -457,6 +511,92 @@ def main():
     if net is not None:
         ctx.set_surrogate(None)
         net.close()
+    ctx.close()
+
+
+def sampled_bench(args, ctx, log):
+    """Pixel-subsampled evaluation: one step = one subsampled ELBO + gradient + Hessian estimate
+    of every source of the batched-uneven workload at the plain start, 8-row blocks kept with
+    probability keep_prob (fresh seeded masks, uploaded by each call), timed for several
+    keep_prob values; the headline is the one given by --keep-prob."""
+    import numpy as np
+    import torch
+
+    import synth
+    from synth.subsample import block_masks
+    from paper_1611_03404_amd import celeste as cb
+    sb = synth.make_config(2, n_sources=args.sources, device="cuda")
+    batch = cb.Batch.from_synth(sb)
+    theta0 = np.zeros((sb.n_sources, 27))
+    theta0[:, 0:2] = sb.u_cat
+    th, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+    tune = None if args.no_autotune else ctx.autotune(batch, th)
+    log(f"sampled: {sb.n_sources} sources, {sb.n_pixels} px, autotune {tune}")
+    ctx.set_option(cb.OPT_PROFILE, 1)
+    w = sb.img_w.astype(np.int64)
+    h = sb.img_h.astype(np.int64)
+    K = 3
+    E, D = len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0])
+    f_full = flop_full_per_px(K, E, D)
+    probs = sorted(set([1.0, 0.5, 0.25, 0.1, args.keep_prob]), reverse=True)
+    sweep = {}
+    for i, p in enumerate(probs):
+        masks = [block_masks(sb.img_h, p, 161103410 + 97 * i + k) for k in range(args.warmup + args.steps)]
+        img_of = np.repeat(np.arange(len(h)), (h + 7) // 8)
+        blk_px = np.minimum(8, h[img_of] - 8 * (np.arange(img_of.size) - np.repeat(masks[0][1][:-1], (h + 7) // 8)))
+        blk_px *= w[img_of]     # pixels of each 8-row block (the last block of an image may be shorter)
+        kept_px = [int(np.sum(blk_px[keep != 0])) for keep, _ in masks]
+        for k in range(args.warmup):
+            ctx.elbo_eval_sampled(batch, th, masks[k][0], masks[k][1], p)
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            ctx.elbo_eval_sampled(batch, th, masks[k][0], masks[k][1], p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stats()
+        px = sum(kept_px[args.warmup:])
+        kern_s = st["ms_full"] / 1e3
+        sweep[p] = {"keep_prob": p, "ms_per_eval": 1e3 * wall / args.steps,
+                    "source_evals_per_s": sb.n_sources * args.steps / wall,
+                    "kept_pixel_fraction": px / (args.steps * sb.n_pixels),
+                    "kernel_ms_per_eval": st["ms_full"] / args.steps,
+                    "kernel_kept_pixel_evals_per_s": px / kern_s if kern_s > 0 else None,
+                    "kernel_tflops": f_full * px / kern_s / 1e12 if kern_s > 0 else None, "_px": px,
+                    "_kern_s": kern_s}
+        log(f"keep_prob {p}: {sweep[p]['ms_per_eval']:.2f} ms/eval, kernel {sweep[p]['kernel_ms_per_eval']:.2f} ms")
+    head = sweep[args.keep_prob]
+    achieved = head["kernel_tflops"]
+    out = {
+        "metric": "pixel-subsampled ELBO+gradient+Hessian source evaluations/s",
+        "value": head["source_evals_per_s"],
+        "unit": "source evaluations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_eval"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 pixel arithmetic, f64 accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"batched uneven sources ({sb.n_sources} sources, {sb.n_pixels} px) at the plain "
+                               f"start, 8-row blocks kept with probability {args.keep_prob}",
+                   "keep_prob": args.keep_prob, "n_sources": sb.n_sources, "n_pixels": sb.n_pixels},
+        "speedup_vs_full_eval": head["source_evals_per_s"] / sweep[1.0]["source_evals_per_s"],
+        "sweep": [{k: v for k, v in r.items() if not k.startswith("_")} for r in sweep.values()],
+        "autotune": tune,
+        "roofline": {
+            "kernel": "k_eval_full (value+gradient+Hessian pixel kernel), kept pixels only",
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS if achieved else None,
+            "flop_per_pixel_eval": f_full,
+            "avg_launch_ms": head["kernel_ms_per_eval"],
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = sampled_cpu_baseline(sb, th.cpu().numpy() if hasattr(th, "cpu") else th,
+                                                   args.keep_prob, 161103408)
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 

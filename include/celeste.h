@@ -222,6 +222,27 @@ void celeste_fit_opts_default(celeste_fit_opts* opts);
 int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
                       double* elbo, double* grad, double* hess, void* stream);
 
+/* Pixel-subsampled estimate of the same quantities (the paper's closing section names
+ * subsampling pixels, a second source of randomness in the stochastic optimisation, as a
+ * further speed-up).  Each image is cut into 8-row blocks (the last one may be shorter);
+ * a kept block's pixels weigh 1 / keep_prob, a dropped block's weigh 0, and the part of
+ * every pixel's term that does not depend on theta (x log E_bg - E_bg - lgamma(x + 1),
+ * E_bg = sky + neighbour mean) is summed over all pixels.  With blocks kept independently
+ * with probability keep_prob the estimate is unbiased for celeste_elbo_eval's results;
+ * an all-ones keep with keep_prob 1 gives them exactly.  Only kept blocks are evaluated.
+ *   keep     : host array, keep_off[n_images] bytes; keep[keep_off[i] + j] != 0 keeps
+ *              rows [8j, 8j + 8) of image i (image order of the batch)
+ *   keep_off : host array of n_images + 1 offsets; keep_off[0] == 0 and
+ *              keep_off[i + 1] - keep_off[i] == (h_i + 7) / 8
+ *   keep_prob: in (0, 1]
+ * Other arguments as celeste_elbo_eval.  Both host arrays are read before the call
+ * returns and stay owned by the caller.  Errors: as celeste_elbo_eval; E_INVALID for a
+ * NULL keep / keep_off, keep_prob outside (0, 1] or offsets that do not match the
+ * image heights. */
+int celeste_elbo_eval_sampled(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                              const uint8_t* keep, const int64_t* keep_off, double keep_prob,
+                              double* elbo, double* grad, double* hess, void* stream);
+
 /* Trust-region Newton fit of ONE source (batch->n_sources must be 1), host-driven:
  * one host/device round trip per iteration (section III-B).  theta_inout: 27 natural
  * coordinates in (start) and out (result), in batch->mem_kind memory.  Returns the

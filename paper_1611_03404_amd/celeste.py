@@ -105,6 +105,8 @@ def load():
     lib.celeste_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
     lib.celeste_fit_opts_default.restype = None
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
+    lib.celeste_elbo_eval_sampled.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, ctypes.c_double, vp, vp, vp,
+                                              vp]
     lib.celeste_newton_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
     lib.celeste_batch_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp, vp]
     lib.celeste_ctx_get_stats.argtypes = [vp, ctypes.POINTER(Stats), ctypes.c_int]
@@ -127,7 +129,8 @@ def load():
     lib.celeste_colour_sources.argtypes = [ctypes.POINTER(CBatch), vp, vp]
     lib.celeste_update_fields.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, ctypes.POINTER(CFields)]
     lib.celeste_field_elbo.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields), vp, vp, vp]
-    for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_newton_fit",
+    for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_elbo_eval_sampled",
+                 "celeste_newton_fit",
                  "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
                  "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
                  "celeste_ctx_set_surrogate", "celeste_theta_to_psi", "celeste_psi_to_theta",
@@ -354,6 +357,26 @@ class Context:
         _check(load().celeste_elbo_eval(self._h, ctypes.byref(batch.c), _ptr(th), _ptr(elbo),
                                         _ptr(grad) if grad is not None else None,
                                         _ptr(hess) if hess is not None else None, self._stream(batch)))
+        return elbo, grad, hess
+
+    def elbo_eval_sampled(self, batch: Batch, theta, keep, keep_off, keep_prob, want="hess"):
+        """Pixel-subsampled estimate of elbo_eval's results: keep (uint8) and keep_off (int64,
+        n_images + 1) select 8-row blocks of each image, kept blocks weigh 1 / keep_prob."""
+        S = batch.n_sources
+        th = batch.as_input(theta)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta must have shape ({S}, {NP})")
+        kp = np.ascontiguousarray(keep, dtype=np.uint8)
+        ko = np.ascontiguousarray(keep_off, dtype=np.int64)
+        if ko.ndim != 1 or kp.ndim != 1 or ko.size != len(batch.images) + 1 or ko[-1] != kp.size:
+            raise ValueError("keep_off must hold n_images + 1 offsets ending at keep.size")
+        elbo = batch.array((S,))
+        grad = batch.array((S, NP)) if want in ("grad", "hess") else None
+        hess = batch.array((S, NP, NP)) if want == "hess" else None
+        _check(load().celeste_elbo_eval_sampled(self._h, ctypes.byref(batch.c), _ptr(th), kp.ctypes.data,
+                                                ko.ctypes.data, float(keep_prob), _ptr(elbo),
+                                                _ptr(grad) if grad is not None else None,
+                                                _ptr(hess) if hess is not None else None, self._stream(batch)))
         return elbo, grad, hess
 
     def newton_fit(self, batch: Batch, theta0, opts=None):

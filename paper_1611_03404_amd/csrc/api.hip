@@ -82,6 +82,7 @@ struct celeste_ctx {
   DevBuf sur;                   // surrogate predictions (float, S x 27)
   DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
   DevBuf tables2, fsky;                            // second setup table (field updates), field skies
+  DevBuf kept;                                     // first rows of the kept blocks of a pixel subsample
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
 
@@ -390,6 +391,54 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
   return CELESTE_OK;
 }
 
+// Pixel subsample: the work items are rebuilt over the kept 8-row blocks only.  kept_rows
+// receives the first row of every kept block (image by image, in row order); an item takes
+// up to a band's worth of one image's consecutive list entries (the blocks need not be
+// adjacent), and its [row_begin, row_end) indexes kept_rows.  The item ranges of the images
+// and sources and the sources' pixel counts follow.  keep / keep_off: host arrays.
+int subsample_items(celeste_ctx* ctx, const celeste_batch* b, Packed* P, const uint8_t* keep,
+                    const int64_t* keep_off, std::vector<int>& kept_rows) {
+  if (keep_off[0] != 0) return fail(CELESTE_E_INVALID, "keep_off[0] must be 0");
+  for (int i = 0; i < P->n_img; ++i)
+    if (keep_off[i + 1] - keep_off[i] != (b->images[i].h + 7) / 8)
+      return fail(CELESTE_E_INVALID, "image %d: keep_off must give (h + 7) / 8 blocks", i);
+  const int chunk = std::max(64, ctx->chunk_px);
+  std::vector<WorkItem> items;
+  std::vector<int64_t> kept_px(P->n_img, 0);
+  kept_rows.clear();
+  for (int i = 0; i < P->n_img; ++i) {
+    const celeste_image& im = b->images[i];
+    const uint8_t* k = keep + keep_off[i];
+    const int nb = (im.h + 7) / 8;
+    const int per_item = std::max(TILE, (chunk / std::max(1, im.w)) / TILE * TILE) / TILE;   // blocks
+    ImgDev& d = P->imgs[i];
+    const size_t first = kept_rows.size();
+    for (int j = 0; j < nb; ++j)
+      if (k[j]) {
+        kept_rows.push_back(TILE * j);
+        kept_px[i] += (int64_t)(std::min(im.h, TILE * (j + 1)) - TILE * j) * im.w;
+      }
+    if (kept_rows.size() > (size_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many kept blocks");
+    d.item_begin = (int)items.size();
+    for (size_t e = first; e < kept_rows.size(); e += per_item)
+      items.push_back(WorkItem{i, d.src, (int)e, (int)std::min(kept_rows.size(), e + per_item)});
+    if (items.size() > (size_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
+    d.item_end = (int)items.size();
+  }
+  CHK(ensure_host(ctx->h_items, sizeof(WorkItem) * std::max<size_t>(1, items.size())));
+  P->items = as<WorkItem>(ctx->h_items);
+  if (!items.empty()) std::memcpy(P->items, items.data(), sizeof(WorkItem) * items.size());
+  for (int s = 0; s < P->n_src; ++s) {
+    SrcDev& sd = P->srcs[s];
+    sd.item_begin = P->imgs[sd.img_begin].item_begin;
+    sd.item_end = P->imgs[sd.img_end - 1].item_end;
+    sd.npix = 0;
+    for (int i = sd.img_begin; i < sd.img_end; ++i) sd.npix += kept_px[i];
+  }
+  P->n_items = (int)items.size();
+  return CELESTE_OK;
+}
+
 // Copies host pixel arrays into one device staging buffer and repoints the images.
 int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st) {
   size_t total = 0;
@@ -484,6 +533,9 @@ struct PhaseTimer {
   }
 };
 
+int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
+              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob);
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -553,7 +605,8 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
-                    &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky};
+                    &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
+                    &c->kept};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
@@ -617,6 +670,23 @@ size_t celeste_struct_size(int which) {
 
 int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
                       double* hess, void* stream) {
+  return eval_impl(ctx, b, theta, elbo, grad, hess, stream, nullptr, nullptr, 1.0);
+}
+
+int celeste_elbo_eval_sampled(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const uint8_t* keep,
+                              const int64_t* keep_off, double keep_prob, double* elbo, double* grad, double* hess,
+                              void* stream) {
+  if (!keep || !keep_off) return fail(CELESTE_E_INVALID, "keep and keep_off must not be NULL");
+  if (!(keep_prob > 0.0 && keep_prob <= 1.0)) return fail(CELESTE_E_INVALID, "keep_prob must be in (0, 1]");
+  return eval_impl(ctx, b, theta, elbo, grad, hess, stream, keep, keep_off, keep_prob);
+}
+
+}  // extern "C"
+
+namespace {
+
+int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
+              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob) {
   Packed P;
   CHK(validate_and_pack(ctx, b, &P));
   if (!theta || !elbo) return fail(CELESTE_E_INVALID, "theta and elbo must not be NULL");
@@ -637,7 +707,20 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
     HIPCHK(hipStreamSynchronize(st));
     for (size_t s = 0; s < S; ++s) CHK(check_theta(th_host.data() + s * NP, (int64_t)s));
   }
+  double px_weight = 1.0;
+  std::vector<int> kept_rows;
+  if (keep) {
+    CHK(subsample_items(ctx, b, &P, keep, keep_off, kept_rows));
+    px_weight = 1.0 / keep_prob;
+  }
   CHK(prepare(ctx, b, &P, st));
+  const int* kept = nullptr;
+  if (keep) {
+    CHK(ensure(ctx->kept, sizeof(int) * std::max<size_t>(1, kept_rows.size())));
+    if (!kept_rows.empty())
+      HIPCHK(hipMemcpyAsync(ctx->kept.p, kept_rows.data(), sizeof(int) * kept_rows.size(), hipMemcpyHostToDevice, st));
+    kept = as<int>(ctx->kept);
+  }
   double *d_elbo = elbo, *d_grad = grad, *d_hess = hess;
   if (b->mem_kind == CELESTE_MEM_HOST) {
     CHK(ensure(ctx->o_elbo, sizeof(double) * S));
@@ -660,19 +743,20 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
   if (grad) {
     HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant,
-                            ctx->tile_log2, st));
+                            ctx->tile_log2, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
-                              ctr_full(ctx), st));
+                              ctr_full(ctx), st, px_weight));
     ctx->stats.full_launches += 1;
   } else {
     HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                              P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
-                             ctx->vtile_log2, st));
+                             ctx->vtile_log2, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
-                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, ctr_value(ctx), st));
+                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, ctr_value(ctx), st,
+                               px_weight));
     ctx->stats.value_launches += 1;
   }
   T.mark(3, st);
@@ -690,7 +774,7 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
   return CELESTE_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 // =============================================================================== fits
 

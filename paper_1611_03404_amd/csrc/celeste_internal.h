@@ -92,20 +92,27 @@ hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, cons
                         ProfDev prof, float* tables, int tstride, hipStream_t st);
 hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStream_t st);
 hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st);
-// tw_log2: log2 of the pixel-tile width (3..6; tiles hold 64 pixels).
+// tw_log2: log2 of the pixel-tile width (3..6; tiles hold 64 pixels).  kept: nullptr for
+// dense work items; for a pixel subsample, the first rows of the kept 8-row blocks, and each
+// item's [row_begin, row_end) indexes this list instead of rows.
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                            int block, int variant, int tw_log2, hipStream_t st);
+                            int block, int variant, int tw_log2, hipStream_t st,
+                            const int* kept = nullptr);
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                              int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                             int block, int variant, int tw_log2, hipStream_t st);
+                             int block, int variant, int tw_log2, hipStream_t st,
+                             const int* kept = nullptr);
+// px_weight scales every image's pixel partials (not its theta-free constant): 1/p for a
+// pixel subsample whose work items cover only the kept rows.
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                               double* elbo, double* grad, double* hess, unsigned long long* px_ctr,
-                              hipStream_t st);
+                              hipStream_t st, double px_weight = 1.0);
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                               double* elbo, unsigned long long* px_ctr, hipStream_t st);
+                               double* elbo, unsigned long long* px_ctr, hipStream_t st,
+                               double px_weight = 1.0);
 
 hipError_t launch_render(const int* tile_off, const int* tile_img, int n_tiles, const ImgDev* imgs,
                          const float* tables, int tstride, int n_exp, int n_dev, int H, int W, int tiles_x,

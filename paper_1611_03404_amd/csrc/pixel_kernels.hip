@@ -1,7 +1,9 @@
 // Pixel-sum kernels: the hot loop of the per-source ELBO (sections III-A/B).
 //
 // One work item = a band of rows of one image; a block takes one work item and
-// its wavefronts walk the band in 8x8 pixel tiles, one pixel per lane.  Per pixel the kernel
+// its wavefronts walk the band in 64-pixel tiles, one pixel per lane.  For a pixel
+// subsample an item is instead a run of the image's kept 8-row blocks (not necessarily
+// adjacent), read through a list of their first rows; tiles never straddle a block.  Per pixel the kernel
 // evaluates the PSF-convolved star mixture and the exp/dev galaxy mixtures with
 // all derivatives needed for the gradient and dense Hessian, forms the mean and
 // variance of the Poisson rate under q, applies the delta-method expected
@@ -160,7 +162,8 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
-                                                     int tw_log2, double* __restrict__ partials) {
+                                                     int tw_log2, const int* __restrict__ kept,
+                                                     double* __restrict__ partials) {
   __shared__ double red[BLOCK / 64][80];
   // per wavefront: [A rows (dT, dU) | B columns (hT, hU)][T or U part][z index][pixel]
   __shared__ __align__(16) float jbuf[MF ? BLOCK / 64 : 1][2][2][MF ? NZ : 1][MF ? JP : 4];
@@ -185,7 +188,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
   const int tiles_x = (w + tw - 1) >> tw_log2;
-  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + th - 1) >> th_log2);
+  // Row blocks: a dense item covers rows [row_begin, row_end); a subsampled item covers the
+  // 8-row blocks kept[row_begin .. row_end) (first rows of kept blocks of the image, in order).
+  const int q_log2 = 3 - th_log2;   // tile rows per 8-row block, log2
+  const int n_rows = kept ? (wi.row_end - wi.row_begin) << 3 : wi.row_end - wi.row_begin;
+  const int row_lim = kept ? im.h : wi.row_end, row_safe = kept ? 0 : wi.row_begin;
+  const int n_tiles = tiles_x * ((n_rows + th - 1) >> th_log2);
   const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
   double val = 0.0;                 // ELBO value, per lane
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // wavefront sums of 5 derivative entries (quad-uniform)
@@ -216,9 +224,11 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
 
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row = wi.row_begin + (ty << th_log2) + lrow, col = (tx << tw_log2) + lcol;
-    const bool live = row < wi.row_end && col < w;
-    const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
+    const int row0 = kept ? kept[wi.row_begin + (ty >> q_log2)] + ((ty & ((1 << q_log2) - 1)) << th_log2)
+                          : wi.row_begin + (ty << th_log2);
+    const int row = row0 + lrow, col = (tx << tw_log2) + lcol;
+    const bool live = row < row_lim && col < w;
+    const int rc = live ? row : row_safe, cc = live ? col : 0;
     const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
     const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
     const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
@@ -488,7 +498,8 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
                                                       const ImgDev* __restrict__ imgs,
                                                       const float* __restrict__ tables, int tstride, int n_exp_rt,
                                                       int n_dev_rt, const int* __restrict__ src_flag,
-                                                      int tw_log2, double* __restrict__ partials) {
+                                                      int tw_log2, const int* __restrict__ kept,
+                                                      double* __restrict__ partials) {
   const int n_exp = NE > 0 ? NE : n_exp_rt, n_dev = NE > 0 ? ND : n_dev_rt;
   __shared__ double red[BLOCK / 64];
   const WorkItem wi = items[blockIdx.x];
@@ -506,14 +517,21 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
   const int tiles_x = (w + tw - 1) >> tw_log2;
-  const int n_tiles = tiles_x * ((wi.row_end - wi.row_begin + th - 1) >> th_log2);
+  // Row blocks: a dense item covers rows [row_begin, row_end); a subsampled item covers the
+  // 8-row blocks kept[row_begin .. row_end) (first rows of kept blocks of the image, in order).
+  const int q_log2 = 3 - th_log2;   // tile rows per 8-row block, log2
+  const int n_rows = kept ? (wi.row_end - wi.row_begin) << 3 : wi.row_end - wi.row_begin;
+  const int row_lim = kept ? im.h : wi.row_end, row_safe = kept ? 0 : wi.row_begin;
+  const int n_tiles = tiles_x * ((n_rows + th - 1) >> th_log2);
   const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
   double acc = 0.0;
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row = wi.row_begin + (ty << th_log2) + lrow, col = (tx << tw_log2) + lcol;
-    const bool live = row < wi.row_end && col < w;
-    const int rc = live ? row : wi.row_begin, cc = live ? col : 0;
+    const int row0 = kept ? kept[wi.row_begin + (ty >> q_log2)] + ((ty & ((1 << q_log2) - 1)) << th_log2)
+                          : wi.row_begin + (ty << th_log2);
+    const int row = row0 + lrow, col = (tx << tw_log2) + lcol;
+    const bool live = row < row_lim && col < w;
+    const int rc = live ? row : row_safe, cc = live ? col : 0;
     const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
     const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
     const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
@@ -559,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
-                            int tw_log2, hipStream_t st) {
+                            int tw_log2, hipStream_t st, const int* kept) {
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
@@ -567,7 +585,7 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
   const dim3 g(n_items);
 #define CELESTE_LAUNCH_FULL(B, W, E, D, M) \
   hipLaunchKernelGGL((k_eval_full<B, W, E, D, M>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, tw_log2, partials)
+                     src_flag, tw_log2, kept, partials)
   if (block == 128) {
     if (mf) {
       if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true);
@@ -591,13 +609,13 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
 
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                              int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
-                             int tw_log2, hipStream_t st) {
+                             int tw_log2, hipStream_t st, const int* kept) {
   if (n_items <= 0) return hipSuccess;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
   const dim3 g(n_items);
 #define CELESTE_LAUNCH_VALUE(B, E, D) \
   hipLaunchKernelGGL((k_eval_value<B, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, tw_log2, partials)
+                     src_flag, tw_log2, kept, partials)
   if (block == 128) {
     if (unroll) CELESTE_LAUNCH_VALUE(128, 6, 8); else CELESTE_LAUNCH_VALUE(128, 0, 0);
   } else {

@@ -5,7 +5,9 @@
 // image's z-space sums are mapped to the 27 natural parameters (theta -> z is
 // linear per image: band colour signs and the WCS matrix), and the closed-form
 // Kullback-Leibler terms of q(a), q(r|a), q(c|a) against their priors
-// (sections III-A/B) are added with their exact gradient and Hessian.
+// (sections III-A/B) are added with their exact gradient and Hessian.  For a pixel
+// subsample the work items cover only the kept rows and px_weight (1/p) scales each
+// image's pixel partials; the theta-free constant of the image is added unscaled.
 #include <math.h>
 
 #include "celeste_internal.h"
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
                                                     const double* __restrict__ theta, PriorDev prior,
                                                     const int* __restrict__ src_flag, double* __restrict__ elbo,
                                                     double* __restrict__ grad, double* __restrict__ hess,
-                                                    unsigned long long* __restrict__ px_ctr) {
+                                                    unsigned long long* __restrict__ px_ctr, double px_weight) {
   __shared__ double tmp[NACC];
   __shared__ double Hz[NZ * NZ];
   __shared__ double Ht[NP * NP];
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
     if (t < NACC) {
       double acc = 0.0;
       for (int it = im.item_begin; it < im.item_end; ++it) acc += partials[(size_t)it * NACC + t];
-      tmp[t] = acc;
+      tmp[t] = acc * px_weight;
     }
     __syncthreads();
     if (t < NZ * NZ) {
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict_
                                                        const double* __restrict__ img_const,
                                                        const double* __restrict__ theta, PriorDev prior,
                                                        const int* __restrict__ src_flag, double* __restrict__ elbo,
-                                                       unsigned long long* __restrict__ px_ctr) {
+                                                       unsigned long long* __restrict__ px_ctr, double px_weight) {
   const int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= n_src) return;
   if (src_flag && !src_flag[s]) return;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict_
     const ImgDev& im = imgs[i];
     double a = 0.0;
     for (int it = im.item_begin; it < im.item_end; ++it) a += partials[it];
-    v += a + img_const[i];
+    v += a * px_weight + img_const[i];
   }
   KL k;
   kl_value_grad(theta + (size_t)s * NP, prior, k);
@@ -226,19 +228,19 @@ hipError_t launch_prior_term(const double* theta, int n_src, PriorDev prior, dou
 hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                               double* elbo, double* grad, double* hess, unsigned long long* px_ctr,
-                              hipStream_t st) {
+                              hipStream_t st, double px_weight) {
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_full, dim3(n_src), dim3(RB), 0, st, srcs, imgs, partials, img_const, theta, prior,
-                     src_flag, elbo, grad, hess, px_ctr);
+                     src_flag, elbo, grad, hess, px_ctr, px_weight);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
-                               double* elbo, unsigned long long* px_ctr, hipStream_t st) {
+                               double* elbo, unsigned long long* px_ctr, hipStream_t st, double px_weight) {
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_value_t, dim3((n_src + 63) / 64), dim3(64), 0, st, srcs, n_src, imgs, partials,
-                     img_const, theta, prior, src_flag, elbo, px_ctr);
+                     img_const, theta, prior, src_flag, elbo, px_ctr, px_weight);
   return hipGetLastError();
 }
 
