@@ -328,6 +328,8 @@ def main():
                          "evaluations of the batched workload")
     ap.add_argument("--keep-prob", type=float, default=0.25,
                     help="sampled workload: probability of keeping each 8-row block of an image")
+    ap.add_argument("--sweep-probs", default="1,0.5,0.25,0.1",
+                    help="sampled workload: further keep probabilities timed besides --keep-prob")
     ap.add_argument("--sweeps", type=int, default=3, help="field workload: sweeps (the maximum with --until-rtol)")
     ap.add_argument("--until-rtol", type=float, default=None,
                     help="field workload: sweep until a sweep raises the joint ELBO by at most this fraction")
@@ -359,8 +361,8 @@ def main():
     if args.probe:
         return probe(args, ctx, log)
     if args.workload == "sampled":
-        if not 0.0 < args.keep_prob <= 1.0:
-            sys.exit("--keep-prob must be in (0, 1]")
+        if not all(0.0 < float(x) <= 1.0 for x in args.sweep_probs.split(",") + [args.keep_prob] if x != ""):
+            sys.exit("--keep-prob and --sweep-probs must be in (0, 1]")
         return sampled_bench(args, ctx, log)
     ctx.set_option(cb.OPT_PROFILE, 1)
     sur_info = None
@@ -538,7 +540,7 @@ def sampled_bench(args, ctx, log):
     K = 3
     E, D = len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0])
     f_full = flop_full_per_px(K, E, D)
-    probs = sorted(set([1.0, 0.5, 0.25, 0.1, args.keep_prob]), reverse=True)
+    probs = sorted(set([float(x) for x in args.sweep_probs.split(",") if x] + [args.keep_prob]), reverse=True)
     sweep = {}
     for i, p in enumerate(probs):
         masks = [block_masks(sb.img_h, p, 161103410 + 97 * i + k) for k in range(args.warmup + args.steps)]
@@ -580,7 +582,7 @@ def sampled_bench(args, ctx, log):
         "config": {"workload": f"batched uneven sources ({sb.n_sources} sources, {sb.n_pixels} px) at the plain "
                                f"start, 8-row blocks kept with probability {args.keep_prob}",
                    "keep_prob": args.keep_prob, "n_sources": sb.n_sources, "n_pixels": sb.n_pixels},
-        "speedup_vs_full_eval": head["source_evals_per_s"] / sweep[1.0]["source_evals_per_s"],
+        "speedup_vs_full_eval": head["source_evals_per_s"] / sweep[1.0]["source_evals_per_s"] if 1.0 in sweep else None,
         "sweep": [{k: v for k, v in r.items() if not k.startswith("_")} for r in sweep.values()],
         "autotune": tune,
         "roofline": {
