@@ -419,7 +419,7 @@ def main():
             log(f"{name} step {k}: {time.perf_counter() - ts:.2f} s, converged {c}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        runs[name] = dict(wall=wall, res=res, conv=conv, stats=ctx.stats())
+        runs[name] = dict(wall=wall, res=res, conv=conv, stats=ctx.stats(), theta=th)
     # ELBO tolerance rule against the best optimum either start reached
     best = np.max(np.stack([r["res"]["elbo"] for r in runs.values()]), axis=0)
 
@@ -503,6 +503,7 @@ def main():
             "counters": counters,
         },
     }
+    out["lr_covariance"] = lr_measure(ctx, batch, runs["plain"]["theta"], sb, log)
     if "plain" in runs and net is not None:
         out["surrogate_gain"] = out["starts"]["surrogate"]["converged_per_s"] / out["starts"]["plain"]["converged_per_s"]
     if not args.no_cpu_baseline:
@@ -600,6 +601,46 @@ def sampled_bench(args, ctx, log):
                                                    args.keep_prob, 161103408)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def lr_measure(ctx, batch, theta, sb, log):
+    """Linear-response covariance of every source at its plain-start fit (box centres = catalog
+    positions, as in that fit), outside the timed steps: the call's wall time, the covariance
+    kernel's HIP-event time, statuses, and how far linear response moves the variances."""
+    import numpy as np
+    import torch
+    S = sb.n_sources
+    u0 = torch.from_numpy(np.asarray(sb.u_cat, dtype=np.float64)).cuda()
+    ctx.stats(reset=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    cov, st = ctx.lr_covariance(batch, theta, u0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    s2 = ctx.stats()
+    c = cov.cpu().numpy()
+    th = theta.cpu().numpy() if hasattr(theta, "cpu") else np.asarray(theta)
+    ok = st == 0
+    idx = np.arange(S)
+    star = th[:, 2] >= 0.5
+    r1, r2 = np.where(star, 7, 8), np.where(star, 9, 10)
+    ratio = c[idx, r1, r1] / th[idx, r2]
+    # as executed: Cholesky n^3/3, inverse of L n^3/3, L^-T L^-1 over all entries 2n^3/3, scalings 3n^2
+    flop = 4 * 27 ** 3 // 3 + 3 * 27 * 27
+    kern_s = s2["ms_lr"] / 1e3
+    info = {
+        "ms_call": 1e3 * wall, "kernel_ms": s2["ms_lr"], "eval_kernel_ms": s2["ms_full"],
+        "sources": S, "status_ok": int(ok.sum()), "not_positive_definite": int(np.sum(st == 1)),
+        "nonfinite": int(np.sum(st == 2)),
+        "median_lr_over_mean_field_var_log_r": float(np.median(ratio[ok])),
+        "p90_lr_over_mean_field_var_log_r": float(np.quantile(ratio[ok], 0.9)),
+        "median_lr_sd_position_px": float(np.median(np.sqrt(c[ok, 0, 0]))),
+        "kernel_gflops": flop * S / kern_s / 1e9 if kern_s > 0 else None,
+        "flop_per_source": flop,
+        "u0": "catalog positions (the plain-start fits' box centres)",
+    }
+    log(f"lr covariance: {info}")
+    return info
 
 
 def field_bench(args, ctx, net, sur_info, log):

@@ -106,6 +106,9 @@ typedef struct celeste_stats {
    * validating the batch on the host, uploading metadata and checking pixels, choosing the start
    * (network, start evaluations), and the iterations' polling and result download */
   double ms_host_pack, ms_prepare, ms_start, ms_loop, ms_results;
+  /* linear-response covariance launches, and their kernel milliseconds (CELESTE_OPT_PROFILE only) */
+  int64_t lr_launches;
+  double ms_lr;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;
@@ -242,6 +245,35 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* batch, const double
 int celeste_elbo_eval_sampled(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
                               const uint8_t* keep, const int64_t* keep_off, double keep_prob,
                               double* elbo, double* grad, double* hess, void* stream);
+
+/* Linear-response covariance of fitted sources (the paper's closing section proposes linear
+ * response methods, after Giordano et al. 2015, because a factorised q under-estimates the
+ * posterior variance and point-estimated parameters get none).  At a fitted theta, tilting the
+ * objective by t theta_i moves the optimum by d theta / dt = Sigma e_i with
+ *   Sigma = D (-H_psi)^{-1} D,   H_psi = D H D + diag(D' g),
+ * where psi are the fit's unconstrained coordinates (position box of half-width u_box around
+ * u0, logistic boxes of a, e_dev, e_axis, e_scale, logs of the variances), D = d theta / d psi
+ * (diagonal), and g, H the natural gradient and Hessian of the ELBO.  A coordinate held at a
+ * box edge gets (near) zero variance; at an interior stationary point Sigma = -H^{-1}.
+ * Entries of u, a, e_*, r1 and c1 are covariances of first moments of q or of point
+ * estimates; rows of r2 and c2 are sensitivities of the variance parameters.  FP64 Cholesky
+ * per source, one wavefront each.
+ *   theta : n x 27 natural coordinates      u0 : n x 2 position-box centres of the fit
+ *   grad  : n x 27, hess : n x 27 x 27 (row-major; symmetrised before use)
+ *   cov   : n x 27 x 27 out, row-major, exactly symmetric; NaN where status != 0
+ *   status: host array of n: 0, 1 (-H_psi not positive definite: no strict local maximum),
+ *           2 (a non-finite input)
+ * theta, u0, grad, hess and cov are in mem_kind memory (CELESTE_MEM_HOST or _DEVICE).
+ * Errors: E_INVALID (NULL pointers, n out of range, u_box not > 0), E_DEVICE, E_NOMEM. */
+int celeste_lr_covariance_from_hessian(celeste_ctx* ctx, int64_t n, int mem_kind, const double* theta,
+                                       const double* u0, double u_box, const double* grad, const double* hess,
+                                       double* cov, int32_t* status, void* stream);
+
+/* The same for every source of a batch, with gradient and Hessian evaluated at theta by the
+ * pixel sum (celeste_elbo_eval) first.  theta, u0 and cov in batch->mem_kind memory; status a
+ * host array of n_sources.  Errors: as celeste_elbo_eval and celeste_lr_covariance_from_hessian. */
+int celeste_lr_covariance(celeste_ctx* ctx, const celeste_batch* batch, const double* theta, const double* u0,
+                          double u_box, double* cov, int32_t* status, void* stream);
 
 /* Trust-region Newton fit of ONE source (batch->n_sources must be 1), host-driven:
  * one host/device round trip per iteration (section III-B).  theta_inout: 27 natural

@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_full", ctypes.c_double), ("ms_reduce_full", ctypes.c_double), ("ms_tr", ctypes.c_double),
                 ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double),
                 ("ms_host_pack", ctypes.c_double), ("ms_prepare", ctypes.c_double), ("ms_start", ctypes.c_double),
-                ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double)]
+                ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double), ("lr_launches", ctypes.c_int64),
+                ("ms_lr", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -105,6 +106,9 @@ def load():
     lib.celeste_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
     lib.celeste_fit_opts_default.restype = None
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
+    lib.celeste_lr_covariance_from_hessian.argtypes = [vp, i64, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp, vp,
+                                                       vp, vp]
+    lib.celeste_lr_covariance.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, ctypes.c_double, vp, vp, vp]
     lib.celeste_elbo_eval_sampled.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, ctypes.c_double, vp, vp, vp,
                                               vp]
     lib.celeste_newton_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp]
@@ -130,6 +134,7 @@ def load():
     lib.celeste_update_fields.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, ctypes.POINTER(CFields)]
     lib.celeste_field_elbo.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(CFields), vp, vp, vp]
     for name in ("celeste_ctx_create", "celeste_ctx_set_option", "celeste_elbo_eval", "celeste_elbo_eval_sampled",
+                 "celeste_lr_covariance", "celeste_lr_covariance_from_hessian",
                  "celeste_newton_fit",
                  "celeste_batch_fit", "celeste_ctx_get_stats", "celeste_net_create", "celeste_net_get_params",
                  "celeste_net_loss_grad", "celeste_net_forward", "celeste_net_train", "celeste_make_patches",
@@ -378,6 +383,47 @@ class Context:
                                                 _ptr(grad) if grad is not None else None,
                                                 _ptr(hess) if hess is not None else None, self._stream(batch)))
         return elbo, grad, hess
+
+    def lr_covariance(self, batch: Batch, theta, u0, u_box=3.0):
+        """Linear-response covariance (S, 27, 27) at theta, with the gradient and Hessian
+        evaluated by the pixel sum; u0 (S, 2) are the fits' position-box centres.  Returns
+        (cov, status) with status (S,) int32 on the host."""
+        S = batch.n_sources
+        th = batch.as_input(theta)
+        uu = batch.as_input(u0)
+        if tuple(th.shape) != (S, NP) or tuple(uu.shape) != (S, 2):
+            raise ValueError(f"theta must have shape ({S}, {NP}) and u0 ({S}, 2)")
+        cov = batch.array((S, NP, NP))
+        status = np.zeros(S, dtype=np.int32)
+        _check(load().celeste_lr_covariance(self._h, ctypes.byref(batch.c), _ptr(th), _ptr(uu), float(u_box),
+                                            _ptr(cov), status.ctypes.data, self._stream(batch)))
+        return cov, status
+
+    def lr_covariance_from_hessian(self, theta, u0, grad, hess, u_box=3.0):
+        """The same from given natural gradients (n, 27) and Hessians (n, 27, 27): NumPy arrays
+        (host memory) or CUDA tensors (device memory), all of one kind."""
+        dev = _is_torch(theta) and theta.is_cuda
+        if dev:
+            import torch
+            arrs = [x.to(torch.float64).contiguous() for x in (theta, u0, grad, hess)]
+            torch.cuda.synchronize(arrs[0].device)
+        else:
+            arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (theta, u0, grad, hess)]
+        th, uu, g, H = arrs
+        n = th.shape[0]
+        if tuple(th.shape) != (n, NP) or tuple(uu.shape) != (n, 2) or tuple(g.shape) != (n, NP) \
+                or tuple(H.shape) != (n, NP, NP):
+            raise ValueError("theta (n, 27), u0 (n, 2), grad (n, 27), hess (n, 27, 27) expected")
+        if dev:
+            import torch
+            cov = torch.empty((n, NP, NP), dtype=torch.float64, device=th.device)
+        else:
+            cov = np.empty((n, NP, NP), dtype=np.float64)
+        status = np.zeros(n, dtype=np.int32)
+        _check(load().celeste_lr_covariance_from_hessian(self._h, n, MEM_DEVICE if dev else MEM_HOST, _ptr(th),
+                                                         _ptr(uu), float(u_box), _ptr(g), _ptr(H), _ptr(cov),
+                                                         status.ctypes.data, None))
+        return cov, status
 
     def newton_fit(self, batch: Batch, theta0, opts=None):
         if batch.n_sources != 1:

@@ -83,6 +83,7 @@ struct celeste_ctx {
   DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
   DevBuf tables2, fsky;                            // second setup table (field updates), field skies
   DevBuf kept;                                     // first rows of the kept blocks of a pixel subsample
+  DevBuf lr_in, lr_cov, lr_status, lr_eval;        // linear-response covariance staging
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
 
@@ -606,7 +607,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
                     &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
-                    &c->kept};
+                    &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
@@ -679,6 +680,73 @@ int celeste_elbo_eval_sampled(celeste_ctx* ctx, const celeste_batch* b, const do
   if (!keep || !keep_off) return fail(CELESTE_E_INVALID, "keep and keep_off must not be NULL");
   if (!(keep_prob > 0.0 && keep_prob <= 1.0)) return fail(CELESTE_E_INVALID, "keep_prob must be in (0, 1]");
   return eval_impl(ctx, b, theta, elbo, grad, hess, stream, keep, keep_off, keep_prob);
+}
+
+int celeste_lr_covariance_from_hessian(celeste_ctx* ctx, int64_t n, int mem_kind, const double* theta,
+                                       const double* u0, double u_box, const double* grad, const double* hess,
+                                       double* cov, int32_t* status, void* stream) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  if (n < 0 || n > (int64_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "n out of range");
+  if (mem_kind != CELESTE_MEM_HOST && mem_kind != CELESTE_MEM_DEVICE)
+    return fail(CELESTE_E_INVALID, "mem_kind must be CELESTE_MEM_HOST or CELESTE_MEM_DEVICE");
+  if (!theta || !u0 || !grad || !hess || !cov || !status) return fail(CELESTE_E_INVALID, "NULL argument");
+  if (!(u_box > 0.0) || !std::isfinite(u_box)) return fail(CELESTE_E_INVALID, "u_box must be finite and > 0");
+  if (n == 0) return CELESTE_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const hipStream_t st = pick(ctx, stream);
+  const size_t S = (size_t)n;
+  const double *d_th = theta, *d_u0 = u0, *d_g = grad, *d_h = hess;
+  double* d_cov = cov;
+  if (mem_kind == CELESTE_MEM_HOST) {
+    CHK(ensure(ctx->lr_in, sizeof(double) * S * (NP + 2 + NP + NP * NP)));
+    double* base = as<double>(ctx->lr_in);
+    double *th = base, *uu = th + S * NP, *gg = uu + S * 2, *hh = gg + S * NP;
+    HIPCHK(hipMemcpyAsync(th, theta, sizeof(double) * S * NP, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(uu, u0, sizeof(double) * S * 2, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(gg, grad, sizeof(double) * S * NP, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(hh, hess, sizeof(double) * S * NP * NP, hipMemcpyHostToDevice, st));
+    d_th = th;
+    d_u0 = uu;
+    d_g = gg;
+    d_h = hh;
+    CHK(ensure(ctx->lr_cov, sizeof(double) * S * NP * NP));
+    d_cov = as<double>(ctx->lr_cov);
+  }
+  CHK(ensure(ctx->lr_status, sizeof(int) * S));
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
+  T.mark(0, st);
+  HIPCHK(launch_lr_cov(d_th, d_u0, u_box, d_g, d_h, (int)S, d_cov, as<int>(ctx->lr_status), st));
+  T.mark(1, st);
+  if (mem_kind == CELESTE_MEM_HOST)
+    HIPCHK(hipMemcpyAsync(cov, d_cov, sizeof(double) * S * NP * NP, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(status, ctx->lr_status.p, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->stats.lr_launches += 1;
+  if (T.on) ctx->stats.ms_lr += T.span(0, 1);
+  return CELESTE_OK;
+}
+
+int celeste_lr_covariance(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const double* u0,
+                          double u_box, double* cov, int32_t* status, void* stream) {
+  if (!ctx || !b) return fail(CELESTE_E_INVALID, "context or batch is NULL");
+  if (!theta || !u0 || !cov || !status) return fail(CELESTE_E_INVALID, "NULL argument");
+  if (b->n_sources < 1) return fail(CELESTE_E_INVALID, "n_sources must be >= 1");
+  if (!(u_box > 0.0) || !std::isfinite(u_box)) return fail(CELESTE_E_INVALID, "u_box must be finite and > 0");
+  const size_t S = (size_t)b->n_sources;
+  if (b->mem_kind == CELESTE_MEM_HOST) {
+    std::vector<double> e(S), g(S * NP), h(S * NP * NP);
+    CHK(eval_impl(ctx, b, theta, e.data(), g.data(), h.data(), stream, nullptr, nullptr, 1.0));
+    return celeste_lr_covariance_from_hessian(ctx, (int64_t)S, CELESTE_MEM_HOST, theta, u0, u_box, g.data(),
+                                              h.data(), cov, status, stream);
+  }
+  CHK(ensure(ctx->lr_eval, sizeof(double) * S * (1 + NP + NP * NP)));
+  double* e = as<double>(ctx->lr_eval);
+  double* g = e + S;
+  double* h = g + S * NP;
+  CHK(eval_impl(ctx, b, theta, e, g, h, stream, nullptr, nullptr, 1.0));
+  return celeste_lr_covariance_from_hessian(ctx, (int64_t)S, CELESTE_MEM_DEVICE, theta, u0, u_box, g, h, cov, status,
+                                            stream);
 }
 
 }  // extern "C"

@@ -176,5 +176,9 @@ hipError_t launch_plain_init(const SrcDev* srcs, int n_src, const ImgDev* imgs, 
 hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+// Linear-response covariance per source from the natural gradient and Hessian at theta (u0:
+// S x 2 position-box centres of the fit's coordinates); cov S x 27 x 27, status S.
+hipError_t launch_lr_cov(const double* theta, const double* u0, double u_box, const double* grad, const double* hess,
+                         int n_src, double* cov, int* status, hipStream_t s);
 
 }  // namespace celeste

@@ -431,6 +431,96 @@ __global__ void k_zero(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// ---------------------------------------------------------------- linear-response covariance
+// Sigma = D (-H_psi)^{-1} D at a fitted theta, H_psi = D H D + diag(D' g) in the fit's
+// unconstrained coordinates (D = d theta / d psi, diagonal), one wavefront per source, FP64:
+// Cholesky factor L of -H_psi in LDS (right-looking, one column per step, the trailing
+// update spread over the lanes), L^{-1} by forward substitution (one column per lane), and
+// Sigma_psi = L^{-T} L^{-1} summed in the same order for (a, b) and (b, a), so the result is
+// exactly symmetric.  status: 0, 1 when a pivot is not positive (-H_psi not positive
+// definite), 2 for a non-finite input; cov is NaN where status != 0.
+__global__ __launch_bounds__(64) void k_lr_cov(const double* __restrict__ theta, const double* __restrict__ u0s,
+                                               double u_box, const double* __restrict__ grad,
+                                               const double* __restrict__ hess, double* __restrict__ cov,
+                                               int* __restrict__ status) {
+  __shared__ double M[NP][NP + 1];
+  __shared__ double W[NP][NP + 1];
+  __shared__ double d1s[NP];
+  __shared__ int bad;
+  const int s = blockIdx.x, t = threadIdx.x;
+  const double* th = theta + (size_t)s * NP;
+  const double* g = grad + (size_t)s * NP;
+  const double* H = hess + (size_t)s * NP * NP;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  double d2g = 0.0;
+  if (t < NP) {
+    const double u0[2] = {u0s[2 * s], u0s[2 * s + 1]};
+    const Box b = box_of(t, u0, u_box);
+    double d1, d2;
+    to_theta1(to_psi1(th[t], b), b, &d1, &d2);
+    d1s[t] = d1;
+    d2g = d2 * g[t];
+    if (!isfinite(th[t]) || !isfinite(g[t]) || !isfinite(u0[0]) || !isfinite(u0[1])) atomicOr(&bad, 2);
+  }
+  __syncthreads();
+  for (int k = t; k < NP * NP; k += 64) {
+    const int r = k / NP, c = k - r * NP;
+    const double h = 0.5 * (H[r * NP + c] + H[c * NP + r]);
+    if (!isfinite(h)) atomicOr(&bad, 2);
+    M[r][c] = -(d1s[r] * h * d1s[c]);
+  }
+  __syncthreads();
+  if (t < NP) M[t][t] -= d2g;
+  __syncthreads();
+  if (bad == 0) {
+    for (int k = 0; k < NP; ++k) {
+      const double piv = M[k][k];
+      if (!(piv > 0.0) || !isfinite(piv)) {   // the same value on every lane: a uniform exit
+        if (t == 0) bad = 1;
+        break;
+      }
+      const double lkk = sqrt(piv);
+      __syncthreads();
+      if (t == k) M[k][k] = lkk;
+      if (t > k && t < NP) M[t][k] /= lkk;
+      __syncthreads();
+      for (int e = t; e < NP * NP; e += 64) {
+        const int i = e / NP, j = e - i * NP;
+        if (j > k && i >= j) M[i][j] -= M[i][k] * M[j][k];
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  double* out = cov + (size_t)s * NP * NP;
+  if (bad != 0) {
+    for (int k = t; k < NP * NP; k += 64) out[k] = __builtin_nan("");
+    if (t == 0) status[s] = bad;
+    return;
+  }
+  if (t < NP) {
+    const int j = t;
+    for (int i = 0; i < NP; ++i) {
+      if (i < j) {
+        W[i][j] = 0.0;
+        continue;
+      }
+      double acc = i == j ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) acc -= M[i][k] * W[k][j];
+      W[i][j] = acc / M[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < NP * NP; e += 64) {
+    const int a = e / NP, b = e - a * NP;
+    double acc = 0.0;
+    for (int k = a > b ? a : b; k < NP; ++k) acc += W[k][a] * W[k][b];
+    out[e] = acc * (d1s[a] * d1s[b]);   // the same rounding for (a, b) and (b, a)
+  }
+  if (t == 0) status[s] = 0;
+}
+
 }  // namespace
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s) {
@@ -462,6 +552,13 @@ hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s) {
 
 hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s) {
   hipLaunchKernelGGL(k_accept, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_lr_cov(const double* theta, const double* u0, double u_box, const double* grad, const double* hess,
+                         int n_src, double* cov, int* status, hipStream_t s) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lr_cov, dim3(n_src), dim3(64), 0, s, theta, u0, u_box, grad, hess, cov, status);
   return hipGetLastError();
 }
 
