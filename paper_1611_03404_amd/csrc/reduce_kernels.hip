@@ -110,6 +110,42 @@ __device__ inline double kl_hess(const double* th, const PriorDev& pr, const KL&
 
 constexpr int RB = 128;
 
+// Adds one z-space sum (tmp: value, 11 gradient, 66 Hessian entries, in LDS) mapped to the 27
+// natural parameters through the map of (band, WCS matrix) to Ht / gt.  All threads; tmp
+// must be complete on entry (barrier before the call); ends with a barrier.
+__device__ inline void project_add(const double* tmp, int band, const double* wcs, double* Hz, double* Ht,
+                                   double* gt) {
+  const int t = threadIdx.x;
+  if (t < NZ * NZ) {
+    const int a = t / NZ, b = t - a * NZ;
+    Hz[t] = tmp[1 + NZ + (a <= b ? tri(a, b) : tri(b, a))];
+  }
+  __syncthreads();
+  for (int k = t; k < NP * NP; k += RB) {
+    const int r = k / NP, c = k - r * NP;
+    int zr[2], zc[2];
+    double cr[2], cc[2];
+    const int nr = theta_to_z(r, band, wcs, zr, cr);
+    const int nc = theta_to_z(c, band, wcs, zc, cc);
+    double h = 0.0;
+    for (int u = 0; u < nr; ++u)
+      for (int v = 0; v < nc; ++v) h += cr[u] * cc[v] * Hz[zr[u] * NZ + zc[v]];
+    Ht[k] += h;
+  }
+  if (t < NP) {
+    int zr[2];
+    double cr[2];
+    const int nr = theta_to_z(t, band, wcs, zr, cr);
+    double g = 0.0;
+    for (int u = 0; u < nr; ++u) g += cr[u] * tmp[1 + zr[u]];
+    gt[t] += g;
+  }
+  __syncthreads();
+}
+
+// The map theta -> z of an image depends only on its band and the linear part of its WCS, so
+// the z-space sums of the images that share the source's first WCS matrix are added per band
+// first and mapped once per band; images with another WCS matrix are mapped one by one.
 __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ srcs, const ImgDev* __restrict__ imgs,
                                                     const double* __restrict__ partials,
                                                     const double* __restrict__ img_const,
@@ -118,6 +154,7 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
                                                     double* __restrict__ grad, double* __restrict__ hess,
                                                     unsigned long long* __restrict__ px_ctr, double px_weight) {
   __shared__ double tmp[NACC];
+  __shared__ double grp[5][NACC];
   __shared__ double Hz[NZ * NZ];
   __shared__ double Ht[NP * NP];
   __shared__ double gt[NP];
@@ -129,43 +166,38 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
   const double* th = theta + (size_t)s * NP;
   for (int k = t; k < NP * NP; k += RB) Ht[k] = 0.0;
   if (t < NP) gt[t] = 0.0;
+  if (t < NACC)
+    for (int b = 0; b < 5; ++b) grp[b][t] = 0.0;
   if (t == 0) vt = 0.0;
   __syncthreads();
   const SrcDev sr = srcs[s];
+  const double* wref = imgs[sr.img_begin].wcs;
+  unsigned used = 0;   // bands with images in grp (the same on every thread)
   for (int i = sr.img_begin; i < sr.img_end; ++i) {
     const ImgDev& im = imgs[i];
+    double acc = 0.0;
     if (t < NACC) {
-      double acc = 0.0;
       for (int it = im.item_begin; it < im.item_end; ++it) acc += partials[(size_t)it * NACC + t];
-      tmp[t] = acc * px_weight;
+      acc *= px_weight;
     }
+    if (t == 0) vt += img_const[i];
+    const bool shared = im.wcs[0] == wref[0] && im.wcs[1] == wref[1] && im.wcs[2] == wref[2] && im.wcs[3] == wref[3];
+    if (shared) {
+      if (t < NACC) grp[im.band][t] += acc;   // each thread owns its entry: no barrier needed
+      used |= 1u << im.band;
+    } else {
+      if (t < NACC) tmp[t] = acc;
+      __syncthreads();
+      if (t == 0) vt += tmp[0];
+      project_add(tmp, im.band, im.wcs, Hz, Ht, gt);
+    }
+  }
+  for (int b = 0; b < 5; ++b) {
+    if (!(used & (1u << b))) continue;
+    if (t < NACC) tmp[t] = grp[b][t];
     __syncthreads();
-    if (t < NZ * NZ) {
-      const int a = t / NZ, b = t - a * NZ;
-      Hz[t] = tmp[1 + NZ + (a <= b ? tri(a, b) : tri(b, a))];
-    }
-    __syncthreads();
-    for (int k = t; k < NP * NP; k += RB) {
-      const int r = k / NP, c = k - r * NP;
-      int zr[2], zc[2];
-      double cr[2], cc[2];
-      const int nr = theta_to_z(r, im.band, im.wcs, zr, cr);
-      const int nc = theta_to_z(c, im.band, im.wcs, zc, cc);
-      double h = 0.0;
-      for (int u = 0; u < nr; ++u)
-        for (int v = 0; v < nc; ++v) h += cr[u] * cc[v] * Hz[zr[u] * NZ + zc[v]];
-      Ht[k] += h;
-    }
-    if (t < NP) {
-      int zr[2];
-      double cr[2];
-      const int nr = theta_to_z(t, im.band, im.wcs, zr, cr);
-      double g = 0.0;
-      for (int u = 0; u < nr; ++u) g += cr[u] * tmp[1 + zr[u]];
-      gt[t] += g;
-    }
-    if (t == 0) vt += tmp[0] + img_const[i];
-    __syncthreads();
+    if (t == 0) vt += tmp[0];
+    project_add(tmp, b, wref, Hz, Ht, gt);
   }
   if (t == 0) kl_value_grad(th, prior, kl);
   __syncthreads();
