@@ -84,6 +84,8 @@ struct celeste_ctx {
   DevBuf tables2, fsky;                            // second setup table (field updates), field skies
   DevBuf kept;                                     // first rows of the kept blocks of a pixel subsample
   DevBuf lr_in, lr_cov, lr_status, lr_eval;        // linear-response covariance staging
+  DevBuf lfact;                                    // log n! table of the pixel constants
+  bool lfact_ready = false;
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
 
@@ -495,13 +497,18 @@ int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st,
     HIPCHK(hipStreamSynchronize(st));
     return CELESTE_OK;
   }
+  if (!ctx->lfact_ready) {
+    CHK(ensure(ctx->lfact, sizeof(double) * LFACT_N));
+    HIPCHK(launch_lfact(as<double>(ctx->lfact), st));
+    ctx->lfact_ready = true;   // complete before first use: the check below synchronises the stream
+  }
   HIPCHK(launch_zero_int(as<int>(ctx->flag), 4, st));
-  HIPCHK(launch_check_pixels(as<ImgDev>(ctx->imgs), P->n_img, as<int>(ctx->flag), st));
+  HIPCHK(launch_check_const(as<ImgDev>(ctx->imgs), P->n_img, as<double>(ctx->lfact), as<double>(ctx->img_const),
+                            as<int>(ctx->flag), st));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (bad) return fail(CELESTE_E_INVALID, "pixel or neighbour arrays hold negative or non-finite values");
-  HIPCHK(launch_const(as<ImgDev>(ctx->imgs), P->n_img, as<double>(ctx->img_const), st));
   return CELESTE_OK;
 }
 
@@ -607,7 +614,8 @@ void celeste_ctx_destroy(celeste_ctx* c) {
   DevBuf* bufs[] = {&c->imgs, &c->items, &c->srcs, &c->tables, &c->partials, &c->img_const, &c->staging,
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
                     &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
-                    &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval};
+                    &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval,
+                    &c->lfact};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})

@@ -90,8 +90,13 @@ inline int table_stride(int max_psf, int n_exp, int n_dev) {
 // ---------------------------------------------------------------- launch wrappers
 hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, const int* src_flag,
                         ProfDev prof, float* tables, int tstride, hipStream_t st);
-hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStream_t st);
-hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st);
+// log n! table for the theta-independent pixel constants (LFACT_N doubles), and the pass that
+// checks every pixel / neighbour value (bad |= 1 on a negative or non-finite one) and writes
+// each image's constant sum x log E_bg - E_bg - log x!.
+constexpr int LFACT_N = 1 << 16;
+hipError_t launch_lfact(double* table, hipStream_t st);
+hipError_t launch_check_const(const ImgDev* imgs, int n_img, const double* lfact, double* img_const, int* bad,
+                              hipStream_t st);
 // tw_log2: log2 of the pixel-tile width (3..6; tiles hold 64 pixels).  kept: nullptr for
 // dense work items; for a pixel subsample, the first rows of the kept 8-row blocks, and each
 // item's [row_begin, row_end) indexes this list instead of rows.

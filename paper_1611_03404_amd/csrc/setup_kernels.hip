@@ -219,44 +219,54 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// theta-independent part of the pixel term: sum x log E_bg - E_bg - lgamma(x + 1).
-__global__ __launch_bounds__(256) void k_const(const ImgDev* __restrict__ imgs, double* __restrict__ out) {
+// log n! for the integer counts below LFACT_N, filled with the device's own lgamma(n + 1).
+__global__ __launch_bounds__(256) void k_lfact(double* __restrict__ t) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < LFACT_N) t[i] = lgamma((double)i + 1.0);
+}
+
+// One pass over every pixel of an image (one block per image): flags any negative or
+// non-finite pixel / neighbour value, and sums the theta-independent part of the pixel term,
+// x log E_bg - E_bg - log x!, E_bg = sky + neighbour mean.  log x! of an integer count below
+// LFACT_N is read from the table (the same value lgamma gives); without neighbour arrays E_bg
+// is the sky at every pixel, so the first two terms are log(sky) sum x - n sky.
+__global__ __launch_bounds__(256) void k_check_const(const ImgDev* __restrict__ imgs, const double* __restrict__ lfact,
+                                                     double* __restrict__ out, int* __restrict__ bad) {
   __shared__ double sh[4];
   const ImgDev& im = imgs[blockIdx.x];
   const int n = im.h * im.w;
-  double acc = 0.0;
+  double acc = 0.0, sx = 0.0;
+  int cnt = 0, flag = 0;
   for (int m = threadIdx.x; m < n; m += 256) {
     const int r = m / im.w, c = m - r * im.w;
     const size_t o = (size_t)r * im.pitch + c;
     const size_t on = (size_t)r * im.nbr_pitch + c;
-    const double x = im.pix[o];
-    const double ebg = im.sky + (im.nbr_mean ? (double)im.nbr_mean[on] : 0.0);
-    acc += x * log(ebg) - ebg - lgamma(x + 1.0);
-  }
-  const double tot = block_sum<256>(acc, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = tot;
-}
-
-// Flags any negative or non-finite pixel / neighbour value.
-__global__ __launch_bounds__(256) void k_check(const ImgDev* __restrict__ imgs, int* __restrict__ bad) {
-  const ImgDev& im = imgs[blockIdx.x];
-  const int n = im.h * im.w;
-  int flag = 0;
-  for (int m = threadIdx.x; m < n; m += 256) {
-    const int r = m / im.w, c = m - r * im.w;
-    const size_t o = (size_t)r * im.pitch + c;
-    const size_t on = (size_t)r * im.nbr_pitch + c;
-    const float x = im.pix[o];
-    if (!(x >= 0.0f) || !isfinite(x)) flag = 1;
+    const float xf = im.pix[o];
+    if (!(xf >= 0.0f) || !isfinite(xf)) flag = 1;
+    const double x = xf;
+    double lg;
+    if (x >= 0.0 && x < (double)LFACT_N && x == (double)(int)x)
+      lg = lfact[(int)x];
+    else
+      lg = lgamma(x + 1.0);
     if (im.nbr_mean) {
       const float e = im.nbr_mean[on];
       if (!(e >= 0.0f) || !isfinite(e)) flag = 1;
+      const double ebg = im.sky + (double)e;
+      acc += x * log(ebg) - ebg - lg;
+    } else {
+      sx += x;
+      ++cnt;
+      acc -= lg;
     }
     if (im.nbr_var) {
       const float v = im.nbr_var[on];
       if (!(v >= 0.0f) || !isfinite(v)) flag = 1;
     }
   }
+  if (!im.nbr_mean) acc += log(im.sky) * sx - (double)cnt * im.sky;
+  const double tot = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
   if (flag) atomicOr(bad, 1);
 }
 
@@ -324,15 +334,15 @@ hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, cons
   return hipGetLastError();
 }
 
-hipError_t launch_const(const ImgDev* imgs, int n_img, double* img_const, hipStream_t st) {
-  if (n_img <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_const, dim3(n_img), dim3(256), 0, st, imgs, img_const);
+hipError_t launch_lfact(double* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_lfact, dim3((LFACT_N + 255) / 256), dim3(256), 0, st, table);
   return hipGetLastError();
 }
 
-hipError_t launch_check_pixels(const ImgDev* imgs, int n_img, int* bad, hipStream_t st) {
+hipError_t launch_check_const(const ImgDev* imgs, int n_img, const double* lfact, double* img_const, int* bad,
+                              hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check, dim3(n_img), dim3(256), 0, st, imgs, bad);
+  hipLaunchKernelGGL(k_check_const, dim3(n_img), dim3(256), 0, st, imgs, lfact, img_const, bad);
   return hipGetLastError();
 }
 
