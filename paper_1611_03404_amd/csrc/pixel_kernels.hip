@@ -1,9 +1,10 @@
 // Pixel-sum kernels: the hot loop of the per-source ELBO (sections III-A/B).
 //
 // One work item = a band of rows of one image; a block takes one work item and
-// its wavefronts walk the band in 64-pixel tiles, one pixel per lane.  For a pixel
-// subsample an item is instead a run of the image's kept 8-row blocks (not necessarily
-// adjacent), read through a list of their first rows; tiles never straddle a block.  Per pixel the kernel
+// its wavefronts walk the band in 64-pixel tiles, one pixel per lane (by default 8-row bands
+// in column-major order, so tiles are 8 x 8 squares packed without gaps at the image's right
+// edge; see TileMap).  For a pixel subsample an item is instead a run of the image's kept
+// 8-row blocks (not necessarily adjacent), read through a list of their first rows.  Per pixel the kernel
 // evaluates the PSF-convolved star mixture and the exp/dev galaxy mixtures with
 // all derivatives needed for the gradient and dense Hessian, forms the mean and
 // variance of the Poisson rate under q, applies the delta-method expected
@@ -120,6 +121,79 @@ __device__ __forceinline__ void gal_value(const float* __restrict__ r, float dxx
   acc += ex2(fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0]))));
 }
 
+// Pixel -> lane layout of a work item.  Unpacked (tile width 16, 32 or 64): a grid of
+// tw x (64 / tw) tiles over the item's rows; lanes past the image edge are dead.  Packed (tile
+// width 8): the item's rows as 8-row bands (the image's last band may be shorter), each band's
+// pixels in column-major order and the bands back to back; a tile is 64 consecutive pixels of
+// that order, an 8 x 8 square except where it wraps from one band into the next, and only the
+// item's last tile has dead lanes.  Bands are row_begin + 8 b for a dense item and the kept
+// blocks kept[row_begin + b] for a subsampled one.
+struct TileMap {
+  bool packed;
+  int w, rb, tw_log2, th_log2, tiles_x, q_log2, row_lim, row_safe, n_tiles;
+  int nb, hl, bw, npx;
+  float inv_bw, inv_hl;
+  const int* kept;
+
+  __device__ __forceinline__ TileMap(const WorkItem& wi, int w_, int h, int tw_log2_, const int* kept_) {
+    w = w_;
+    rb = wi.row_begin;
+    kept = kept_;
+    tw_log2 = tw_log2_;
+    th_log2 = 6 - tw_log2;
+    packed = tw_log2 == 3;
+    row_lim = kept ? h : wi.row_end;
+    row_safe = kept ? 0 : wi.row_begin;
+    tiles_x = (w + (1 << tw_log2) - 1) >> tw_log2;
+    q_log2 = 3 - th_log2;
+    nb = kept ? wi.row_end - wi.row_begin : (wi.row_end - wi.row_begin + 7) >> 3;
+    const int r_last = kept ? kept[wi.row_end - 1] : wi.row_begin + ((nb - 1) << 3);
+    hl = min(8, row_lim - r_last);
+    bw = w << 3;
+    npx = (nb - 1) * bw + hl * w;
+    inv_bw = 1.0f / (float)bw;
+    inv_hl = 1.0f / (float)hl;
+    if (packed) {
+      n_tiles = (npx + 63) >> 6;
+    } else {
+      const int n_rows = kept ? nb << 3 : wi.row_end - wi.row_begin;
+      n_tiles = tiles_x * ((n_rows + (1 << th_log2) - 1) >> th_log2);
+    }
+  }
+
+  // row, column and liveness of this lane's pixel in tile t; dead lanes get an in-image pixel
+  __device__ __forceinline__ void pixel(int t, int lane, int& row, int& col, bool& live) const {
+    if (packed) {
+      const int q = (t << 6) + lane;
+      live = q < npx;
+      const int qc = live ? q : 0;
+      int b = (int)(((float)qc + 0.5f) * inv_bw);   // within one of the true band index
+      b -= (b * bw > qc) ? 1 : 0;
+      b += ((b + 1) * bw <= qc) ? 1 : 0;
+      b = min(b, nb - 1);
+      const int qq = qc - b * bw;
+      const bool full = b < nb - 1;
+      int cl = (int)(((float)qq + 0.5f) * inv_hl);   // within one of qq / hl
+      cl -= (cl * hl > qq) ? 1 : 0;
+      cl += ((cl + 1) * hl <= qq) ? 1 : 0;
+      col = full ? qq >> 3 : cl;
+      const int r = full ? (qq & 7) : qq - cl * hl;
+      row = (kept ? kept[rb + b] : rb + (b << 3)) + r;
+    } else {
+      const int ty = t / tiles_x, tx = t - ty * tiles_x;
+      const int row0 = kept ? kept[rb + (ty >> q_log2)] + ((ty & ((1 << q_log2) - 1)) << th_log2)
+                            : rb + (ty << th_log2);
+      row = row0 + (lane >> tw_log2);
+      col = (tx << tw_log2) + (lane & ((1 << tw_log2) - 1));
+      live = row < row_lim && col < w;
+      if (!live) {
+        row = row_safe;
+        col = 0;
+      }
+    }
+  }
+};
+
 constexpr int tri(int i, int j) { return i * NZ - (i * (i - 1)) / 2 + (j - i); }
 
 // Wavefront sum of 80 lane values by recursive halving (masks 32, 16, 8, 4) and a
@@ -186,15 +260,8 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   const float io2 = io * io, io3 = io2 * io;
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
-  const int tiles_x = (w + tw - 1) >> tw_log2;
-  // Row blocks: a dense item covers rows [row_begin, row_end); a subsampled item covers the
-  // 8-row blocks kept[row_begin .. row_end) (first rows of kept blocks of the image, in order).
-  const int q_log2 = 3 - th_log2;   // tile rows per 8-row block, log2
-  const int n_rows = kept ? (wi.row_end - wi.row_begin) << 3 : wi.row_end - wi.row_begin;
-  const int row_lim = kept ? im.h : wi.row_end, row_safe = kept ? 0 : wi.row_begin;
-  const int n_tiles = tiles_x * ((n_rows + th - 1) >> th_log2);
-  const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
+  const TileMap tm(wi, w, im.h, tw_log2, kept);
+  const int n_tiles = tm.n_tiles;
   double val = 0.0;                 // ELBO value, per lane
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // wavefront sums of 5 derivative entries (quad-uniform)
   const int base5 = quad_base(lane);              // first of the 5 entries this lane's quad holds
@@ -223,15 +290,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
   };
 
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row0 = kept ? kept[wi.row_begin + (ty >> q_log2)] + ((ty & ((1 << q_log2) - 1)) << th_log2)
-                          : wi.row_begin + (ty << th_log2);
-    const int row = row0 + lrow, col = (tx << tw_log2) + lcol;
-    const bool live = row < row_lim && col < w;
-    const int rc = live ? row : row_safe, cc = live ? col : 0;
-    const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
-    const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
-    const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
+    int row, col;
+    bool live;
+    tm.pixel(t, lane, row, col, live);   // (row, col) is inside the image on every lane
+    const float x = live ? pix[(size_t)row * pitch + col] : 0.f;
+    const float ebg = sky + (nbrE && live ? nbrE[(size_t)row * npitch + col] : 0.f);
+    const float vbg = nbrV && live ? nbrV[(size_t)row * npitch + col] : 0.f;
     const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
 
     // ---- star: N, dN/dp, d2N/dp2
@@ -515,26 +579,16 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   const float ed = T[EDEV];
   const float cs = T[CS], cg = T[CG], Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tw = 1 << tw_log2, th_log2 = 6 - tw_log2, th = 1 << th_log2;   // tile of tw x th = 64 pixels
-  const int tiles_x = (w + tw - 1) >> tw_log2;
-  // Row blocks: a dense item covers rows [row_begin, row_end); a subsampled item covers the
-  // 8-row blocks kept[row_begin .. row_end) (first rows of kept blocks of the image, in order).
-  const int q_log2 = 3 - th_log2;   // tile rows per 8-row block, log2
-  const int n_rows = kept ? (wi.row_end - wi.row_begin) << 3 : wi.row_end - wi.row_begin;
-  const int row_lim = kept ? im.h : wi.row_end, row_safe = kept ? 0 : wi.row_begin;
-  const int n_tiles = tiles_x * ((n_rows + th - 1) >> th_log2);
-  const int lrow = lane >> tw_log2, lcol = lane & (tw - 1);
+  const TileMap tm(wi, w, im.h, tw_log2, kept);
+  const int n_tiles = tm.n_tiles;
   double acc = 0.0;
   for (int t = wv; t < n_tiles; t += BLOCK / 64) {
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int row0 = kept ? kept[wi.row_begin + (ty >> q_log2)] + ((ty & ((1 << q_log2) - 1)) << th_log2)
-                          : wi.row_begin + (ty << th_log2);
-    const int row = row0 + lrow, col = (tx << tw_log2) + lcol;
-    const bool live = row < row_lim && col < w;
-    const int rc = live ? row : row_safe, cc = live ? col : 0;
-    const float x = live ? pix[(size_t)rc * pitch + cc] : 0.f;
-    const float ebg = sky + (nbrE && live ? nbrE[(size_t)rc * npitch + cc] : 0.f);
-    const float vbg = nbrV && live ? nbrV[(size_t)rc * npitch + cc] : 0.f;
+    int row, col;
+    bool live;
+    tm.pixel(t, lane, row, col, live);   // (row, col) is inside the image on every lane
+    const float x = live ? pix[(size_t)row * pitch + col] : 0.f;
+    const float ebg = sky + (nbrE && live ? nbrE[(size_t)row * npitch + col] : 0.f);
+    const float vbg = nbrV && live ? nbrV[(size_t)row * npitch + col] : 0.f;
     const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
     float Gs = 0.f, gx = 0.f, gd = 0.f;
     for (int k = 0; k < npsf; ++k) {
