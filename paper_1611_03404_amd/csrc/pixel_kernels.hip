@@ -71,11 +71,12 @@ __device__ __forceinline__ void zero(GalAcc& A) {
 }
 
 // One galaxy component: N and the Hermite polynomials H1..H4 of b = P d,
-// i.e. the derivatives of N with respect to its mean up to order 4.
-__device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
+// i.e. the derivatives of N with respect to its mean up to order 4.  Returns false (the same
+// on every lane) when the component is exactly 0 on the whole tile and was skipped.
+__device__ __forceinline__ bool gal_comp(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
                                          float dyy, GalAcc& A) {
   const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
-  if (!wave_any(e >= E_ZERO)) return;
+  if (!wave_any(e >= E_ZERO)) return false;
   const float N = ex2(e);
   const float Pxx = r[R_PXX], Pxy = r[R_PXY], Pyy = r[R_PYY];
   const float bx = fmaf(Pxx, dx, Pxy * dy);
@@ -112,6 +113,7 @@ __device__ __forceinline__ void gal_comp(const float* __restrict__ r, float dx, 
   A.b4[2] = fmaf(Nn2, h42, A.b4[2]);
   A.b4[3] = fmaf(Nn2, h43, A.b4[3]);
   A.b4[4] = fmaf(Nn2, h44, A.b4[4]);
+  return true;
 }
 
 // acc += density of one component (value path).  No exact-zero skip here: one exp costs less
@@ -299,12 +301,14 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
     const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
 
     // ---- star: N, dN/dp, d2N/dp2
+    bool hit = false;   // some component is not exactly 0 on this tile (wavefront-uniform)
     float s0 = 0.f, s1x = 0.f, s1y = 0.f, s2xx = 0.f, s2xy = 0.f, s2yy = 0.f;
     for (int k = 0; k < npsf; ++k) {
       const float* __restrict__ r = T + STAR + k * STAR_REC;
       const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
       const float e = fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0])));
       if (!wave_any(e >= E_ZERO)) continue;
+      hit = true;
       const float N = ex2(e);
       const float bx = fmaf(r[R_PXX], dx, r[R_PXY] * dy), by = fmaf(r[R_PXY], dx, r[R_PYY] * dy);
       s0 += N;
@@ -326,13 +330,22 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
       if constexpr (NE > 0) {
 #pragma unroll
-        for (int j = 0; j < NE; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+        for (int j = 0; j < NE; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
 #pragma unroll
-        for (int j = NE; j < NE + ND; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+        for (int j = NE; j < NE + ND; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
       } else {
-        for (int j = 0; j < ne; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
-        for (int j = ne; j < ncomp; ++j) gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+        for (int j = 0; j < ne; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+        for (int j = ne; j < ncomp; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
       }
+    }
+    if (!hit) {
+      // No component reaches the tile: T, U and all their derivatives are exactly 0, so the
+      // gradient and Hessian terms are 0 and the pixel term keeps only its neighbour-variance
+      // part, the same value as the general formula below with T = U = 0.
+      const float rE = __builtin_amdgcn_rcpf(ebg);
+      const float xr2 = (x * rE) * rE;
+      val += (double)(0.f - 0.5f * vbg * xr2);
+      continue;
     }
 
     // ---- galaxy profile and its derivatives in y = (p_x, p_y, e_dev, e_axis, e_angle, e_scale)
