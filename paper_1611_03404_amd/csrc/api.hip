@@ -71,6 +71,7 @@ struct celeste_ctx {
   int use_graph = 1;
   int variant = 3;   // pixel-kernel variant (register budget / unrolling), see CELESTE_OPT_VARIANT
   int tile_log2 = 3;     // log2 tile width of the value+gradient+Hessian kernel
+  float e_zero = -160.f; // exact-zero threshold of the pixel kernels (log2 density), set at creation
   int vblock = 256;      // value kernel block size
   int vtile_log2 = 3;    // log2 tile width of the value kernel
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
@@ -588,6 +589,24 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "counter allocation failed");
   }
+  {
+    // Exact-zero threshold: where the device's exp2 returns exactly 0 below 2^-126 (results
+    // that would be subnormal are flushed), a component whose log2 density is below -127 on a
+    // whole tile contributes exactly 0 and the threshold is -127; otherwise -160 (below the
+    // smallest subnormal).
+    const float in[4] = {-126.5f, -127.0f, -135.0f, -149.5f};
+    float res[4] = {1.f, 1.f, 1.f, 1.f};
+    DevBuf pb;
+    if (ensure(pb, sizeof(in) * 2) == CELESTE_OK) {
+      float* d = as<float>(pb);
+      if (hipMemcpy(d, in, sizeof(in), hipMemcpyHostToDevice) == hipSuccess &&
+          launch_exp2_probe(d, d + 4, 4, c->stream) == hipSuccess &&
+          hipMemcpyAsync(res, d + 4, sizeof(res), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+          hipStreamSynchronize(c->stream) == hipSuccess)
+        c->e_zero = (res[0] == 0.f && res[1] == 0.f && res[2] == 0.f && res[3] == 0.f) ? -127.f : -160.f;
+      (void)hipFree(pb.p);
+    }
+  }
   *out = c;
   return CELESTE_OK;
 }
@@ -819,7 +838,7 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
   if (grad) {
     HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant,
-                            ctx->tile_log2, st, kept));
+                            ctx->tile_log2, ctx->e_zero, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
@@ -922,7 +941,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, ctx->variant, ctx->tile_log2, st));
+                          ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -1680,7 +1699,8 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
           double ms = 0.0;
           rc = time_min(st, 3, [&]() {
             return launch_eval_full(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
-                                    P.prof.n_dev, nullptr, as<double>(ctx->partials), block, variant, tl, st);
+                                    P.prof.n_dev, nullptr, as<double>(ctx->partials), block, variant, tl,
+                                    ctx->e_zero, st);
           }, &ms);
           r.n_candidates += 1;
           if (chunk == 4096 && block == 256 && variant == 3 && tl == 3) r.default_full_ms = ms;

@@ -100,10 +100,14 @@ hipError_t launch_check_const(const ImgDev* imgs, int n_img, const double* lfact
 // tw_log2: log2 of the pixel-tile width (3..6; tiles hold 64 pixels).  kept: nullptr for
 // dense work items; for a pixel subsample, the first rows of the kept 8-row blocks, and each
 // item's [row_begin, row_end) indexes this list instead of rows.
+// e_zero: a component whose log2 density is below e_zero on every lane of a tile is exactly 0
+// there and is skipped (see launch_exp2_probe).
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
-                            int block, int variant, int tw_log2, hipStream_t st,
+                            int block, int variant, int tw_log2, float e_zero, hipStream_t st,
                             const int* kept = nullptr);
+// out[i] = the pixel kernels' exp2(in[i]) on the device (i < n).
+hipError_t launch_exp2_probe(const float* in, float* out, int n, hipStream_t st);
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                              int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
                              int block, int variant, int tw_log2, hipStream_t st,

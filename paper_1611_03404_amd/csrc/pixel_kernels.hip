@@ -40,7 +40,9 @@ using namespace tab;
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-constexpr float E_ZERO = -160.f;   // exp2 below this is exactly 0 in FP32
+// Exact-zero threshold on log2 of a component's density, a launch argument: -160 in general
+// (2^-160 lies below the smallest FP32 subnormal), -127 where v_exp_f32 flushes results below
+// 2^-126 to zero, which the library checks on the device when a context is created.
 constexpr float FAR = 1.0e4f;      // offset used by lanes outside the image
 constexpr int FLUSH = 16;          // tile steps of lane sums in FP32 before a butterfly into FP64
 constexpr int JFLUSH = 8;          // tile steps of matrix-core sums in FP32 before FP64
@@ -74,9 +76,9 @@ __device__ __forceinline__ void zero(GalAcc& A) {
 // i.e. the derivatives of N with respect to its mean up to order 4.  Returns false (the same
 // on every lane) when the component is exactly 0 on the whole tile and was skipped.
 __device__ __forceinline__ bool gal_comp(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
-                                         float dyy, GalAcc& A) {
+                                         float dyy, float e_zero, GalAcc& A) {
   const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
-  if (!wave_any(e >= E_ZERO)) return false;
+  if (!wave_any(e >= e_zero)) return false;
   const float N = ex2(e);
   const float Pxx = r[R_PXX], Pxy = r[R_PXY], Pyy = r[R_PYY];
   const float bx = fmaf(Pxx, dx, Pxy * dy);
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
-                                                     int tw_log2, const int* __restrict__ kept,
+                                                     int tw_log2, float e_zero, const int* __restrict__ kept,
                                                      double* __restrict__ partials) {
   __shared__ double red[BLOCK / 64][80];
   // per wavefront: [A rows (dT, dU) | B columns (hT, hU)][T or U part][z index][pixel]
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float* __restrict__ r = T + STAR + k * STAR_REC;
       const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
       const float e = fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0])));
-      if (!wave_any(e >= E_ZERO)) continue;
+      if (!wave_any(e >= e_zero)) continue;
       hit = true;
       const float N = ex2(e);
       const float bx = fmaf(r[R_PXX], dx, r[R_PXY] * dy), by = fmaf(r[R_PXY], dx, r[R_PYY] * dy);
@@ -330,12 +332,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
       if constexpr (NE > 0) {
 #pragma unroll
-        for (int j = 0; j < NE; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
+        for (int j = 0; j < NE; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, X);
 #pragma unroll
-        for (int j = NE; j < NE + ND; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+        for (int j = NE; j < NE + ND; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, D);
       } else {
-        for (int j = 0; j < ne; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, X);
-        for (int j = ne; j < ncomp; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, D);
+        for (int j = 0; j < ne; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, X);
+        for (int j = ne; j < ncomp; ++j) hit |= gal_comp(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, D);
       }
     }
     if (!hit) {
@@ -644,7 +646,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
-                            int tw_log2, hipStream_t st, const int* kept) {
+                            int tw_log2, float e_zero, hipStream_t st, const int* kept) {
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
@@ -652,7 +654,7 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
   const dim3 g(n_items);
 #define CELESTE_LAUNCH_FULL(B, W, E, D, M) \
   hipLaunchKernelGGL((k_eval_full<B, W, E, D, M>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, tw_log2, kept, partials)
+                     src_flag, tw_log2, e_zero, kept, partials)
   if (block == 128) {
     if (mf) {
       if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true);
@@ -671,6 +673,19 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
     }
   }
 #undef CELESTE_LAUNCH_FULL
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void k_exp2_probe(const float* __restrict__ in, float* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ex2(in[i]);
+}
+}  // namespace
+
+hipError_t launch_exp2_probe(const float* in, float* out, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exp2_probe, dim3((n + 63) / 64), dim3(64), 0, st, in, out, n);
   return hipGetLastError();
 }
 
