@@ -89,7 +89,13 @@ enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_TILE_W = 6,       /* width of the 64-pixel tile a wavefront of the value+gradient+Hessian
                                    kernel takes per step: 8, 16, 32 or 64 (default 8) */
   CELESTE_OPT_VALUE_BLOCK = 7,  /* threads per value-kernel block: 128 or 256 (default 256) */
-  CELESTE_OPT_VALUE_TILE_W = 8  /* tile width of the value kernel: 8, 16, 32 or 64 (default 8) */
+  CELESTE_OPT_VALUE_TILE_W = 8, /* tile width of the value kernel: 8, 16, 32 or 64 (default 8) */
+  CELESTE_OPT_EXACT_ZERO = 9    /* skip threshold of the value+gradient+Hessian kernel: a mixture
+                                   component whose density is below 2^-v on a whole tile is skipped.
+                                   160 (always exact: below the smallest FP32 subnormal), 127 (exact
+                                   where the device's exp2 flushes results below 2^-126 to zero, which
+                                   the context checks at creation; E_UNSUPPORTED elsewhere), or 0 for
+                                   the context's choice (127 where exact, else 160; the default) */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -194,7 +200,9 @@ void celeste_ctx_destroy(celeste_ctx* ctx);
 const char* celeste_last_error(void);
 
 /* Set a tuning option of the context (CELESTE_OPT_*).  The options change only how the
- * pixel sums are grouped (results move by rounding, far inside the stated tolerances).
+ * pixel sums are grouped (results move by rounding, far inside the stated tolerances);
+ * CELESTE_OPT_EXACT_ZERO changes only which exactly-zero work is skipped (results are
+ * bitwise the same).
  * Errors: E_INVALID (unknown option or value out of range). */
 int celeste_ctx_set_option(celeste_ctx* ctx, int option, int64_t value);
 

@@ -347,6 +347,13 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float rE = __builtin_amdgcn_rcpf(ebg);
       const float xr2 = (x * rE) * rE;
       val += (double)(0.f - 0.5f * vbg * xr2);
+      // the same flush points as the general path, so a skip threshold changes no bit
+      ++since;
+      if (MF && (since % JFLUSH) == 0) flushJ();
+      if (since == FLUSH) {
+        flush();
+        since = 0;
+      }
       continue;
     }
 

@@ -156,6 +156,33 @@ def test_deterministic_and_batch_equals_single(cb, ctx):
     assert np.allclose(e3, e1, rtol=1e-12) and deriv_err(g3, g1) < 2e-5 and deriv_err(H3, H1) < 2e-5
 
 
+def test_exact_zero_threshold_changes_no_bit(cb, ctx):
+    """Skipping components below 2^-127 instead of 2^-160 on a tile skips only work that is
+    exactly zero on this device (its exp2 flushes results below 2^-126): every output bit is the
+    same, with and without neighbour arrays."""
+    full = synth.make_config(1, n_sources=6)
+    th = perturb_theta(full.theta_truth, 14)
+    rng = np.random.default_rng(15)
+    n = full.n_pixels
+    nbr = (rng.uniform(0, 30, n).astype(np.float32), rng.uniform(0, 8, n).astype(np.float32))
+    try:
+        for batch in (cb.Batch.from_synth(full), cb.Batch.from_synth(full, nbr=nbr)):
+            ctx.set_option(cb.OPT_EXACT_ZERO, 160)
+            e1, g1, H1 = ctx.elbo_eval(batch, th)
+            try:
+                ctx.set_option(cb.OPT_EXACT_ZERO, 127)
+            except cb.CelesteError as err:
+                assert err.code == cb.E_UNSUPPORTED
+                pytest.skip("this device's exp2 keeps subnormal results")
+            e2, g2, H2 = ctx.elbo_eval(batch, th)
+            assert np.array_equal(e1, e2) and np.array_equal(g1, g2) and np.array_equal(H1, H2)
+    finally:
+        ctx.set_option(cb.OPT_EXACT_ZERO, 0)
+    with pytest.raises(cb.CelesteError) as ei:
+        ctx.set_option(cb.OPT_EXACT_ZERO, 100)
+    assert ei.value.code == cb.E_INVALID
+
+
 def test_value_only_matches_full(cb, ctx):
     full = synth.make_config(1, n_sources=5)
     th = perturb_theta(full.theta_truth, 10)
