@@ -347,199 +347,195 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float rE = __builtin_amdgcn_rcpf(ebg);
       const float xr2 = (x * rE) * rE;
       val += (double)(0.f - 0.5f * vbg * xr2);
-      // the same flush points as the general path, so a skip threshold changes no bit
-      ++since;
-      if (MF && (since % JFLUSH) == 0) flushJ();
-      if (since == FLUSH) {
-        flush();
-        since = 0;
-      }
-      continue;
-    }
+    } else {
 
-    // ---- galaxy profile and its derivatives in y = (p_x, p_y, e_dev, e_axis, e_angle, e_scale)
-    const float ed = T[EDEV];
-    auto mix = [ed](float d, float x_) { return fmaf(ed, d - x_, x_); };
-    const float Gg = mix(D.a0, X.a0);
-    float dG[6], d2G[6][6];
-    dG[0] = mix(D.a1x, X.a1x);
-    dG[1] = mix(D.a1y, X.a1y);
-    dG[2] = D.a0 - X.a0;
-    const float b2c[3] = {mix(D.b2xx, X.b2xx), mix(D.b2xy, X.b2xy), mix(D.b2yy, X.b2yy)};
-    const float b2d[3] = {D.b2xx - X.b2xx, D.b2xy - X.b2xy, D.b2yy - X.b2yy};
-    float b3c[4], b4c[5];
+      // ---- galaxy profile and its derivatives in y = (p_x, p_y, e_dev, e_axis, e_angle, e_scale)
+      const float ed = T[EDEV];
+      auto mix = [ed](float d, float x_) { return fmaf(ed, d - x_, x_); };
+      const float Gg = mix(D.a0, X.a0);
+      float dG[6], d2G[6][6];
+      dG[0] = mix(D.a1x, X.a1x);
+      dG[1] = mix(D.a1y, X.a1y);
+      dG[2] = D.a0 - X.a0;
+      const float b2c[3] = {mix(D.b2xx, X.b2xx), mix(D.b2xy, X.b2xy), mix(D.b2yy, X.b2yy)};
+      const float b2d[3] = {D.b2xx - X.b2xx, D.b2xy - X.b2xy, D.b2yy - X.b2yy};
+      float b3c[4], b4c[5];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b3c[i] = mix(D.b3[i], X.b3[i]);
+      for (int i = 0; i < 4; ++i) b3c[i] = mix(D.b3[i], X.b3[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) b4c[i] = mix(D.b4[i], X.b4[i]);
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const float w0 = T[W1 + 3 * e], w1 = T[W1 + 3 * e + 1], w2 = T[W1 + 3 * e + 2];
-      dG[3 + e] = fmaf(w0, b2c[0], fmaf(w1, b2c[1], w2 * b2c[2]));
-      d2G[0][3 + e] = fmaf(w0, b3c[0], fmaf(w1, b3c[1], w2 * b3c[2]));
-      d2G[1][3 + e] = fmaf(w0, b3c[1], fmaf(w1, b3c[2], w2 * b3c[3]));
-      d2G[2][3 + e] = fmaf(w0, b2d[0], fmaf(w1, b2d[1], w2 * b2d[2]));
-    }
-    d2G[0][0] = mix(D.a2xx, X.a2xx);
-    d2G[0][1] = mix(D.a2xy, X.a2xy);
-    d2G[1][1] = mix(D.a2yy, X.a2yy);
-    d2G[0][2] = D.a1x - X.a1x;
-    d2G[1][2] = D.a1y - X.a1y;
-    d2G[2][2] = 0.f;
-    {
-      int k = 0;
+      for (int i = 0; i < 5; ++i) b4c[i] = mix(D.b4[i], X.b4[i]);
 #pragma unroll
       for (int e = 0; e < 3; ++e) {
+        const float w0 = T[W1 + 3 * e], w1 = T[W1 + 3 * e + 1], w2 = T[W1 + 3 * e + 2];
+        dG[3 + e] = fmaf(w0, b2c[0], fmaf(w1, b2c[1], w2 * b2c[2]));
+        d2G[0][3 + e] = fmaf(w0, b3c[0], fmaf(w1, b3c[1], w2 * b3c[2]));
+        d2G[1][3 + e] = fmaf(w0, b3c[1], fmaf(w1, b3c[2], w2 * b3c[3]));
+        d2G[2][3 + e] = fmaf(w0, b2d[0], fmaf(w1, b2d[1], w2 * b2d[2]));
+      }
+      d2G[0][0] = mix(D.a2xx, X.a2xx);
+      d2G[0][1] = mix(D.a2xy, X.a2xy);
+      d2G[1][1] = mix(D.a2yy, X.a2yy);
+      d2G[0][2] = D.a1x - X.a1x;
+      d2G[1][2] = D.a1y - X.a1y;
+      d2G[2][2] = 0.f;
+      {
+        int k = 0;
 #pragma unroll
-        for (int f = e; f < 3; ++f, ++k) {
-          const float* w4 = T + W4 + 5 * k;
-          const float* w2 = T + W2 + 3 * k;
-          float v = w4[0] * b4c[0];
+        for (int e = 0; e < 3; ++e) {
 #pragma unroll
-          for (int q = 1; q < 5; ++q) v = fmaf(w4[q], b4c[q], v);
-          v = fmaf(w2[0], b2c[0], fmaf(w2[1], b2c[1], fmaf(w2[2], b2c[2], v)));
-          d2G[3 + e][3 + f] = v;
+          for (int f = e; f < 3; ++f, ++k) {
+            const float* w4 = T + W4 + 5 * k;
+            const float* w2 = T + W2 + 3 * k;
+            float v = w4[0] * b4c[0];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) v = fmaf(w4[q], b4c[q], v);
+            v = fmaf(w2[0], b2c[0], fmaf(w2[1], b2c[1], fmaf(w2[2], b2c[2], v)));
+            d2G[3 + e][3 + f] = v;
+          }
         }
       }
-    }
-    // star derivatives in the same y coordinates (zero beyond the position)
-    const float dGs[2] = {s1x, s1y};
+      // star derivatives in the same y coordinates (zero beyond the position)
+      const float dGs[2] = {s1x, s1y};
 
-    // ---- mean T and variance U of the source's contribution, and their z-derivatives
-    const float cs = T[CS], cg = T[CG], mus = T[MU_S], mug = T[MU_G];
-    const float Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
-    const float Gs = s0;
-    const float Gs2 = Gs * Gs, Gg2 = Gg * Gg, Gsg = Gs * Gg;
-    const float Tv = fmaf(cs, Gs, cg * Gg);
-    const float Uv = fmaf(Ks, Gs2, fmaf(Kg, Gg2, Ksg * Gsg));
-    const float rhos = fmaf(2.f * Ks, Gs, Ksg * Gg), rhog = fmaf(2.f * Kg, Gg, Ksg * Gs);
-    float Tz[NZ], Uz[NZ];
-    Tz[0] = fmaf(mus, Gs, -mug * Gg);
-    Tz[1] = cs * Gs;
-    Tz[2] = 0.5f * Tz[1];
-    Tz[3] = cg * Gg;
-    Tz[4] = 0.5f * Tz[3];
-    Uz[0] = fmaf(T[KA_S], Gs2, fmaf(T[KA_G], Gg2, T[KA_SG] * Gsg));
-    Uz[1] = fmaf(2.f * Ks, Gs2, Ksg * Gsg);
-    Uz[2] = fmaf(T[KV_S], Gs2, 0.5f * Ksg * Gsg);
-    Uz[3] = fmaf(2.f * Kg, Gg2, Ksg * Gsg);
-    Uz[4] = fmaf(T[KV_G], Gg2, 0.5f * Ksg * Gsg);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float gs = k < 2 ? dGs[k] : 0.f;
-      Tz[5 + k] = fmaf(cs, gs, cg * dG[k]);
-      Uz[5 + k] = fmaf(rhos, gs, rhog * dG[k]);
-    }
-
-    // ---- delta-method pixel term and its partials in (E, V)
-    const float E = fmaf(io, Tv, ebg);
-    const float V = fmaf(io2, Uv, vbg);
-    const float rE = __builtin_amdgcn_rcpf(E);
-    const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
-    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
-    const float lE = fmaf(x - E, rE, V * xr3);
-    const float lV = -0.5f * xr2;
-    const float lEE = -fmaf(3.f * V * xr3, rE, xr2);
-    const float lEV = xr3;
-    const float wT = io * lE, wU = io2 * lV, wTT = io2 * lEE, wTU = io3 * lEV;
-
-    // ---- sparse second-order part S = wT d2T + wU d2U (upper triangle)
-    float S[NZ * (NZ + 1) / 2];
-    S[tri(0, 0)] = wU * fmaf(T[KS_AA], Gs2, fmaf(T[KG_AA], Gg2, T[KSG_AA] * Gsg));
-    S[tri(0, 1)] = fmaf(wT, mus * Gs, wU * fmaf(T[KS_AM], Gs2, T[KSG_AM] * Gsg));
-    S[tri(0, 2)] = fmaf(wT, 0.5f * mus * Gs, wU * fmaf(T[KS_AV], Gs2, T[KSG_AV] * Gsg));
-    S[tri(0, 3)] = fmaf(wT, -mug * Gg, wU * fmaf(T[KG_AM], Gg2, T[KSG_AM] * Gsg));
-    S[tri(0, 4)] = fmaf(wT, -0.5f * mug * Gg, wU * fmaf(T[KG_AV], Gg2, T[KSG_AV] * Gsg));
-    S[tri(1, 1)] = fmaf(wT, Tz[1], wU * fmaf(T[KS_MM], Gs2, Ksg * Gsg));
-    S[tri(1, 2)] = fmaf(wT, 0.5f * Tz[1], wU * fmaf(T[KS_MV], Gs2, 0.5f * Ksg * Gsg));
-    S[tri(1, 3)] = wU * Ksg * Gsg;
-    S[tri(1, 4)] = 0.5f * wU * Ksg * Gsg;
-    S[tri(2, 2)] = fmaf(wT, 0.25f * Tz[1], wU * fmaf(T[KS_VV], Gs2, 0.25f * Ksg * Gsg));
-    S[tri(2, 3)] = 0.5f * wU * Ksg * Gsg;
-    S[tri(2, 4)] = 0.25f * wU * Ksg * Gsg;
-    S[tri(3, 3)] = fmaf(wT, Tz[3], wU * fmaf(T[KG_MM], Gg2, Ksg * Gsg));
-    S[tri(3, 4)] = fmaf(wT, 0.5f * Tz[3], wU * fmaf(T[KG_MV], Gg2, 0.5f * Ksg * Gsg));
-    S[tri(4, 4)] = fmaf(wT, 0.25f * Tz[3], wU * fmaf(T[KG_VV], Gg2, 0.25f * Ksg * Gsg));
-    {
-      // brightness x geometry block
-      const float dks[5] = {T[KA_S], 2.f * Ks, T[KV_S], 0.f, 0.f};
-      const float dkg[5] = {T[KA_G], 0.f, 0.f, 2.f * Kg, T[KV_G]};
-      const float dksg[5] = {T[KA_SG], Ksg, 0.5f * Ksg, Ksg, 0.5f * Ksg};
-      const float cts[5] = {mus, cs, 0.5f * cs, 0.f, 0.f};
-      const float ctg[5] = {-mug, 0.f, 0.f, cg, 0.5f * cg};
-#pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const float sgs = fmaf(wT, cts[i], wU * fmaf(2.f * dks[i], Gs, dksg[i] * Gg));
-        const float sgg = fmaf(wT, ctg[i], wU * fmaf(2.f * dkg[i], Gg, dksg[i] * Gs));
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const float gs = k < 2 ? dGs[k] : 0.f;
-          S[tri(i, 5 + k)] = fmaf(sgs, gs, sgg * dG[k]);
-        }
-      }
-      // geometry x geometry block
-      const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
-      const float d2Gs[3] = {s2xx, s2xy, s2yy};
+      // ---- mean T and variance U of the source's contribution, and their z-derivatives
+      const float cs = T[CS], cg = T[CG], mus = T[MU_S], mug = T[MU_G];
+      const float Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+      const float Gs = s0;
+      const float Gs2 = Gs * Gs, Gg2 = Gg * Gg, Gsg = Gs * Gg;
+      const float Tv = fmaf(cs, Gs, cg * Gg);
+      const float Uv = fmaf(Ks, Gs2, fmaf(Kg, Gg2, Ksg * Gsg));
+      const float rhos = fmaf(2.f * Ks, Gs, Ksg * Gg), rhog = fmaf(2.f * Kg, Gg, Ksg * Gs);
+      float Tz[NZ], Uz[NZ];
+      Tz[0] = fmaf(mus, Gs, -mug * Gg);
+      Tz[1] = cs * Gs;
+      Tz[2] = 0.5f * Tz[1];
+      Tz[3] = cg * Gg;
+      Tz[4] = 0.5f * Tz[3];
+      Uz[0] = fmaf(T[KA_S], Gs2, fmaf(T[KA_G], Gg2, T[KA_SG] * Gsg));
+      Uz[1] = fmaf(2.f * Ks, Gs2, Ksg * Gsg);
+      Uz[2] = fmaf(T[KV_S], Gs2, 0.5f * Ksg * Gsg);
+      Uz[3] = fmaf(2.f * Kg, Gg2, Ksg * Gsg);
+      Uz[4] = fmaf(T[KV_G], Gg2, 0.5f * Ksg * Gsg);
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
+        const float gs = k < 2 ? dGs[k] : 0.f;
+        Tz[5 + k] = fmaf(cs, gs, cg * dG[k]);
+        Uz[5 + k] = fmaf(rhos, gs, rhog * dG[k]);
+      }
+
+      // ---- delta-method pixel term and its partials in (E, V)
+      const float E = fmaf(io, Tv, ebg);
+      const float V = fmaf(io2, Uv, vbg);
+      const float rE = __builtin_amdgcn_rcpf(E);
+      const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
+      const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
+      const float lE = fmaf(x - E, rE, V * xr3);
+      const float lV = -0.5f * xr2;
+      const float lEE = -fmaf(3.f * V * xr3, rE, xr2);
+      const float lEV = xr3;
+      const float wT = io * lE, wU = io2 * lV, wTT = io2 * lEE, wTU = io3 * lEV;
+
+      // ---- sparse second-order part S = wT d2T + wU d2U (upper triangle)
+      float S[NZ * (NZ + 1) / 2];
+      S[tri(0, 0)] = wU * fmaf(T[KS_AA], Gs2, fmaf(T[KG_AA], Gg2, T[KSG_AA] * Gsg));
+      S[tri(0, 1)] = fmaf(wT, mus * Gs, wU * fmaf(T[KS_AM], Gs2, T[KSG_AM] * Gsg));
+      S[tri(0, 2)] = fmaf(wT, 0.5f * mus * Gs, wU * fmaf(T[KS_AV], Gs2, T[KSG_AV] * Gsg));
+      S[tri(0, 3)] = fmaf(wT, -mug * Gg, wU * fmaf(T[KG_AM], Gg2, T[KSG_AM] * Gsg));
+      S[tri(0, 4)] = fmaf(wT, -0.5f * mug * Gg, wU * fmaf(T[KG_AV], Gg2, T[KSG_AV] * Gsg));
+      S[tri(1, 1)] = fmaf(wT, Tz[1], wU * fmaf(T[KS_MM], Gs2, Ksg * Gsg));
+      S[tri(1, 2)] = fmaf(wT, 0.5f * Tz[1], wU * fmaf(T[KS_MV], Gs2, 0.5f * Ksg * Gsg));
+      S[tri(1, 3)] = wU * Ksg * Gsg;
+      S[tri(1, 4)] = 0.5f * wU * Ksg * Gsg;
+      S[tri(2, 2)] = fmaf(wT, 0.25f * Tz[1], wU * fmaf(T[KS_VV], Gs2, 0.25f * Ksg * Gsg));
+      S[tri(2, 3)] = 0.5f * wU * Ksg * Gsg;
+      S[tri(2, 4)] = 0.25f * wU * Ksg * Gsg;
+      S[tri(3, 3)] = fmaf(wT, Tz[3], wU * fmaf(T[KG_MM], Gg2, Ksg * Gsg));
+      S[tri(3, 4)] = fmaf(wT, 0.5f * Tz[3], wU * fmaf(T[KG_MV], Gg2, 0.5f * Ksg * Gsg));
+      S[tri(4, 4)] = fmaf(wT, 0.25f * Tz[3], wU * fmaf(T[KG_VV], Gg2, 0.25f * Ksg * Gsg));
+      {
+        // brightness x geometry block
+        const float dks[5] = {T[KA_S], 2.f * Ks, T[KV_S], 0.f, 0.f};
+        const float dkg[5] = {T[KA_G], 0.f, 0.f, 2.f * Kg, T[KV_G]};
+        const float dksg[5] = {T[KA_SG], Ksg, 0.5f * Ksg, Ksg, 0.5f * Ksg};
+        const float cts[5] = {mus, cs, 0.5f * cs, 0.f, 0.f};
+        const float ctg[5] = {-mug, 0.f, 0.f, cg, 0.5f * cg};
 #pragma unroll
-        for (int l = k; l < 6; ++l) {
-          const float gsk = k < 2 ? dGs[k] : 0.f, gsl = l < 2 ? dGs[l] : 0.f;
-          const float hs = (k < 2 && l < 2) ? d2Gs[k + l] : 0.f;
-          float v = fmaf(als, hs, alg * d2G[k][l]);
-          const float q = fmaf(2.f * Ks, gsk * gsl, fmaf(2.f * Kg, dG[k] * dG[l], Ksg * fmaf(gsk, dG[l], gsl * dG[k])));
-          S[tri(5 + k, 5 + l)] = fmaf(wU, q, v);
+        for (int i = 0; i < 5; ++i) {
+          const float sgs = fmaf(wT, cts[i], wU * fmaf(2.f * dks[i], Gs, dksg[i] * Gg));
+          const float sgg = fmaf(wT, ctg[i], wU * fmaf(2.f * dkg[i], Gg, dksg[i] * Gs));
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const float gs = k < 2 ? dGs[k] : 0.f;
+            S[tri(i, 5 + k)] = fmaf(sgs, gs, sgg * dG[k]);
+          }
+        }
+        // geometry x geometry block
+        const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
+        const float d2Gs[3] = {s2xx, s2xy, s2yy};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+#pragma unroll
+          for (int l = k; l < 6; ++l) {
+            const float gsk = k < 2 ? dGs[k] : 0.f, gsl = l < 2 ? dGs[l] : 0.f;
+            const float hs = (k < 2 && l < 2) ? d2Gs[k + l] : 0.f;
+            float v = fmaf(als, hs, alg * d2G[k][l]);
+            const float q =
+                fmaf(2.f * Ks, gsk * gsl, fmaf(2.f * Kg, dG[k] * dG[l], Ksg * fmaf(gsk, dG[l], gsl * dG[k])));
+            S[tri(5 + k, 5 + l)] = fmaf(wU, q, v);
+          }
         }
       }
-    }
 
-    // ---- value in FP64 per lane; gradient and second-order part in the per-lane FP32 sums
-    val += (double)lval;
-    float hT[NZ], hU[NZ];
+      // ---- value in FP64 per lane; gradient and second-order part in the per-lane FP32 sums
+      val += (double)lval;
+      float hT[NZ], hU[NZ];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-      accf[j] += fmaf(wT, Tz[j], wU * Uz[j]);
-      hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
-      hU[j] = wTU * Tz[j];
-    }
-    if constexpr (!MF) {
-#pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-#pragma unroll
-        for (int j = i; j < NZ; ++j)
-          accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+      for (int j = 0; j < NZ; ++j) {
+        accf[j] += fmaf(wT, Tz[j], wU * Uz[j]);
+        hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
+        hU[j] = wTU * Tz[j];
       }
-    } else {
+      if constexpr (!MF) {
 #pragma unroll
-      for (int t = 0; t < NZ * (NZ + 1) / 2; ++t) accf[NZ + t] += S[t];
-      // ---- J^T W J over the tile: C = sum_k A[:, k] B[k, :], k = 4 m + kq over (pixel, part)
-      float(*J)[2][MF ? NZ : 1][MF ? JP : 4] = jbuf[wv];
+        for (int i = 0; i < NZ; ++i) {
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        J[0][0][i][lane] = Tz[i];
-        J[0][1][i][lane] = Uz[i];
-        J[1][0][i][lane] = hT[i];
-        J[1][1][i][lane] = hU[i];
+          for (int j = i; j < NZ; ++j)
+            accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < NZ * (NZ + 1) / 2; ++t) accf[NZ + t] += S[t];
+        // ---- J^T W J over the tile: C = sum_k A[:, k] B[k, :], k = 4 m + kq over (pixel, part)
+        float(*J)[2][MF ? NZ : 1][MF ? JP : 4] = jbuf[wv];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          J[0][0][i][lane] = Tz[i];
+          J[0][1][i][lane] = Uz[i];
+          J[1][0][i][lane] = hT[i];
+          J[1][1][i][lane] = hU[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane (mi, kq) feeds A[mi][4m + kq] and B[4m + kq][mi]: part kq & 1 of pixel 32 (kq >> 1) + m
+        const float* ar = mrow ? &J[0][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
+        const float* br = mrow ? &J[1][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float4 a = *reinterpret_cast<const float4*>(ar + 4 * q);
+          const float4 b = *reinterpret_cast<const float4*>(br + 4 * q);
+          C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, C0, 0, 0, 0);
+          C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, C1, 0, 0, 0);
+          C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, C0, 0, 0, 0);
+          C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, C1, 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // lane (mi, kq) feeds A[mi][4m + kq] and B[4m + kq][mi]: part kq & 1 of pixel 32 (kq >> 1) + m
-      const float* ar = mrow ? &J[0][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
-      const float* br = mrow ? &J[1][kq & 1][mi][32 * (kq >> 1)] : &zrow[32 * (kq >> 1)];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float4 a = *reinterpret_cast<const float4*>(ar + 4 * q);
-        const float4 b = *reinterpret_cast<const float4*>(br + 4 * q);
-        C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, C0, 0, 0, 0);
-        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, C1, 0, 0, 0);
-        C0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, C0, 0, 0, 0);
-        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, C1, 0, 0, 0);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    }   // hit
+    // every tile step counts, so the flush points (and every bit of the result) do not depend on
+    // which exactly-zero work was skipped
     ++since;
     if (MF && (since % JFLUSH) == 0) flushJ();
     if (since == FLUSH) {
