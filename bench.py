@@ -295,7 +295,7 @@ def probe(args, ctx, log):
     theta0 = np.zeros((sb.n_sources, 27))
     theta0[:, 0:2] = sb.u_cat
     th, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
-    tune = None if args.no_autotune else ctx.autotune(batch, th)
+    tune = None if args.no_autotune else ctx.autotune(batch, th, cache_path=args.tune_cache)
     log(f"probe: {sb.n_sources} sources, {sb.n_pixels} px, autotune {tune}")
     for _ in range(2):
         ctx.elbo_eval(batch, th)
@@ -337,6 +337,10 @@ def main():
                     help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
                          "sweeps over conflict-free colours")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: read the launch shapes from it when it has an entry for this "
+                         "device and workload, else time them and add one (runs that must share a launch "
+                         "configuration, such as hardware-counter passes, pass the same file)")
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection target: two value+gradient+Hessian and two value evaluations of the "
                          "batched workload at the plain start, then two 1 GiB device copies; no timing")
@@ -395,7 +399,7 @@ def main():
         # launch and tile shapes of the pixel kernels, timed on a sample at the plain start (not timed)
         th_start, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
         t = time.perf_counter()
-        tune = ctx.autotune(batch, th_start)
+        tune = ctx.autotune(batch, th_start, cache_path=args.tune_cache)
         tune["tune_s"] = time.perf_counter() - t
         log(f"autotune: {tune}")
     modes = [("plain", cb.INIT_PLAIN)] + ([] if net is None else [("surrogate", cb.INIT_SURROGATE)])
@@ -533,7 +537,7 @@ def sampled_bench(args, ctx, log):
     theta0 = np.zeros((sb.n_sources, 27))
     theta0[:, 0:2] = sb.u_cat
     th, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
-    tune = None if args.no_autotune else ctx.autotune(batch, th)
+    tune = None if args.no_autotune else ctx.autotune(batch, th, cache_path=args.tune_cache)
     log(f"sampled: {sb.n_sources} sources, {sb.n_pixels} px, autotune {tune}")
     ctx.set_option(cb.OPT_PROFILE, 1)
     w = sb.img_w.astype(np.int64)
@@ -667,7 +671,7 @@ def field_bench(args, ctx, net, sur_info, log):
         th0 = np.zeros((sb.n_sources, 27))
         th0[:, 0:2] = sb.u_cat
         th_start, _ = ctx.start(b0, th0, cb.default_opts(init_mode=cb.INIT_PLAIN))
-        tune = ctx.autotune(b0, th_start)
+        tune = ctx.autotune(b0, th_start, cache_path=args.tune_cache)
         log(f"autotune: {tune}")
         del b0
     for w in range(args.warmup):
