@@ -237,31 +237,46 @@ __global__ __launch_bounds__(256) void k_check_const(const ImgDev* __restrict__ 
   const int n = im.h * im.w;
   double acc = 0.0, sx = 0.0;
   int cnt = 0, flag = 0;
-  for (int m = threadIdx.x; m < n; m += 256) {
-    const int r = m / im.w, c = m - r * im.w;
-    const size_t o = (size_t)r * im.pitch + c;
-    const size_t on = (size_t)r * im.nbr_pitch + c;
-    const float xf = im.pix[o];
-    if (!(xf >= 0.0f) || !isfinite(xf)) flag = 1;
-    const double x = xf;
-    double lg;
-    if (x >= 0.0 && x < (double)LFACT_N && x == (double)(int)x)
-      lg = lfact[(int)x];
-    else
-      lg = lgamma(x + 1.0);
-    if (im.nbr_mean) {
-      const float e = im.nbr_mean[on];
-      if (!(e >= 0.0f) || !isfinite(e)) flag = 1;
-      const double ebg = im.sky + (double)e;
-      acc += x * log(ebg) - ebg - lg;
-    } else {
-      sx += x;
-      ++cnt;
-      acc -= lg;
+  // four pixels per thread and step, their loads issued before any is used (the pass is bound by
+  // memory latency, not bandwidth)
+  constexpr int U = 4;
+  for (int m0 = threadIdx.x; m0 < n; m0 += U * 256) {
+    float xs[U], es[U], vs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = min(m0 + u * 256, n - 1);
+      const int r = m / im.w, c = m - r * im.w;
+      const size_t o = (size_t)r * im.pitch + c;
+      const size_t on = (size_t)r * im.nbr_pitch + c;
+      xs[u] = im.pix[o];
+      es[u] = im.nbr_mean ? im.nbr_mean[on] : 0.f;
+      vs[u] = im.nbr_var ? im.nbr_var[on] : 0.f;
     }
-    if (im.nbr_var) {
-      const float v = im.nbr_var[on];
-      if (!(v >= 0.0f) || !isfinite(v)) flag = 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (m0 + u * 256 >= n) break;
+      const float xf = xs[u];
+      if (!(xf >= 0.0f) || !isfinite(xf)) flag = 1;
+      const double x = xf;
+      double lg;
+      if (x >= 0.0 && x < (double)LFACT_N && x == (double)(int)x)
+        lg = lfact[(int)x];
+      else
+        lg = lgamma(x + 1.0);
+      if (im.nbr_mean) {
+        const float e = es[u];
+        if (!(e >= 0.0f) || !isfinite(e)) flag = 1;
+        const double ebg = im.sky + (double)e;
+        acc += x * log(ebg) - ebg - lg;
+      } else {
+        sx += x;
+        ++cnt;
+        acc -= lg;
+      }
+      if (im.nbr_var) {
+        const float v = vs[u];
+        if (!(v >= 0.0f) || !isfinite(v)) flag = 1;
+      }
     }
   }
   if (!im.nbr_mean) acc += log(im.sky) * sx - (double)cnt * im.sky;
