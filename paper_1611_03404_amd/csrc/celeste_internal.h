@@ -80,6 +80,9 @@ constexpr int R_3PXX = 8, R_3PYY = 9, R_2PXY = 10, R_6PXX = 11, R_6PYY = 12, R_3
 constexpr int R_K4A = 15, R_K4B = 16, R_K4C = 17, R_K4D = 18, R_K4E = 19;
 // star record fields: c0, qxx, qxy, qyy, Pxx, Pxy, Pyy, xi_x, xi_y
 constexpr int S_XIX = 7, S_XIY = 8;
+// bound of the galaxy components of one PSF component: each has log2 density at most
+// S_GC0 + S_GMU |d|^2 at offset d from the PSF component's centre (S_GMU < 0)
+constexpr int S_GC0 = 9, S_GMU = 10;
 }  // namespace tab
 
 inline int table_stride(int max_psf, int n_exp, int n_dev) {

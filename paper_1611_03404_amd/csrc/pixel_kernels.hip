@@ -329,6 +329,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float* __restrict__ sr = T + STAR + k * STAR_REC;
       const float dx = dx0 - sr[S_XIX], dy = dy0 - sr[S_XIY];
       const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+      // the whole galaxy group is exactly 0 on the tile when its bound is (a margin of 1 covers the
+      // FP32 rounding of the bound and of the components' exponents)
+      if (!wave_any(fmaf(sr[S_GMU], dxx + dyy, sr[S_GC0]) >= e_zero - 1.f)) continue;
       const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
       if constexpr (NE > 0) {
 #pragma unroll

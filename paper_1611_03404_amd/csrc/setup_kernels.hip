@@ -197,6 +197,24 @@ __global__ __launch_bounds__(64) void k_setup(const ImgDev* __restrict__ imgs, c
     write_component(rec, ps[0], Sym2{ps[3], ps[4], ps[5]}, false, 0.0);
     rec[tab::S_XIX] = (float)ps[1];
     rec[tab::S_XIY] = (float)ps[2];
+    // bound of this PSF component's galaxy group: C_j = nu_j W + Sigma_k has
+    // lambda_max(C_j) <= nu_max lambda_max(W) + lambda_max(Sigma_k) and det C_j >= det Sigma_k, so
+    // each component's log2 density is at most log2(w_k amp_max / (2 pi sqrt(det Sigma_k))) -
+    // log2(e) |d|^2 / (2 (nu_max lambda_max(W) + lambda_max(Sigma_k))); both rounded up
+    double amp_max = 0.0, nu_max = 0.0;
+    for (int j = 0; j < ncomp; ++j) {
+      amp_max = fmax(amp_max, prof.amp[j]);
+      nu_max = fmax(nu_max, prof.var[j]);
+    }
+    auto lam_max = [](double a, double b, double c) { return 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b); };
+    const double lmax = nu_max * lam_max(sd.W.xx, sd.W.xy, sd.W.yy) + lam_max(ps[3], ps[4], ps[5]);
+    const double c0b = log2(ps[0] * amp_max) - log2(kTwoPi) - 0.5 * log2(ps[3] * ps[5] - ps[4] * ps[4]);
+    const double mub = -0.5 * kLog2e / lmax;
+    float c0f = (float)c0b, muf = (float)mub;
+    if ((double)c0f < c0b) c0f = nextafterf(c0f, INFINITY);
+    if ((double)muf < mub) muf = nextafterf(muf, INFINITY);
+    rec[tab::S_GC0] = c0f;
+    rec[tab::S_GMU] = muf;
   }
   for (int c = t; c < im.n_psf * ncomp; c += blockDim.x) {
     const int k = c / ncomp, j = c - k * ncomp;
