@@ -346,8 +346,8 @@ def main():
                          "batched workload at the plain start, then two 1 GiB device copies; no timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported in this build "
-              "(sources are independent, see the design notes on sharding)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (sources are "
+              "independent: several GPUs would each fit a share of the source list)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
