@@ -56,7 +56,7 @@ enum {
   CELESTE_E_INVALID = -1,      /* bad shape, range, NaN, band, or count */
   CELESTE_E_NOMEM = -2,        /* device or host allocation failed */
   CELESTE_E_DEVICE = -3,       /* a HIP runtime call failed */
-  CELESTE_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+  CELESTE_E_UNSUPPORTED = -4   /* valid request the library or the device does not support */
 };
 
 enum { CELESTE_MEM_HOST = 0, CELESTE_MEM_DEVICE = 1 };
