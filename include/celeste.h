@@ -409,7 +409,8 @@ typedef struct celeste_tune_result {
   int32_t from_cache;                         /* 1: taken from the cache file without timing */
   int64_t sample_sources, sample_px;          /* tuning sample */
   double full_ms, value_ms;                   /* best time per launch over the sample */
-  double default_full_ms, default_value_ms;   /* the default options' times on the same sample */
+  double default_full_ms, default_value_ms;   /* the default options' times on the same sample
+                                                 (default_full_ms from the same pass as full_ms) */
   double vector_full_ms, matrix_full_ms;      /* best value+gradient+Hessian time with J^T W J on the
                                                  vector units / on the matrix cores */
 } celeste_tune_result;
@@ -419,9 +420,12 @@ typedef struct celeste_tune_result {
  * sample of the batch (every k-th source, about sample_px pixels; sample_px <= 0 means
  * 6e7), evaluates it at theta (n_sources x 27, batch memory) with the value+gradient+
  * Hessian kernel under every candidate work-item size (4096..16384 px), block size,
- * register budget, J^T W J unit (vector or matrix cores) and tile width, then with the value kernel under every block size and
- * tile width, keeps the fastest (minimum of three timed launches each, HIP events on the
- * library's stream) and sets them on the context.  cache_path (may be NULL) names a text
+ * register budget, J^T W J unit (vector or matrix cores) and tile width (minimum of three
+ * timed launches each, HIP events on the library's stream), re-times the four fastest and
+ * the default options together (minimum of nine launches each) and keeps the fastest of
+ * that pass, so full_ms <= default_full_ms; then times the value kernel under every block
+ * size and tile width on the chosen work items, and sets the choice on the context (on an
+ * error the context keeps its earlier options).  cache_path (may be NULL) names a text
  * file of earlier choices, one per line, keyed by device, compute-unit count, component
  * counts and the batch's size class: a hit is applied without timing, a miss is appended.
  * out may be NULL.  Errors: as celeste_elbo_eval; E_INVALID for an unreadable or

@@ -1688,15 +1688,20 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
   HIPCHK(hipMemcpyAsync(ctx->theta.p, ths.data(), sizeof(double) * ths.size(), hipMemcpyHostToDevice, st));
   const double* th_dev = as<double>(ctx->theta);
 
-  const int saved_chunk = ctx->chunk_px;
+  // every return before the end leaves the context's work-item size as it was
+  struct ChunkGuard {
+    celeste_ctx* c;
+    int saved;
+    ~ChunkGuard() { c->chunk_px = saved; }
+  } guard{ctx, ctx->chunk_px};
   const int chunks[] = {4096, 8192, 16384};
   const int variants[] = {2, 3, 6, 7};
   struct Cand {
     double ms;
     int chunk, block, variant, tl;
+    bool is_default() const { return chunk == 4096 && block == 256 && variant == 3 && tl == 3; }
   };
   std::vector<Cand> cands;
-  double best = 1e300;
   int rc = CELESTE_OK;
   for (int chunk : chunks) {
     ctx->chunk_px = chunk;
@@ -1717,52 +1722,60 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
                                     ctx->e_zero, st);
           }, &ms);
           r.n_candidates += 1;
-          if (chunk == 4096 && block == 256 && variant == 3 && tl == 3) r.default_full_ms = ms;
           double& unit_best = (variant & 4) ? r.matrix_full_ms : r.vector_full_ms;
           if (rc == CELESTE_OK && (unit_best == 0.0 || ms < unit_best)) unit_best = ms;
           if (rc == CELESTE_OK) cands.push_back(Cand{ms, chunk, block, variant, tl});
         }
     if (rc != CELESTE_OK) break;
   }
-  // the four fastest again, nine launches each: candidates within a few per cent of each other
-  // are ordered by more than one noisy minimum
-  if (rc == CELESTE_OK && !cands.empty()) {
-    std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    cands.resize(std::min<size_t>(4, cands.size()));
-    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.chunk < y.chunk; });
+  if (rc != CELESTE_OK) return rc;
+  if (cands.empty()) return fail(CELESTE_E_DEVICE, "autotune: no candidate could be timed");
+  // the four fastest and the default again, nine launches each, in one pass: candidates within a
+  // few per cent of each other are ordered by more than one noisy minimum, and the default is
+  // timed beside them, so the pick is never slower than the default by the pass's own timings
+  std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  {
+    std::vector<Cand> fin(cands.begin(), cands.begin() + std::min<size_t>(4, cands.size()));
+    bool has_default = false;
+    for (const Cand& c : fin) has_default = has_default || c.is_default();
+    if (!has_default)
+      for (const Cand& c : cands)
+        if (c.is_default()) fin.push_back(c);
+    cands.swap(fin);
+  }
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.chunk < y.chunk; });
+  {
     int prepared = 0;
     Packed P;
     for (Cand& c : cands) {
       if (c.chunk != prepared) {
         ctx->chunk_px = c.chunk;
-        rc = validate_and_pack(ctx, &sub, &P);
-        if (rc == CELESTE_OK) rc = prepare(ctx, &sub, &P, st);
-        if (rc != CELESTE_OK) break;
+        CHK(validate_and_pack(ctx, &sub, &P));
+        CHK(prepare(ctx, &sub, &P, st));
         HIPCHK(launch_setup(as<ImgDev>(ctx->imgs), P.n_img, th_dev, nullptr, P.prof, as<float>(ctx->tables),
                             P.tstride, st));
         prepared = c.chunk;
       }
       const ImgDev* di = as<ImgDev>(ctx->imgs);
       float* tables = as<float>(ctx->tables);
-      rc = time_min(st, 9, [&]() {
+      CHK(time_min(st, 9, [&]() {
         return launch_eval_full(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
                                 P.prof.n_dev, nullptr, as<double>(ctx->partials), c.block, c.variant, c.tl,
                                 ctx->e_zero, st);
-      }, &c.ms);
-      if (rc != CELESTE_OK) break;
-      if (c.ms < best) {
-        best = c.ms;
-        r.full_ms = c.ms;
-        r.chunk_px = c.chunk;
-        r.block = c.block;
-        r.variant = c.variant;
-        r.tile_w = 1 << c.tl;
-      }
+      }, &c.ms));
+      if (c.is_default()) r.default_full_ms = c.ms;
     }
   }
-  if (rc != CELESTE_OK) {
-    ctx->chunk_px = saved_chunk;
-    return rc;
+  {
+    // fastest of the pass; on a tie the default stays
+    const Cand* pick = nullptr;
+    for (const Cand& c : cands)
+      if (!pick || c.ms < pick->ms || (c.ms == pick->ms && c.is_default())) pick = &c;
+    r.full_ms = pick->ms;
+    r.chunk_px = pick->chunk;
+    r.block = pick->block;
+    r.variant = pick->variant;
+    r.tile_w = 1 << pick->tl;
   }
   // value kernel on the chosen work items
   ctx->chunk_px = r.chunk_px;
@@ -1805,7 +1818,7 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
                                P.prof.n_dev, nullptr, as<double>(ctx->partials), 256, 3, 3, st);
     }, &r.default_value_ms));
   }
-  ctx->chunk_px = r.chunk_px;
+  guard.saved = r.chunk_px;  // the guard leaves the chosen size on the context
   ctx->block = r.block;
   ctx->variant = r.variant;
   ctx->tile_log2 = log2_tile(r.tile_w);
