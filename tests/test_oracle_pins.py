@@ -172,28 +172,60 @@ def test_integer_translation(cfg0):
 
 # ---------------------------------------------------------------------------- P6 / P7 derivatives
 
+# coordinates whose scale is their value (variances, e_scale) or their distance to the
+# bounds of (0, 1) (a, e_dev, e_axis); the others (u in px, e_angle in rad, the log-brightness
+# and colour means) have unit scale
+_POSITIVE = [6, 9, 10] + list(range(19, 27))
+_UNIT = [2, 3, 4]
+
+
+def _fd_steps(th, rel=1e-2):
+    """Per-coordinate steps: rel times the coordinate's scale, so that every step stays inside
+    the domain, the rounding of the differenced ELBO values (a few ulp of |L| ~ 2e4, divided
+    by the step) stays far below the tolerance, and the O(h^4) error left by Richardson
+    extrapolation is negligible."""
+    s = np.ones_like(th)
+    s[_POSITIVE] = th[_POSITIVE]
+    s[_UNIT] = np.minimum(th[_UNIT], 1.0 - th[_UNIT])
+    return rel * s
+
+
+def _richardson(f, th, h):
+    """Central differences of f along each coordinate, Richardson-extrapolated from steps
+    h and h/2: (4 D(h/2) - D(h)) / 3 cancels the h^2 term, leaving an O(h^4) error."""
+    out = []
+    for j in range(th.size):
+        def d(step):
+            tp, tm = th.copy(), th.copy()
+            tp[j] += step
+            tm[j] -= step
+            return (f(tp) - f(tm)) / (2.0 * step)
+        out.append((4.0 * d(0.5 * h[j]) - d(h[j])) / 3.0)
+    return np.array(out)
+
+
 def _fd_check(th, imgs, prior, profiles, rtol_g=1e-6, rtol_h=1e-6):
+    """Analytic gradient and Hessian against Richardson-extrapolated central differences of
+    the value (gradient) and of the analytic gradient (Hessian), per entry relative to
+    max(|e|, 1e-3 max|array|).  Returns the largest errors (they sit well below the
+    tolerance, so harmless changes of the evaluation point do not trip the pin)."""
     v, g, H = model.elbo(th, imgs, prior, profiles)
     assert np.max(np.abs(H - H.T)) <= 1e-12 * np.max(np.abs(H))
-    fdg = np.zeros(27)
-    fdH = np.zeros((27, 27))
-    for j in range(27):
-        h = 1e-5 * max(1.0, abs(th[j]))
-        tp, tm = th.copy(), th.copy()
-        tp[j] += h
-        tm[j] -= h
-        fdg[j] = (model.elbo_value(tp, imgs, prior, profiles) - model.elbo_value(tm, imgs, prior, profiles)) / (2 * h)
-        fdH[:, j] = (model.elbo(tp, imgs, prior, profiles)[1] - model.elbo(tm, imgs, prior, profiles)[1]) / (2 * h)
+    h = _fd_steps(th)
+    fdg = _richardson(lambda t: model.elbo_value(t, imgs, prior, profiles), th, h)
+    fdH = _richardson(lambda t: model.elbo(t, imgs, prior, profiles)[1], th, h).T
     eg = np.abs(fdg - g) / np.maximum(np.abs(g), 1e-3 * np.max(np.abs(g)))
     eh = np.abs(fdH - H) / np.maximum(np.abs(H), 1e-3 * np.max(np.abs(H)))
     assert eg.max() < rtol_g, (eg.max(), np.argmax(eg))
     assert eh.max() < rtol_h, (eh.max(), np.unravel_index(np.argmax(eh), eh.shape))
+    return eg.max(), eh.max()
 
 
 def test_gradient_hessian_finite_differences(cfg0):
     imgs = model.source_images(cfg0, 0)
     th = perturb_theta(cfg0.theta_truth, 1)[0]
-    _fd_check(th, imgs, cfg0.prior, cfg0.profiles)
+    eg, eh = _fd_check(th, imgs, cfg0.prior, cfg0.profiles)
+    assert eg < 1e-7 and eh < 1e-7          # ten times under the tolerance: room for harmless changes
 
 
 def test_fd_general_wcs_and_neighbours():
@@ -210,7 +242,8 @@ def test_fd_general_wcs_and_neighbours():
         im["nbr_var"] = rng.uniform(0, 5, (19, 21))
         imgs.append(im)
     th = perturb_theta(np.array([[5.2, 4.1] + [0.5] * 5 + [3.0, 3.2, 0.1, 0.1] + [0.3] * 8 + [0.05] * 8]), 3)[0]
-    _fd_check(th, imgs, synth.PRIOR, prof)
+    eg, eh = _fd_check(th, imgs, synth.PRIOR, prof)
+    assert eg < 1e-7 and eh < 1e-7
 
 
 # ---------------------------------------------------------------------------- P8 delta method
