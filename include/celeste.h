@@ -233,6 +233,29 @@ void celeste_fit_opts_default(celeste_fit_opts* opts);
 int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
                       double* elbo, double* grad, double* hess, void* stream);
 
+/* Size of the device array that celeste_elbo_eval_noalloc works in (64 MiB on each GPU). */
+#define CELESTE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* celeste_elbo_eval for callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same kernels and results
+ * (bitwise equal to celeste_elbo_eval under the same context options), with no hipMalloc,
+ * hipHostMalloc, hipFree or other allocating library call during the call.  Device memory
+ * for the packed metadata, setup tables, partial sums and flags comes from one library-wide
+ * array of CELESTE_NOALLOC_SCRATCH_BYTES per GPU, resident until the process ends; its
+ * device address is taken once per GPU when a context is created there.  Host-side packing
+ * uses the process heap.  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (from several threads, or on streams that
+ * run concurrently) race and must be serialised by the caller.
+ *   batch: mem_kind must be CELESTE_MEM_DEVICE (host batches need staging memory);
+ *   theta, elbo, grad, hess: device memory, as celeste_elbo_eval; stream as there.
+ * The call returns after the results are written.  About 4.9 KB per image (3 PSF
+ * components), 16 B per work item plus 624 B (value only: 8 B) per work item, 0.5 MB fixed:
+ * a batch of about 11,000 images fits.
+ * Errors: as celeste_elbo_eval; E_INVALID for a host batch; E_NOMEM (nothing launched) when
+ * the batch needs more than CELESTE_NOALLOC_SCRATCH_BYTES, with the size in the message. */
+int celeste_elbo_eval_noalloc(celeste_ctx* ctx, const celeste_batch* batch, const double* theta,
+                              double* elbo, double* grad, double* hess, void* stream);
+
 /* Pixel-subsampled estimate of the same quantities (the paper's closing section names
  * subsampling pixels, a second source of randomness in the stochastic optimisation, as a
  * further speed-up).  Each image is cut into 8-row blocks (the last one may be shorter);

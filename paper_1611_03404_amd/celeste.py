@@ -106,6 +106,7 @@ def load():
     lib.celeste_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
     lib.celeste_fit_opts_default.restype = None
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
+    lib.celeste_elbo_eval_noalloc.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_lr_covariance_from_hessian.argtypes = [vp, i64, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp, vp,
                                                        vp, vp]
     lib.celeste_lr_covariance.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, ctypes.c_double, vp, vp, vp]
@@ -362,6 +363,25 @@ class Context:
         _check(load().celeste_elbo_eval(self._h, ctypes.byref(batch.c), _ptr(th), _ptr(elbo),
                                         _ptr(grad) if grad is not None else None,
                                         _ptr(hess) if hess is not None else None, self._stream(batch)))
+        return elbo, grad, hess
+
+    def elbo_eval_noalloc(self, batch: Batch, theta, elbo, grad=None, hess=None):
+        """elbo_eval into caller-owned device tensors through the entry point that allocates
+        nothing (celeste_elbo_eval_noalloc): a device batch (the library refuses host batches),
+        theta (S, 27), and float64 CUDA tensors elbo (S,), grad (S, 27) or None, hess
+        (S, 27, 27) or None."""
+        S = batch.n_sources
+        th = batch.as_input(theta)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta must have shape ({S}, {NP})")
+        for name, t, shape in (("elbo", elbo, (S,)), ("grad", grad, (S, NP)), ("hess", hess, (S, NP, NP))):
+            if t is None:
+                continue
+            if not (_is_torch(t) and t.is_cuda) or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA tensor of shape {shape}")
+        _check(load().celeste_elbo_eval_noalloc(self._h, ctypes.byref(batch.c), _ptr(th), _ptr(elbo),
+                                                _ptr(grad) if grad is not None else None,
+                                                _ptr(hess) if hess is not None else None, self._stream(batch)))
         return elbo, grad, hess
 
     def elbo_eval_sampled(self, batch: Batch, theta, keep, keep_off, keep_prob, want="hess"):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -263,6 +264,14 @@ int check_theta(const double* th, int64_t s) {
 
 // Host-side packed metadata; the arrays live in the context's pinned staging buffers (valid
 // until the context packs the next batch).
+// Host storage of the packed metadata from the process heap (the no-allocation entry point),
+// instead of the context's pinned buffers.
+struct HostPack {
+  std::vector<ImgDev> imgs;
+  std::vector<WorkItem> items;
+  std::vector<SrcDev> srcs;
+};
+
 struct Packed {
   ImgDev* imgs = nullptr;
   WorkItem* items = nullptr;
@@ -294,7 +303,7 @@ int items_of(const celeste_image& im, int chunk) {
   return (im.h + band - 1) / band;
 }
 
-int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
+int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P, HostPack* hp = nullptr) {
   if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
   if (!b) return fail(CELESTE_E_INVALID, "batch is NULL");
   if (b->n_sources < 1) return fail(CELESTE_E_INVALID, "n_sources must be >= 1");
@@ -338,17 +347,30 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P) {
   P->tstride = table_stride(max_psf, P->prof.n_exp, P->prof.n_dev);
   P->n_src = b->n_sources;
   P->n_img = (int)n_img;
-  CHK(ensure_host(ctx->h_imgs, sizeof(ImgDev) * n_img));
-  CHK(ensure_host(ctx->h_srcs, sizeof(SrcDev) * b->n_sources));
-  P->imgs = as<ImgDev>(ctx->h_imgs);
-  P->srcs = as<SrcDev>(ctx->h_srcs);
+  if (hp) {
+    hp->imgs.resize((size_t)n_img);
+    hp->srcs.resize((size_t)b->n_sources);
+    P->imgs = hp->imgs.data();
+    P->srcs = hp->srcs.data();
+  } else {
+    CHK(ensure_host(ctx->h_imgs, sizeof(ImgDev) * n_img));
+    CHK(ensure_host(ctx->h_srcs, sizeof(SrcDev) * b->n_sources));
+    P->imgs = as<ImgDev>(ctx->h_imgs);
+    P->srcs = as<SrcDev>(ctx->h_srcs);
+  }
+
   const int chunk = std::max(64, ctx->chunk_px);
   // work-item offsets per image (items in image order, so per source contiguous)
   std::vector<int64_t> first_item(n_img + 1, 0);
   for (int64_t i = 0; i < n_img; ++i) first_item[i + 1] = first_item[i] + items_of(b->images[i], chunk);
   if (first_item[n_img] > (int64_t)INT32_MAX / 2) return fail(CELESTE_E_INVALID, "too many work items");
-  CHK(ensure_host(ctx->h_items, sizeof(WorkItem) * first_item[n_img]));
-  P->items = as<WorkItem>(ctx->h_items);
+  if (hp) {
+    hp->items.resize((size_t)first_item[n_img]);
+    P->items = hp->items.data();
+  } else {
+    CHK(ensure_host(ctx->h_items, sizeof(WorkItem) * first_item[n_img]));
+    P->items = as<WorkItem>(ctx->h_items);
+  }
   std::vector<int> src_of(n_img);
   for (int s = 0; s < b->n_sources; ++s)
     for (int64_t i = b->image_offsets[s]; i < b->image_offsets[s + 1]; ++i) src_of[i] = s;
@@ -481,10 +503,22 @@ int stage_host_pixels(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipSt
   return CELESTE_OK;
 }
 
-// Metadata upload + pixel validation + per-image constants (the last two only when the
-// call reads pixels).  Synchronous.
-int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st, bool pixels = true) {
-  if (b->mem_kind == CELESTE_MEM_HOST) CHK(stage_host_pixels(ctx, b, P, st));
+// Device buffers of one evaluation: packed metadata, setup tables, per-item partial sums,
+// per-image constants, the pixel-check flag and the log n! table.
+struct EvalBufs {
+  ImgDev* imgs = nullptr;
+  WorkItem* items = nullptr;
+  SrcDev* srcs = nullptr;
+  double* img_const = nullptr;
+  float* tables = nullptr;
+  double* partials = nullptr;
+  int* flag = nullptr;
+  double* lfact = nullptr;
+  bool lfact_ready = false;   // the table holds its values (else it is filled before use)
+};
+
+// The context's own buffers, grown to the batch.
+int ctx_bufs(celeste_ctx* ctx, const Packed* P, EvalBufs* B) {
   CHK(ensure(ctx->imgs, sizeof(ImgDev) * P->n_img));
   CHK(ensure(ctx->items, sizeof(WorkItem) * P->n_items));
   CHK(ensure(ctx->srcs, sizeof(SrcDev) * P->n_src));
@@ -492,26 +526,51 @@ int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st,
   CHK(ensure(ctx->tables, sizeof(float) * (size_t)P->tstride * P->n_img));
   CHK(ensure(ctx->partials, sizeof(double) * (size_t)NACC * P->n_items));
   CHK(ensure(ctx->flag, sizeof(int) * 4));
-  HIPCHK(hipMemcpyAsync(ctx->imgs.p, P->imgs, sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ctx->items.p, P->items, sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ctx->srcs.p, P->srcs, sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
+  if (!ctx->lfact_ready) CHK(ensure(ctx->lfact, sizeof(double) * LFACT_N));
+  B->imgs = as<ImgDev>(ctx->imgs);
+  B->items = as<WorkItem>(ctx->items);
+  B->srcs = as<SrcDev>(ctx->srcs);
+  B->img_const = as<double>(ctx->img_const);
+  B->tables = as<float>(ctx->tables);
+  B->partials = as<double>(ctx->partials);
+  B->flag = as<int>(ctx->flag);
+  B->lfact = as<double>(ctx->lfact);
+  B->lfact_ready = ctx->lfact_ready;
+  return CELESTE_OK;
+}
+
+// Metadata upload + pixel validation + per-image constants (the last two only when the
+// call reads pixels) into the buffers B.  Synchronous.  Host batches are staged in the
+// context's staging buffer first.
+int prepare_in(celeste_ctx* ctx, const celeste_batch* b, Packed* P, EvalBufs* B, hipStream_t st, bool pixels) {
+  if (b->mem_kind == CELESTE_MEM_HOST) CHK(stage_host_pixels(ctx, b, P, st));
+  HIPCHK(hipMemcpyAsync(B->imgs, P->imgs, sizeof(ImgDev) * P->n_img, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(B->items, P->items, sizeof(WorkItem) * P->n_items, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(B->srcs, P->srcs, sizeof(SrcDev) * P->n_src, hipMemcpyHostToDevice, st));
   if (!pixels) {
     HIPCHK(hipStreamSynchronize(st));
     return CELESTE_OK;
   }
-  if (!ctx->lfact_ready) {
-    CHK(ensure(ctx->lfact, sizeof(double) * LFACT_N));
-    HIPCHK(launch_lfact(as<double>(ctx->lfact), st));
-    ctx->lfact_ready = true;   // complete before first use: the check below synchronises the stream
+  if (!B->lfact_ready) {
+    HIPCHK(launch_lfact(B->lfact, st));
+    B->lfact_ready = true;   // complete before first use: the check below synchronises the stream
   }
-  HIPCHK(launch_zero_int(as<int>(ctx->flag), 4, st));
-  HIPCHK(launch_check_const(as<ImgDev>(ctx->imgs), P->n_img, as<double>(ctx->lfact), as<double>(ctx->img_const),
-                            as<int>(ctx->flag), st));
+  HIPCHK(launch_zero_int(B->flag, 4, st));
+  HIPCHK(launch_check_const(B->imgs, P->n_img, B->lfact, B->img_const, B->flag, st));
   int bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&bad, B->flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (bad) return fail(CELESTE_E_INVALID, "pixel or neighbour arrays hold negative or non-finite values");
   return CELESTE_OK;
+}
+
+// prepare_in on the context's own buffers.
+int prepare(celeste_ctx* ctx, const celeste_batch* b, Packed* P, hipStream_t st, bool pixels = true) {
+  EvalBufs B;
+  CHK(ctx_bufs(ctx, P, &B));
+  const int rc = prepare_in(ctx, b, P, &B, st, pixels);
+  ctx->lfact_ready = ctx->lfact_ready || B.lfact_ready;
+  return rc;
 }
 
 hipStream_t pick(celeste_ctx* ctx, void* stream) { return stream ? (hipStream_t)stream : ctx->stream; }
@@ -544,7 +603,9 @@ struct PhaseTimer {
 };
 
 int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
-              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob);
+              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob,
+              bool noalloc = false);
+int scratch_init(int device);
 
 }  // namespace
 
@@ -579,6 +640,10 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
   celeste_ctx* c = new (std::nothrow) celeste_ctx();
   if (!c) return fail(CELESTE_E_NOMEM, "context allocation failed");
   c->device = hip_device;
+  if (scratch_init(hip_device) != CELESTE_OK) {   // device address of the no-allocation scratch
+    delete c;
+    return CELESTE_E_DEVICE;
+  }
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
@@ -710,6 +775,11 @@ int celeste_elbo_eval(celeste_ctx* ctx, const celeste_batch* b, const double* th
   return eval_impl(ctx, b, theta, elbo, grad, hess, stream, nullptr, nullptr, 1.0);
 }
 
+int celeste_elbo_eval_noalloc(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo,
+                              double* grad, double* hess, void* stream) {
+  return eval_impl(ctx, b, theta, elbo, grad, hess, stream, nullptr, nullptr, 1.0, true);
+}
+
 int celeste_elbo_eval_sampled(celeste_ctx* ctx, const celeste_batch* b, const double* theta, const uint8_t* keep,
                               const int64_t* keep_off, double keep_prob, double* elbo, double* grad, double* hess,
                               void* stream) {
@@ -789,12 +859,19 @@ int celeste_lr_covariance(celeste_ctx* ctx, const celeste_batch* b, const double
 
 namespace {
 
+int scratch_bufs(celeste_ctx* ctx, const Packed* P, int per_item, EvalBufs* B);
+void scratch_lfact_filled(int device);
+
 int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, double* elbo, double* grad,
-              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob) {
+              double* hess, void* stream, const uint8_t* keep, const int64_t* keep_off, double keep_prob,
+              bool noalloc) {
   Packed P;
-  CHK(validate_and_pack(ctx, b, &P));
+  HostPack hp;
+  CHK(validate_and_pack(ctx, b, &P, noalloc ? &hp : nullptr));
   if (!theta || !elbo) return fail(CELESTE_E_INVALID, "theta and elbo must not be NULL");
   if (hess && !grad) return fail(CELESTE_E_INVALID, "hess requires grad");
+  if (noalloc && b->mem_kind != CELESTE_MEM_DEVICE)
+    return fail(CELESTE_E_INVALID, "the no-allocation evaluation takes device batches only (mem_kind DEVICE)");
   HIPCHK(hipSetDevice(ctx->device));
   const hipStream_t st = pick(ctx, stream);
   const size_t S = P.n_src;
@@ -817,7 +894,18 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
     CHK(subsample_items(ctx, b, &P, keep, keep_off, kept_rows));
     px_weight = 1.0 / keep_prob;
   }
-  CHK(prepare(ctx, b, &P, st));
+  EvalBufs B;
+  if (noalloc) {
+    CHK(scratch_bufs(ctx, &P, grad ? NACC : 1, &B));
+    const int rc = prepare_in(ctx, b, &P, &B, st, true);
+    if (B.lfact_ready) scratch_lfact_filled(ctx->device);
+    CHK(rc);
+  } else {
+    CHK(ctx_bufs(ctx, &P, &B));
+    const int rc = prepare_in(ctx, b, &P, &B, st, true);
+    ctx->lfact_ready = ctx->lfact_ready || B.lfact_ready;
+    CHK(rc);
+  }
   const int* kept = nullptr;
   if (keep) {
     CHK(ensure(ctx->kept, sizeof(int) * std::max<size_t>(1, kept_rows.size())));
@@ -838,29 +926,24 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
       d_hess = as<double>(ctx->o_hess);
     }
   }
-  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
   PhaseTimer T;
-  CHK(T.init(ctx->profile != 0));
+  CHK(T.init(ctx->profile != 0 && !noalloc));   // events are not created on the no-allocation path
   T.mark(0, st);
-  HIPCHK(launch_setup(imgs, P.n_img, th_dev, nullptr, P.prof, as<float>(ctx->tables), P.tstride, st));
+  HIPCHK(launch_setup(B.imgs, P.n_img, th_dev, nullptr, P.prof, B.tables, P.tstride, st));
   T.mark(1, st);
   if (grad) {
-    HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                            P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->block, ctx->variant,
-                            ctx->tile_log2, ctx->e_zero, st, kept));
+    HIPCHK(launch_eval_full(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
+                            B.partials, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
     T.mark(2, st);
-    HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
-                              as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, d_grad, d_hess,
-                              ctr_full(ctx), st, px_weight));
+    HIPCHK(launch_reduce_full(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
+                              d_grad, d_hess, ctr_full(ctx), st, px_weight));
     ctx->stats.full_launches += 1;
   } else {
-    HIPCHK(launch_eval_value(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
-                             P.prof.n_exp, P.prof.n_dev, nullptr, as<double>(ctx->partials), ctx->vblock, ctx->variant,
-                             ctx->vtile_log2, st, kept));
+    HIPCHK(launch_eval_value(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
+                             B.partials, ctx->vblock, ctx->variant, ctx->vtile_log2, st, kept));
     T.mark(2, st);
-    HIPCHK(launch_reduce_value(as<SrcDev>(ctx->srcs), P.n_src, imgs, as<double>(ctx->partials),
-                               as<double>(ctx->img_const), th_dev, P.prior, nullptr, d_elbo, ctr_value(ctx), st,
-                               px_weight));
+    HIPCHK(launch_reduce_value(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
+                               ctr_value(ctx), st, px_weight));
     ctx->stats.value_launches += 1;
   }
   T.mark(3, st);
@@ -876,6 +959,93 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
     (grad ? ctx->stats.ms_reduce_full : ctx->stats.ms_reduce_value) += T.span(2, 3);
   }
   return CELESTE_OK;
+}
+
+}  // namespace
+
+// =============================================================================== no-allocation scratch
+
+// Device memory of celeste_elbo_eval_noalloc: one array on every GPU the library runs on,
+// resident from the code object's load until the process ends, shared by every such call on
+// that GPU (it keeps the last call's contents, and calls that overlap on one GPU race).  In
+// host code the array's name is a host-side stand-in, not a device address: host code uses
+// only the per-device address that hipGetSymbolAddress returns (scratch_init).
+static __device__ __align__(256) unsigned char scratch[CELESTE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct ScratchSlot {
+  unsigned char* ptr = nullptr;   // device address of the scratch array on this GPU
+  bool lfact_ready = false;       // its log n! region holds the table
+};
+std::mutex g_scratch_mu;
+std::unordered_map<int, ScratchSlot> g_scratch;
+
+// Once per device, with that device current (context creation): the device address of the
+// scratch array on it.
+int scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ScratchSlot& sl = g_scratch[device];
+  if (sl.ptr) return CELESTE_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(CELESTE_E_DEVICE, "address of the scratch array on device %d: %s", device, hipGetErrorString(e));
+  }
+  sl.ptr = static_cast<unsigned char*>(ptr);
+  return CELESTE_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// The buffers of one evaluation carved from the device's scratch array: the log n! table
+// first (filled once per device, never written by anything else), then the call's own
+// regions.  E_NOMEM when the batch does not fit.
+int scratch_bufs(celeste_ctx* ctx, const Packed* P, int per_item, EvalBufs* B) {
+  ScratchSlot sl;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(ctx->device);
+    if (it == g_scratch.end() || !it->second.ptr)
+      return fail(CELESTE_E_DEVICE, "no scratch address for device %d", ctx->device);
+    sl = it->second;
+  }
+  size_t off = 0;
+  auto carve = [&off](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t o_lfact = carve(sizeof(double) * LFACT_N);
+  const size_t o_flag = carve(sizeof(int) * 4);
+  const size_t o_imgs = carve(sizeof(ImgDev) * P->n_img);
+  const size_t o_items = carve(sizeof(WorkItem) * P->n_items);
+  const size_t o_srcs = carve(sizeof(SrcDev) * P->n_src);
+  const size_t o_const = carve(sizeof(double) * P->n_img);
+  const size_t o_tables = carve(sizeof(float) * (size_t)P->tstride * P->n_img);
+  const size_t o_part = carve(sizeof(double) * (size_t)per_item * P->n_items);
+  if (off > CELESTE_NOALLOC_SCRATCH_BYTES)
+    return fail(CELESTE_E_NOMEM,
+                "the batch (%d sources, %d images, %d work items) needs %zu bytes of device scratch; "
+                "celeste_elbo_eval_noalloc holds at most %zu: split the batch or use celeste_elbo_eval",
+                P->n_src, P->n_img, P->n_items, off, (size_t)CELESTE_NOALLOC_SCRATCH_BYTES);
+  unsigned char* base = sl.ptr;
+  B->lfact = reinterpret_cast<double*>(base + o_lfact);
+  B->flag = reinterpret_cast<int*>(base + o_flag);
+  B->imgs = reinterpret_cast<ImgDev*>(base + o_imgs);
+  B->items = reinterpret_cast<WorkItem*>(base + o_items);
+  B->srcs = reinterpret_cast<SrcDev*>(base + o_srcs);
+  B->img_const = reinterpret_cast<double*>(base + o_const);
+  B->tables = reinterpret_cast<float*>(base + o_tables);
+  B->partials = reinterpret_cast<double*>(base + o_part);
+  B->lfact_ready = sl.lfact_ready;
+  return CELESTE_OK;
+}
+
+void scratch_lfact_filled(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  g_scratch[device].lfact_ready = true;
 }
 
 }  // namespace

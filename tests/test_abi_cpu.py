@@ -45,6 +45,7 @@ def test_defaults_and_null_context_errors():
     assert b"context" in lib.celeste_last_error()
     b = cb.CBatch()
     assert lib.celeste_elbo_eval(None, ctypes.byref(b), None, None, None, None, None) == cb.E_INVALID
+    assert lib.celeste_elbo_eval_noalloc(None, ctypes.byref(b), None, None, None, None, None) == cb.E_INVALID
     assert lib.celeste_batch_fit(None, ctypes.byref(b), None, None, None, None) == cb.E_INVALID
     assert lib.celeste_autotune(None, ctypes.byref(b), None, 0, None, None) == cb.E_INVALID
     for opt, bad in ((cb.OPT_TILE_W, 12), (cb.OPT_VALUE_BLOCK, 64), (cb.OPT_VALUE_TILE_W, 4)):
