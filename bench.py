@@ -71,6 +71,26 @@ def flop_value_per_px(K, E, D):
     return K * (13 + 8 * (E + D)) + 30
 
 
+def flop_full_per_px_algorithmic(K, E, D):
+    """Algorithmic FP32 FLOPs of one value+gradient+Hessian pixel evaluation by the work units
+    of the formulation: about 170 per galaxy component (the value, 5 gradient and 15 Hessian
+    entries of a PSF-convolved Gaussian), 30 per star component and 400 per pixel for the rate
+    moments and the delta-method term; the 78 FP64 accumulations (about 200 FLOP) are not
+    counted.  The roofline's achieved rate uses this figure: it counts the work of every
+    component, including those the kernel skips where they are exactly zero."""
+    return 170 * K * (E + D) + 30 * K + 400
+
+
+def stratified_sample(npx, n, seed):
+    """One source drawn at random from each of n equal-count strata of the pixel-count order
+    (a size-stratified sample of n sources)."""
+    import numpy as np
+    order = np.argsort(npx, kind="stable")
+    edges = np.linspace(0, len(order), n + 1).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    return [int(order[rng.integers(edges[i], edges[i + 1])]) for i in range(n) if edges[i + 1] > edges[i]]
+
+
 def _one_thread():
     """Pool initialiser: one BLAS/OpenMP thread per worker process."""
     from threadpoolctl import threadpool_limits
@@ -92,56 +112,128 @@ def _oracle_eval_worker(args):
     from oracle import model
     imgs = model.source_images(sb, s)
     t0 = time.perf_counter()
-    model.elbo(theta, imgs, sb.prior, sb.profiles)
+    v, g, H = model.elbo(theta, imgs, sb.prior, sb.profiles)
     t1 = time.perf_counter()
     model.elbo_value(theta, imgs, sb.prior, sb.profiles)
     t2 = time.perf_counter()
     npx = int(sum(int(im["h"]) * int(im["w"]) for im in imgs))
-    return npx, t1 - t0, t2 - t1
+    return npx, t1 - t0, t2 - t1, v, g, H
 
 
-def cpu_baseline(sb, theta0, gpu_full_px_per_step, gpu_value_px_per_step, converged_per_step, budget_s=20.0):
-    """Oracle timed on the host cores: full and value evaluations of random sources of the
-    same workload, scaled to whole fits with the pixel-evaluation counts of the GPU fits."""
+def _rel_stats(x):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    return {"max": float(np.max(x)), "median": float(np.median(x))}
+
+
+def cpu_baseline(sb, theta_fit, gpu_eval, gpu_full_px_per_step, gpu_value_px_per_step, converged_per_step,
+                 budget_s=20.0):
+    """Oracle timed on the host cores on a size-stratified sample of the workload: one
+    value+gradient+Hessian and one value evaluation of each sampled source at the GPU fit's
+    final parameters, scaled to whole fits with the GPU fits' pixel-evaluation counts per step.
+    The same evaluations give the GPU's error against the oracle there: gpu_eval(pick) returns
+    the GPU's ELBO, gradient and Hessian of the picked sources at theta_fit."""
     import multiprocessing as mp
     import numpy as np
-    from oracle import init as oinit
-    from oracle import model
     cores = max(1, min(16, os.cpu_count() or 1))
-    rng = np.random.default_rng(161103404)
-    order = rng.permutation(sb.n_sources)
-    npx = np.array([int(np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64) ** 2))
-                    for s in range(sb.n_sources)])
-    # take random sources until the estimated oracle work (~6e-5 core-s per full pixel) fills the budget
-    pick, est = [], 0.0
-    for s in order:
-        if est > budget_s * cores:
-            break
-        pick.append(int(s))
-        est += 7e-5 * npx[s]
-        if len(pick) >= 4 * cores:
-            break
+    npx = np.array([int(np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64)
+                               * sb.img_w[sb.src_img_off[s]:sb.src_img_off[s + 1]])) for s in range(sb.n_sources)])
+    # as many strata as the budget holds at ~8e-5 core-s per pixel (one full and one value evaluation)
+    n = int(max(cores, min(4 * cores, budget_s * cores / (8e-5 * float(np.mean(npx))))))
+    pick = stratified_sample(npx, n, 161103404)
     sub = sb.subset(pick)
-    args = []
-    for k in range(sub.n_sources):
-        imgs = model.source_images(sub, k)
-        args.append((sub, k, oinit.plain_init(sub.u_cat[k], imgs, sub.prior)))
+    args = [(sub, k, np.asarray(theta_fit[s], dtype=np.float64)) for k, s in enumerate(pick)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores, initializer=_one_thread) as pool:
         out = pool.map(_oracle_eval_worker, args, chunksize=1)
     wall = time.perf_counter() - t0
     px = sum(o[0] for o in out)
-    t_full = sum(o[1] for o in out)
-    t_val = sum(o[2] for o in out)
-    full_rate = px / t_full * cores          # full pixel-evals/s on all cores
-    val_rate = px / t_val * cores
+    full_rate = px / sum(o[1] for o in out) * cores          # full pixel-evals/s on all cores
+    val_rate = px / sum(o[2] for o in out) * cores
     step_s = gpu_full_px_per_step / full_rate + gpu_value_px_per_step / val_rate
+    el, g, H = gpu_eval(pick)
+    e_rel = [abs(el[k] - o[3]) / abs(o[3]) for k, o in enumerate(out)]
+
+    def a23(got, ref):
+        scale = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+        return float(np.max(np.abs(got - ref) / scale))
+
     return {
         "value": converged_per_step / step_s, "unit": "converged sources/s", "cores": cores, "kind": "oracle",
-        "sample": (f"{len(pick)} random sources of the same workload ({px} px), one value+gradient+Hessian and one "
-                   f"value evaluation each at the plain start on {cores} processes ({wall:.1f} s wall); scaled to "
-                   f"whole fits with the GPU fits' pixel-evaluation counts per step"),
+        "sample": (f"size-stratified sample of {len(pick)} sources of the same workload (one per equal-count "
+                   f"stratum of the pixel-count order, {px} px): one value+gradient+Hessian and one value "
+                   f"evaluation each at the GPU fit's final parameters on {cores} processes ({wall:.1f} s wall); "
+                   f"scaled to whole fits with the GPU fits' pixel-evaluation counts per step (extrapolated)"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
+        "gpu_error_at_fitted_theta": {
+            "sources": len(pick),
+            "elbo_rel": _rel_stats(e_rel),
+            "hessian_a23": _rel_stats([a23(H[k], o[5]) for k, o in enumerate(out)]),
+            "gradient_a23": _rel_stats([a23(g[k], o[4]) for k, o in enumerate(out)]),
+            "note": ("relative to max(|e*|, 1e-3 max|array*|) per source; the fitted point is stationary in the "
+                     "fit's coordinates, so gradient entries there are differences of nearly cancelling terms"),
+        },
+    }
+
+
+_FIT_JOB = None   # the sampled subset: inherited by forked workers
+
+
+def _oracle_fit_worker(s):
+    sb = _FIT_JOB
+    from oracle import init as oinit
+    from oracle import model, newton
+    imgs = model.source_images(sb, s)
+    t0 = time.perf_counter()
+    th0 = oinit.plain_init(sb.u_cat[s], imgs, sb.prior)
+    r = newton.fit(th0, imgs, sb.prior, sb.profiles)
+    return time.perf_counter() - t0, float(r.f), int(r.iters), int(r.status)
+
+
+def oracle_fit_baseline(sb, n, gpu_plain_elbo, gpu_head_elbo, log):
+    """Complete oracle fits from the plain start of a size-stratified sample of n sources,
+    timed on the host cores (measured fits, extrapolated to the workload by stratum), and the
+    GPU fits' final ELBO against the oracle-converged one (pass: within 1e-5 |L*| or above)."""
+    import multiprocessing as mp
+    import numpy as np
+    cores = max(1, min(16, os.cpu_count() or 1))
+    npx = np.array([int(np.sum(sb.img_h[sb.src_img_off[s]:sb.src_img_off[s + 1]].astype(np.int64)
+                               * sb.img_w[sb.src_img_off[s]:sb.src_img_off[s + 1]])) for s in range(sb.n_sources)])
+    pick = stratified_sample(npx, n, 161103408)
+    sub = sb.subset(pick)
+    order = np.argsort(-npx[pick], kind="stable")       # largest first, for the pool's balance
+    out = [None] * len(pick)
+    global _FIT_JOB
+    _FIT_JOB = sub
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores, initializer=_one_thread) as pool:
+        for done, (j, o) in enumerate(pool.imap_unordered(_indexed(_oracle_fit_worker), [int(j) for j in order])):
+            out[j] = o
+            log(f"oracle fit {done + 1}/{len(pick)}: source {pick[j]} ({npx[pick[j]]} px) {o[0]:.1f} s, "
+                f"{o[2]} iterations, status {o[3]} ({time.perf_counter() - t0:.0f} s)")
+    wall = time.perf_counter() - t0
+    _FIT_JOB = None
+    t_fit = np.array([o[0] for o in out])
+    ref = np.array([o[1] for o in out])
+    conv = np.array([o[3] == 0 for o in out])
+    # each sampled source stands for its stratum (sb.n_sources / n sources)
+    est_core_s = float(np.sum(t_fit)) * sb.n_sources / len(pick)
+    est_conv = float(np.mean(conv)) * sb.n_sources
+
+    def a22(gpu):
+        got = np.asarray(gpu)[pick]
+        return int(np.sum((np.abs(got - ref) <= 1e-5 * np.abs(ref)) | (got >= ref)))
+
+    return {
+        "value": est_conv / (est_core_s / cores), "unit": "converged sources/s", "cores": cores, "kind": "oracle",
+        "sample": (f"complete oracle fits from the plain start of a size-stratified sample of {len(pick)} sources "
+                   f"(one per equal-count stratum of the pixel-count order) on {cores} processes, {wall:.0f} s wall; "
+                   f"the rate scales the sample's measured fit times to the {sb.n_sources}-source workload"),
+        "measured_fits_per_s": len(pick) / wall,
+        "oracle_iterations_mean": float(np.mean([o[2] for o in out])),
+        "oracle_converged": int(np.sum(conv)),
+        "a22_pass_plain_start": a22(gpu_plain_elbo), "a22_pass_headline_start": a22(gpu_head_elbo),
+        "sources": len(pick),
     }
 
 
@@ -322,6 +414,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--no-surrogate", action="store_true", help="plain start only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-fits", type=int, default=0,
+                    help="batched workload: also fit a size-stratified sample of this many sources with the oracle "
+                         "(complete fits on the host cores; 200 = 1%% of the workload takes about 15 minutes on 16 "
+                         "cores) and check the GPU fits' final ELBO against the oracle-converged one")
     ap.add_argument("--workload", choices=("batched", "field", "sampled"), default="batched",
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps; sampled: pixel-subsampled "
@@ -368,7 +464,6 @@ def main():
         if not all(0.0 < float(x) <= 1.0 for x in args.sweep_probs.split(",") + [args.keep_prob] if x != ""):
             sys.exit("--keep-prob and --sweep-probs must be in (0, 1]")
         return sampled_bench(args, ctx, log)
-    ctx.set_option(cb.OPT_PROFILE, 1)
     sur_info = None
     net = None
     if not args.no_surrogate:
@@ -406,6 +501,9 @@ def main():
     runs = {}
     for name, mode in modes:
         opts = cb.default_opts(init_mode=mode)
+        # timed steps: the production path (each iteration replays a captured HIP graph; the host
+        # reads the active-source count every poll_every iterations)
+        ctx.set_option(cb.OPT_PROFILE, 0)
         for w in range(args.warmup):
             t = time.perf_counter()
             ctx.batch_fit(batch, theta0, opts)
@@ -423,7 +521,24 @@ def main():
             log(f"{name} step {k}: {time.perf_counter() - ts:.2f} s, converged {c}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        runs[name] = dict(wall=wall, res=res, conv=conv, stats=ctx.stats(), theta=th)
+        st_graph = ctx.stats()
+        # one more step in profile mode (eager launches, HIP events around every kernel phase on
+        # the library's stream, the stream drained at every host stage): the phase split and the
+        # roofline's per-launch durations; its wall time is the eager path's
+        ctx.set_option(cb.OPT_PROFILE, 1)
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        th_p, res_p = ctx.batch_fit(batch, theta0, opts)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - tp
+        st_prof = ctx.stats()
+        ctx.set_option(cb.OPT_PROFILE, 0)
+        same = bool(np.array_equal(res_p["elbo"], res["elbo"]) and np.array_equal(res_p["iters"], res["iters"]))
+        log(f"{name} profiled step: {wall_p:.2f} s (graph path {wall / args.steps:.2f} s per step); "
+            f"results identical to the graph path: {same}")
+        runs[name] = dict(wall=wall, res=res, conv=conv, stats=st_graph, prof=st_prof, wall_prof=wall_p,
+                          prof_same=same, theta=th)
     # ELBO tolerance rule against the best optimum either start reached
     best = np.max(np.stack([r["res"]["elbo"] for r in runs.values()]), axis=0)
 
@@ -438,10 +553,10 @@ def main():
     conv_tol = at_tol(H["res"]) * args.steps
     K = 3
     E, D = len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0])
-    f_full = flop_full_per_px(K, E, D)
-    # roofline over every value+gradient+Hessian launch of the timed steps of both starts
-    # (the launches a kernel trace of this command sees on the workload's grid)
-    rl = {k: sum(r["stats"][k] for r in runs.values()) for k in ("ms_full", "full_px", "full_launches")}
+    f_full = flop_full_per_px_algorithmic(K, E, D)
+    # roofline over the value+gradient+Hessian launches of the profiled steps of both starts
+    # (HIP events on the library's stream around each launch)
+    rl = {k: sum(r["prof"][k] for r in runs.values()) for k in ("ms_full", "full_px", "full_launches")}
     full_s = rl["ms_full"] / 1e3
     achieved = f_full * rl["full_px"] / full_s / 1e12 if full_s > 0 else 0.0
     hbm_bytes = 4.0 * rl["full_px"]
@@ -455,6 +570,7 @@ def main():
     def summary(r):
         rr = r["res"]
         return {"converged_per_s": at_tol(rr) * args.steps / r["wall"], "ms_per_step": 1e3 * r["wall"] / args.steps,
+                "ms_per_step_eager_profiled": 1e3 * r["wall_prof"], "profiled_results_identical": r["prof_same"],
                 "converged_status": int(np.sum(rr["status"] == cb.CONVERGED)), "converged_at_tol": at_tol(rr),
                 "iterations_mean": float(np.mean(rr["iters"])), "full_evals_mean": float(np.mean(rr["n_full_evals"])),
                 "fallback_rate": float(np.mean((rr["flags"] & cb.FLAG_FALLBACK_USED) != 0)),
@@ -468,6 +584,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step_eager_profiled": 1e3 * H["wall_prof"],
+        "timed_path": "HIP-graph replay of each iteration, active count read every 4 iterations (profile mode off)",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -485,7 +603,8 @@ def main():
         "iterations_mean": float(np.mean(iters)), "iterations_max": int(np.max(iters)),
         "iterations_hist": np.bincount(iters, minlength=52).tolist(),
         "status": status_counts,
-        "phase_ms_per_step": {k[3:]: v / args.steps for k, v in st.items() if k.startswith("ms_")},
+        "phase_ms_per_step": {k[3:]: v for k, v in H["prof"].items() if k.startswith("ms_")},
+        "phase_source": "the profiled step (eager launches with HIP events), one per start after the timed steps",
         "starts": {name: summary(r) for name, r in runs.items()},
         "autotune": tune,
         "surrogate_training": None if sur_info is None else
@@ -499,9 +618,11 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "flop_per_pixel_eval": f_full,
+            "flop_per_pixel_eval_counted": flop_full_per_px(K, E, D),
             "avg_launch_ms": rl["ms_full"] / max(1, rl["full_launches"]),
             "launches": rl["full_launches"],
-            "over": "all value+gradient+Hessian launches of the timed steps, plain and surrogate starts",
+            "over": "all value+gradient+Hessian launches of the profiled step of each start (same kernels, "
+                    "launch shapes and work as the timed graph replays)",
             "hbm_algorithmic_GBs": hbm_bytes / full_s / 1e9 if full_s > 0 else None,
             "traffic": traffic,
             "counters": counters,
@@ -512,8 +633,19 @@ def main():
         out["surrogate_gain"] = out["starts"]["surrogate"]["converged_per_s"] / out["starts"]["plain"]["converged_per_s"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(sb, theta0, st["full_px"] / args.steps, st["value_px"] / args.steps,
-                                           conv_tol / args.steps)
+        th_fit = H["theta"]
+        th_np = th_fit.cpu().numpy() if hasattr(th_fit, "cpu") else np.asarray(th_fit)
+
+        def gpu_eval(pick):
+            # the GPU's ELBO, gradient and Hessian at the fitted parameters of the picked sources
+            return ctx.elbo_eval(cb.Batch.from_synth(sb.subset(pick)), th_np[pick])
+
+        out["cpu_baseline"] = cpu_baseline(sb, th_np, gpu_eval, st["full_px"] / args.steps,
+                                           st["value_px"] / args.steps, conv_tol / args.steps)
+    if args.cpu_baseline_fits:
+        log(f"oracle fits of a size-stratified sample of {args.cpu_baseline_fits} sources ...")
+        out["cpu_baseline_fits"] = oracle_fit_baseline(sb, args.cpu_baseline_fits, runs["plain"]["res"]["elbo"],
+                                                       H["res"]["elbo"], log)
     print(json.dumps(out), flush=True)
     if net is not None:
         ctx.set_surrogate(None)
@@ -613,8 +745,10 @@ def lr_measure(ctx, batch, theta, sb, log):
     kernel's HIP-event time, statuses, and how far linear response moves the variances."""
     import numpy as np
     import torch
+    from paper_1611_03404_amd import celeste as cb
     S = sb.n_sources
     u0 = torch.from_numpy(np.asarray(sb.u_cat, dtype=np.float64)).cuda()
+    ctx.set_option(cb.OPT_PROFILE, 1)     # HIP events around the evaluation and the covariance kernel
     ctx.stats(reset=True)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -622,6 +756,7 @@ def lr_measure(ctx, batch, theta, sb, log):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     s2 = ctx.stats()
+    ctx.set_option(cb.OPT_PROFILE, 0)
     c = cov.cpu().numpy()
     th = theta.cpu().numpy() if hasattr(theta, "cpu") else np.asarray(theta)
     ok = st == 0

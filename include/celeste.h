@@ -94,8 +94,10 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    component whose density is below 2^-v on a whole tile is skipped.
                                    160 (always exact: below the smallest FP32 subnormal), 127 (exact
                                    where the device's exp2 flushes results below 2^-126 to zero, which
-                                   the context checks at creation; E_UNSUPPORTED elsewhere), or 0 for
-                                   the context's choice (127 where exact, else 160; the default) */
+                                   the context checks at creation; E_UNSUPPORTED elsewhere), 0 for
+                                   the context's choice (127 where exact, else 160; the default), or
+                                   1 to skip nothing: every component, galaxy group and tile is
+                                   evaluated (the reference the skips are tested against) */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */

@@ -745,11 +745,14 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
       c->vblock = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_EXACT_ZERO:
-      if (value != 0 && value != 127 && value != 160)
-        return fail(CELESTE_E_INVALID, "exact-zero threshold must be 0, 127 or 160");
+      if (value != 0 && value != 1 && value != 127 && value != 160)
+        return fail(CELESTE_E_INVALID, "exact-zero threshold must be 0, 1, 127 or 160");
       if (value == 127 && !c->exp2_flushes)
         return fail(CELESTE_E_UNSUPPORTED, "this device's exp2 does not flush results below 2^-126");
-      c->e_zero = value == 160 || (value == 0 && !c->exp2_flushes) ? -160.f : -127.f;
+      if (value == 1)
+        c->e_zero = -INFINITY;   // every skip test (log2 density >= threshold) passes: nothing is skipped
+      else
+        c->e_zero = value == 160 || (value == 0 && !c->exp2_flushes) ? -160.f : -127.f;
       return CELESTE_OK;
     default:
       return fail(CELESTE_E_INVALID, "unknown option %d", option);

@@ -19,3 +19,16 @@ def test_flop_counts_of_the_roofline():
     # 3 PSF components, 6 + 8 galaxy prototypes: the figures the design notes quote
     assert bench.flop_full_per_px(3, 6, 8) == 4729
     assert bench.flop_value_per_px(3, 6, 8) == 3 * (13 + 8 * 14) + 30
+    # algorithmic figure of the roofline: 170 per galaxy component, 30 per star component, 400 per pixel
+    assert bench.flop_full_per_px_algorithmic(3, 6, 8) == 170 * 42 + 90 + 400
+
+
+def test_stratified_sample_takes_one_source_per_size_stratum():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    npx = np.random.default_rng(0).integers(1000, 700000, size=2000)
+    pick = bench.stratified_sample(npx, 40, 5)
+    assert len(pick) == 40 and len(set(pick)) == 40
+    rank = np.argsort(np.argsort(npx, kind="stable"), kind="stable")
+    assert sorted(rank[pick] // 50) == list(range(40))

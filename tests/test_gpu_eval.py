@@ -9,7 +9,7 @@ import synth
 from synth.generate import perturb_theta
 from oracle import init as oinit
 from oracle import model
-from helpers import assert_derivs_close, assert_elbo_close, deriv_err, oracle_eval
+from helpers import assert_derivs_close, assert_elbo_close, assert_structural_zeros, deriv_err, oracle_eval
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,8 @@ def _check_batch(cb, ctx, sb, thetas, nbr=None, what=""):
             _say(tag, "elbo", el[s], v0, "gerr", deriv_err(g[s], g0), "herr", deriv_err(H[s], H0))
             assert_elbo_close(el[s], v0, what=tag)
             assert_derivs_close(g[s], H[s], g0, H0, what=tag)
+            assert_structural_zeros(H0, what="oracle " + tag)
+            assert_structural_zeros(H[s], what="GPU " + tag)
 
 
 def test_config0_three_points(cb, ctx, cfg0):
@@ -181,6 +183,52 @@ def test_exact_zero_threshold_changes_no_bit(cb, ctx):
     with pytest.raises(cb.CelesteError) as ei:
         ctx.set_option(cb.OPT_EXACT_ZERO, 100)
     assert ei.value.code == cb.E_INVALID
+
+
+def test_skips_match_no_skip_reference(cb, ctx):
+    """Every exact-zero skip of the value+gradient+Hessian kernel (single components, whole
+    galaxy groups under their bound, tiles no component reaches) against the option that skips
+    nothing: every output bit is the same, on a ragged config-1 subset (with and without
+    neighbour arrays, vector and matrix-core J^T W J, tile widths 8 and 16) and on a sample of
+    config-2 sources (multi-epoch, per-epoch PSF and sky)."""
+    c1 = synth.make_config(1, n_sources=8)
+    th1 = perturb_theta(c1.theta_truth, 16)
+    rng = np.random.default_rng(17)
+    nbr = (rng.uniform(0, 30, c1.n_pixels).astype(np.float32), rng.uniform(0, 8, c1.n_pixels).astype(np.float32))
+    c2 = synth.make_config(2, n_sources=120).subset([3, 40, 77, 119])
+    th2 = perturb_theta(c2.theta_truth, 18)
+    cases = [(c1, th1, None, 3, 8), (c1, th1, nbr, 3, 8), (c1, th1, nbr, 7, 16), (c2, th2, None, 3, 8)]
+    try:
+        for k, (sb, th, nb, variant, tw) in enumerate(cases):
+            _say("case: no-skip reference", k, sb.name, "variant", variant, "tile", tw, "nbr", nb is not None)
+            ctx.set_option(cb.OPT_VARIANT, variant)
+            ctx.set_option(cb.OPT_TILE_W, tw)
+            b = cb.Batch.from_synth(sb, nbr=nb)
+            ctx.set_option(cb.OPT_EXACT_ZERO, 1)
+            e0, g0, H0 = ctx.elbo_eval(b, th)
+            ctx.set_option(cb.OPT_EXACT_ZERO, 0)
+            e1, g1, H1 = ctx.elbo_eval(b, th)
+            assert np.array_equal(e0, e1), f"case {k}: ELBO"
+            assert np.array_equal(g0, g1), f"case {k}: gradient"
+            assert np.array_equal(H0, H1), f"case {k}: Hessian"
+            # the reference itself meets the oracle on one source
+            v, g, H = oracle_eval(sb, 0, th[0], nbr=_oracle_nbr(sb, nb))
+            assert_elbo_close(e0[0], v, what=f"no-skip case {k}")
+            assert_derivs_close(g0[0], H0[0], g, H, what=f"no-skip case {k}")
+    finally:
+        ctx.set_option(cb.OPT_EXACT_ZERO, 0)
+        ctx.set_option(cb.OPT_VARIANT, 3)
+        ctx.set_option(cb.OPT_TILE_W, 8)
+
+
+def _oracle_nbr(sb, nb):
+    if nb is None:
+        return None
+    out = {}
+    for i in range(int(sb.src_img_off[0]), int(sb.src_img_off[1])):
+        o, h, w = int(sb.img_pix_off[i]), int(sb.img_h[i]), int(sb.img_w[i])
+        out[i] = (nb[0][o:o + h * w].reshape(h, w), nb[1][o:o + h * w].reshape(h, w))
+    return out
 
 
 def test_value_only_matches_full(cb, ctx):

@@ -228,6 +228,20 @@ def test_gradient_hessian_finite_differences(cfg0):
     assert eg < 1e-7 and eh < 1e-7          # ten times under the tolerance: room for harmless changes
 
 
+def test_structural_zeros_are_exact(cfg0):
+    """Colour entries that share no band and no prior term (A23's structural zeros) are exactly 0
+    in the oracle's Hessian, at three points of config 0 and with a general WCS and neighbours."""
+    from helpers import assert_structural_zeros, structural_zeros
+    assert len(structural_zeros()) == 112
+    imgs = model.source_images(cfg0, 0)
+    for seed in (1, 2, 3):
+        th = perturb_theta(cfg0.theta_truth, seed)[0]
+        _, _, H = model.elbo(th, imgs, cfg0.prior, cfg0.profiles)
+        assert_structural_zeros(H, what=f"seed {seed}")
+        # the entries next to them are not zero: the mask is not trivially satisfied
+        assert H[12, 13] != 0.0 and H[13, 14] != 0.0 and H[11, 12] != 0.0
+
+
 def test_fd_general_wcs_and_neighbours():
     """Non-identity WCS (rotation + scale + offset), per-pixel neighbour mean/variance, two bands."""
     rng = np.random.default_rng(7)
