@@ -418,10 +418,12 @@ def main():
                     help="batched workload: also fit a size-stratified sample of this many sources with the oracle "
                          "(complete fits on the host cores; 200 = 1%% of the workload takes about 15 minutes on 16 "
                          "cores) and check the GPU fits' final ELBO against the oracle-converged one")
-    ap.add_argument("--workload", choices=("batched", "field", "sampled"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "field", "sampled", "lbfgs"), default="batched",
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps; sampled: pixel-subsampled "
-                         "evaluations of the batched workload")
+                         "evaluations of the batched workload; lbfgs: L-BFGS against trust-region Newton from the "
+                         "plain start on the 1,000 isolated sources, their bright variant and the batched workload")
+    ap.add_argument("--lbfgs-max-iter", type=int, default=1000, help="lbfgs workload: L-BFGS iteration cap")
     ap.add_argument("--keep-prob", type=float, default=0.25,
                     help="sampled workload: probability of keeping each 8-row block of an image")
     ap.add_argument("--sweep-probs", default="1,0.5,0.25,0.1",
@@ -460,6 +462,8 @@ def main():
     ctx = cb.Context(0)
     if args.probe:
         return probe(args, ctx, log)
+    if args.workload == "lbfgs":
+        return lbfgs_bench(args, ctx, log)
     if args.workload == "sampled":
         if not all(0.0 < float(x) <= 1.0 for x in args.sweep_probs.split(",") + [args.keep_prob] if x != ""):
             sys.exit("--keep-prob and --sweep-probs must be in (0, 1]")
@@ -780,6 +784,75 @@ def lr_measure(ctx, batch, theta, sb, log):
     }
     log(f"lr covariance: {info}")
     return info
+
+
+def lbfgs_bench(args, ctx, log):
+    """The optimiser ablation of section III-B: L-BFGS (the earlier Celeste optimiser) against
+    trust-region Newton, both from the plain start on the same sources and pixel sums, on the
+    1,000 isolated sources of config 1, their bright variant (100 counts/nMgy) and the 20,000
+    batched-uneven sources.  Per workload and method: wall time of one fit of all sources,
+    iterations (mean, percentiles, max, histogram), gradient/Hessian and value evaluations,
+    statuses, and sources converged at the tolerance rule (status converged and ELBO within
+    1e-5 |L| of the better of the two methods' optima)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1611_03404_amd import celeste as cb
+    out = {"metric": "converged sources/s, L-BFGS vs trust-region Newton (plain start)", "workloads": {}}
+    loads = [("config1", dict(k=1)), ("config1_bright", dict(k=1, bright=True)),
+             ("batched_uneven", dict(k=2, n_sources=args.sources))]
+    for name, kw in loads:
+        sb = synth.make_config(kw.pop("k"), device="cuda", **kw)
+        batch = cb.Batch.from_synth(sb)
+        theta0 = np.zeros((sb.n_sources, 27))
+        theta0[:, 0:2] = sb.u_cat
+        th_start, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+        tune = None if args.no_autotune else ctx.autotune(batch, th_start, cache_path=args.tune_cache)
+        runs = {}
+        for meth in ("trust_region", "lbfgs"):
+            ctx.stats(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if meth == "trust_region":
+                th, res = ctx.batch_fit(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+            else:
+                th, res = ctx.lbfgs_fit(batch, theta0, cb.default_lbfgs_opts(init_mode=cb.INIT_PLAIN,
+                                                                             max_iter=args.lbfgs_max_iter))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            runs[meth] = dict(res=res, wall=wall, stats=ctx.stats())
+            log(f"{name} {meth}: {wall:.2f} s, iterations mean {np.mean(res['iters']):.1f} max {np.max(res['iters'])}")
+        best = np.maximum(runs["trust_region"]["res"]["elbo"], runs["lbfgs"]["res"]["elbo"])
+        w = {"n_sources": sb.n_sources, "n_pixels": sb.n_pixels, "autotune": tune, "methods": {}}
+        for meth, r in runs.items():
+            res, st = r["res"], r["stats"]
+            it = res["iters"]
+            ok = (res["status"] == cb.CONVERGED) & (res["elbo"] >= best - 1e-5 * np.abs(best))
+            edges = [0, 10, 20, 50, 100, 200, 500, 1000, 2000, 10 ** 9]
+            w["methods"][meth] = {
+                "wall_s": r["wall"], "converged_at_tol": int(ok.sum()), "converged_per_s": int(ok.sum()) / r["wall"],
+                "status": {k: int(np.sum(res["status"] == c)) for k, c in
+                           (("converged", cb.CONVERGED), ("max_iter", cb.MAX_ITER), ("tr_collapsed", cb.TR_COLLAPSED),
+                            ("nonfinite", cb.NONFINITE), ("line_search_failed", cb.LINE_SEARCH_FAILED))},
+                "iterations": {"mean": float(np.mean(it)), "p50": float(np.percentile(it, 50)),
+                               "p90": float(np.percentile(it, 90)), "p99": float(np.percentile(it, 99)),
+                               "max": int(np.max(it)), "over_50": int(np.sum(it > 50)),
+                               "hist_edges": edges[:-1], "hist": np.histogram(it, bins=edges)[0].tolist()},
+                "derivative_evals_mean": float(np.mean(res["n_full_evals"])),
+                "pixel_evals": {"value_gradient_hessian": st["full_px"], "value_gradient": st["grad_px"],
+                                "value": st["value_px"]},
+                "loop_steps": st["iterations"],
+                "elbo_shortfall_vs_best": {"median_rel": float(np.median((best - res["elbo"]) / np.abs(best))),
+                                           "max_rel": float(np.max((best - res["elbo"]) / np.abs(best)))},
+            }
+        w["speedup_trust_region_over_lbfgs"] = (w["methods"]["trust_region"]["converged_per_s"]
+                                                / max(1e-12, w["methods"]["lbfgs"]["converged_per_s"]))
+        out["workloads"][name] = w
+        del batch, sb
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def field_bench(args, ctx, net, sur_info, log):

@@ -65,7 +65,8 @@ enum {                          /* per-source fit status */
   CELESTE_CONVERGED = 0,        /* predicted gain below tolerance at a concave point */
   CELESTE_MAX_ITER = 1,         /* iteration cap reached */
   CELESTE_TR_COLLAPSED = 2,     /* trust radius fell below delta_min */
-  CELESTE_NONFINITE = 3         /* the starting point has a non-finite ELBO */
+  CELESTE_NONFINITE = 3,        /* the starting point has a non-finite ELBO */
+  CELESTE_LINE_SEARCH_FAILED = 4 /* L-BFGS: no sufficient decrease within max_backtracks halvings */
 };
 
 enum {                          /* start of a fit */
@@ -117,6 +118,11 @@ typedef struct celeste_stats {
   /* linear-response covariance launches, and their kernel milliseconds (CELESTE_OPT_PROFILE only) */
   int64_t lr_launches;
   double ms_lr;
+  /* value+gradient pixel kernel (celeste_elbo_eval without a Hessian, L-BFGS fits): pixel
+   * evaluations, launches, and milliseconds of the kernel, its reduction and the L-BFGS direction
+   * and line-search kernels (the milliseconds under CELESTE_OPT_PROFILE only) */
+  int64_t grad_px, grad_launches;
+  double ms_grad, ms_reduce_grad, ms_lbfgs;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;
@@ -213,7 +219,8 @@ int celeste_ctx_get_stats(celeste_ctx* ctx, celeste_stats* out, int reset);
 
 /* sizeof of the ABI structs, for bindings to check their layouts: 0 celeste_image,
  * 1 celeste_prior, 2 celeste_profiles, 3 celeste_batch, 4 celeste_fit_opts,
- * 5 celeste_fit_result, 6 celeste_stats, 7 celeste_tune_result; 0 for any other value. */
+ * 5 celeste_fit_result, 6 celeste_stats, 7 celeste_tune_result, 8 celeste_lbfgs_opts; 0 for any
+ * other value. */
 size_t celeste_struct_size(int which);
 
 /* Defaults for celeste_fit_opts (values in the comments above). */
@@ -226,7 +233,8 @@ void celeste_fit_opts_default(celeste_fit_opts* opts);
  *   theta : n_sources x 27 (natural coordinates)
  *   elbo  : n_sources
  *   grad  : n_sources x 27, or NULL
- *   hess  : n_sources x 27 x 27 row-major, or NULL (requires grad)
+ *   hess  : n_sources x 27 x 27 row-major, or NULL (requires grad); with grad and no hess the
+ *           value+gradient pixel kernel runs (no Hessian work), with neither the value kernel
  *   stream: hipStream_t to run on, or NULL for the context's stream.  The call
  *           returns after the results are written (host or device memory).
  * Pixel arrays are checked on the device first: any negative or non-finite pixel or
@@ -324,6 +332,41 @@ int celeste_newton_fit(celeste_ctx* ctx, const celeste_batch* batch, double* the
  * position).  Errors as for celeste_elbo_eval. */
 int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
                       const celeste_fit_opts* opts, celeste_fit_result* results, void* stream);
+
+/* Options of the L-BFGS fit (celeste_lbfgs_fit). */
+typedef struct celeste_lbfgs_opts {
+  int32_t max_iter;             /* accepted steps (gradient evaluations - 1), >= 1 (default 1000) */
+  int32_t memory;               /* curvature pairs kept, 1..32 (default 10) */
+  int32_t max_backtracks;       /* halvings of the step per line search, 1..60 (default 30) */
+  int32_t init_mode;            /* CELESTE_INIT_AS_GIVEN, _PLAIN or _SURROGATE (as celeste_fit_opts) */
+  int32_t poll_every;           /* loop steps between host reads of the active count (default 4) */
+  int32_t max_loops;            /* cap on loop steps (one gradient and/or one trial value pass per
+                                   source each); 0 = 4 * max_iter + 64 (default 0) */
+  double pred_rtol;             /* converged when -g'p/2 <= pred_rtol * max(1, |L|) (1e-8) */
+  double armijo_c1;             /* sufficient-decrease constant, in (0, 1/2) (1e-4) */
+  double u_box;                 /* half-width (px) of the position box around the start (3) */
+} celeste_lbfgs_opts;
+
+/* Defaults for celeste_lbfgs_opts (values in the comments above). */
+void celeste_lbfgs_opts_default(celeste_lbfgs_opts* opts);
+
+/* Limited-memory BFGS fit of all sources of the batch: the optimiser of the earlier Celeste,
+ * which section III-B reports needed thousands of iterations on some sources before trust-
+ * region Newton replaced it; built to compare the two on the same data and hardware.  The
+ * same unconstrained coordinates, starts and pixel sums as celeste_batch_fit, without the
+ * Hessian: every loop step evaluates the value and gradient (value+gradient pixel kernel) of
+ * the sources that accepted a step, forms their L-BFGS directions by the two-loop recursion
+ * (Nocedal & Wright, Algorithm 7.4; initial scaling s'y / y'y, unit-length first step), and
+ * evaluates one trial point per source in a line search (backtracking by halving from step 1
+ * until f(psi + a p) <= f(psi) + c1 a g'p for f = -ELBO; pairs with s'y <= 1e-10 |s||y| are not
+ * stored; a non-descent direction restarts from the scaled negative gradient).  Converged when
+ * the quasi-Newton model's predicted gain -g'p/2 is at most pred_rtol max(1, |L|).
+ * theta_inout and results as celeste_batch_fit; results[i].iters = accepted steps,
+ * n_full_evals = value+gradient evaluations, delta = the last accepted step length, pred_gain =
+ * the last predicted gain.  State per source on the device: 2 memory x 27 + 40 FP64 values.
+ * Errors as for celeste_batch_fit; E_INVALID for options out of range. */
+int celeste_lbfgs_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
+                      const celeste_lbfgs_opts* opts, celeste_fit_result* results, void* stream);
 
 /* ----------------------------------------------------------------------------------------
  * Surrogate initialiser network.  A convolutional network maps a source's 5-band 32x32

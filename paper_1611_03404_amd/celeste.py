@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libceleste.so")
 NP = 27
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
-CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE = 0, 1, 2, 3
+CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE, LINE_SEARCH_FAILED = 0, 1, 2, 3, 4
 INIT_AS_GIVEN, INIT_PLAIN, INIT_SURROGATE = 0, 1, 2
 FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
@@ -53,6 +53,12 @@ class FitOpts(ctypes.Structure):
                 ("poll_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class LbfgsOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("memory", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
+                ("init_mode", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("max_loops", ctypes.c_int32),
+                ("pred_rtol", ctypes.c_double), ("armijo_c1", ctypes.c_double), ("u_box", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("full_px", ctypes.c_int64), ("value_px", ctypes.c_int64), ("full_launches", ctypes.c_int64),
                 ("value_launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("ms_setup", ctypes.c_double),
@@ -60,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("ms_value", ctypes.c_double), ("ms_reduce_value", ctypes.c_double), ("ms_accept", ctypes.c_double),
                 ("ms_host_pack", ctypes.c_double), ("ms_prepare", ctypes.c_double), ("ms_start", ctypes.c_double),
                 ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double), ("lr_launches", ctypes.c_int64),
-                ("ms_lr", ctypes.c_double)]
+                ("ms_lr", ctypes.c_double), ("grad_px", ctypes.c_int64), ("grad_launches", ctypes.c_int64),
+                ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -105,6 +112,9 @@ def load():
     lib.celeste_struct_size.restype = ctypes.c_size_t
     lib.celeste_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
     lib.celeste_fit_opts_default.restype = None
+    lib.celeste_lbfgs_opts_default.argtypes = [ctypes.POINTER(LbfgsOpts)]
+    lib.celeste_lbfgs_opts_default.restype = None
+    lib.celeste_lbfgs_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(LbfgsOpts), vp, vp]
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_elbo_eval_noalloc.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_lr_covariance_from_hessian.argtypes = [vp, i64, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp, vp,
@@ -143,9 +153,10 @@ def load():
                  "celeste_render_fields", "celeste_neighbour_arrays", "celeste_start", "celeste_autotune",
                  "celeste_colour_sources", "celeste_update_fields", "celeste_field_elbo"):
         getattr(lib, name).restype = ctypes.c_int
-    sizes = [lib.celeste_struct_size(k) for k in range(8)]
+    sizes = [lib.celeste_struct_size(k) for k in range(9)]
     expect = [IMAGE_DT.itemsize, PRIOR_DT.itemsize, PROF_DT.itemsize, ctypes.sizeof(CBatch),
-              ctypes.sizeof(FitOpts), RESULT_DT.itemsize, ctypes.sizeof(Stats), ctypes.sizeof(TuneResult)]
+              ctypes.sizeof(FitOpts), RESULT_DT.itemsize, ctypes.sizeof(Stats), ctypes.sizeof(TuneResult),
+              ctypes.sizeof(LbfgsOpts)]
     if sizes != expect:
         raise RuntimeError(f"ABI struct sizes differ: library {sizes}, binding {expect}")
     _lib = lib
@@ -163,6 +174,14 @@ def colour_sources(batch: Batch):
     n = ctypes.c_int32()
     _check(load().celeste_colour_sources(ctypes.byref(batch.c), col.ctypes.data, ctypes.byref(n)))
     return col, n.value
+
+
+def default_lbfgs_opts(**kw):
+    o = LbfgsOpts()
+    load().celeste_lbfgs_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
 
 
 def default_opts(**kw):
@@ -524,6 +543,19 @@ class Context:
         imf = np.ascontiguousarray(img_field, dtype=np.int32)
         f = CFields(int(n_fields), int(height), int(width), 0, imf.ctypes.data, _ptr(arrays[0]), _ptr(arrays[1]))
         return f, imf
+
+    def lbfgs_fit(self, batch: Batch, theta0, opts=None):
+        """L-BFGS fit of every source (celeste_lbfgs_fit); returns (theta, results) like batch_fit
+        (iters = accepted steps, n_full_evals = value+gradient evaluations)."""
+        S = batch.n_sources
+        th = batch.as_input(theta0, copy=True)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta0 must have shape ({S}, {NP})")
+        res = np.zeros(S, dtype=RESULT_DT)
+        o = opts if opts is not None else default_lbfgs_opts()
+        _check(load().celeste_lbfgs_fit(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o),
+                                        res.ctypes.data, self._stream(batch)))
+        return th, res
 
     def batch_fit(self, batch: Batch, theta0, opts=None):
         S = batch.n_sources

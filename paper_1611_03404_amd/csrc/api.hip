@@ -88,6 +88,7 @@ struct celeste_ctx {
   DevBuf kept;                                     // first rows of the kept blocks of a pixel subsample
   DevBuf lr_in, lr_cov, lr_status, lr_eval;        // linear-response covariance staging
   DevBuf lfact;                                    // log n! table of the pixel constants
+  DevBuf lb_buf;                                   // L-BFGS state beyond the fit state
   bool lfact_ready = false;
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
@@ -358,7 +359,6 @@ int validate_and_pack(celeste_ctx* ctx, const celeste_batch* b, Packed* P, HostP
     P->imgs = as<ImgDev>(ctx->h_imgs);
     P->srcs = as<SrcDev>(ctx->h_srcs);
   }
-
   const int chunk = std::max(64, ctx->chunk_px);
   // work-item offsets per image (items in image order, so per source contiguous)
   std::vector<int64_t> first_item(n_img + 1, 0);
@@ -577,6 +577,7 @@ hipStream_t pick(celeste_ctx* ctx, void* stream) { return stream ? (hipStream_t)
 
 unsigned long long* ctr_full(celeste_ctx* c) { return as<unsigned long long>(c->ctr); }
 unsigned long long* ctr_value(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 1; }
+unsigned long long* ctr_grad(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 2; }
 
 // HIP events between the kernel phases of one iteration (profile mode).
 struct PhaseTimer {
@@ -648,8 +649,8 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
-  if (ensure(c->ctr, 2 * sizeof(unsigned long long)) != CELESTE_OK ||
-      hipMemset(c->ctr.p, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+  if (ensure(c->ctr, 3 * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipStreamDestroy(c->stream);
     if (c->ctr.p) (void)hipFree(c->ctr.p);
     delete c;
@@ -681,10 +682,11 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
 int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
   HIPCHK(hipSetDevice(c->device));
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[3] = {0, 0, 0};
   HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
   c->stats.full_px = (int64_t)h[0];
   c->stats.value_px = (int64_t)h[1];
+  c->stats.grad_px = (int64_t)h[2];
   *out = c->stats;
   if (reset) {
     HIPCHK(hipMemset(c->ctr.p, 0, sizeof(h)));
@@ -701,7 +703,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
                     &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
                     &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval,
-                    &c->lfact};
+                    &c->lfact, &c->lb_buf};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
@@ -769,6 +771,7 @@ size_t celeste_struct_size(int which) {
     case 5: return sizeof(celeste_fit_result);
     case 6: return sizeof(celeste_stats);
     case 7: return sizeof(celeste_tune_result);
+    case 8: return sizeof(celeste_lbfgs_opts);
     default: return 0;
   }
 }
@@ -899,7 +902,7 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
   }
   EvalBufs B;
   if (noalloc) {
-    CHK(scratch_bufs(ctx, &P, grad ? NACC : 1, &B));
+    CHK(scratch_bufs(ctx, &P, grad ? (hess ? NACC : NGRAD) : 1, &B));
     const int rc = prepare_in(ctx, b, &P, &B, st, true);
     if (B.lfact_ready) scratch_lfact_filled(ctx->device);
     CHK(rc);
@@ -934,13 +937,20 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
   T.mark(0, st);
   HIPCHK(launch_setup(B.imgs, P.n_img, th_dev, nullptr, P.prof, B.tables, P.tstride, st));
   T.mark(1, st);
-  if (grad) {
+  if (grad && hess) {
     HIPCHK(launch_eval_full(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
                             B.partials, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
                               d_grad, d_hess, ctr_full(ctx), st, px_weight));
     ctx->stats.full_launches += 1;
+  } else if (grad) {
+    HIPCHK(launch_eval_grad(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
+                            B.partials, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
+    T.mark(2, st);
+    HIPCHK(launch_reduce_grad(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
+                              d_grad, ctr_grad(ctx), st, px_weight));
+    ctx->stats.grad_launches += 1;
   } else {
     HIPCHK(launch_eval_value(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
                              B.partials, ctx->vblock, ctx->variant, ctx->vtile_log2, st, kept));
@@ -958,8 +968,8 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
   HIPCHK(hipStreamSynchronize(st));
   if (T.on) {
     ctx->stats.ms_setup += T.span(0, 1);
-    (grad ? ctx->stats.ms_full : ctx->stats.ms_value) += T.span(1, 2);
-    (grad ? ctx->stats.ms_reduce_full : ctx->stats.ms_reduce_value) += T.span(2, 3);
+    (hess ? ctx->stats.ms_full : grad ? ctx->stats.ms_grad : ctx->stats.ms_value) += T.span(1, 2);
+    (hess ? ctx->stats.ms_reduce_full : grad ? ctx->stats.ms_reduce_grad : ctx->stats.ms_reduce_value) += T.span(2, 3);
   }
   return CELESTE_OK;
 }
@@ -1156,43 +1166,44 @@ void accumulate_phases(celeste_ctx* ctx, PhaseTimer& T) {
   s.ms_accept += T.span(7, 8);
 }
 
-int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
-            celeste_fit_result* res, hipStream_t st, bool batched, double* start_elbo = nullptr,
-            bool start_only = false) {
-  // host stage clock (profile mode): stage k ends at mark(k); the stream is drained first
-  const bool prof = ctx->profile != 0;
-  auto t_last = std::chrono::steady_clock::now();
-  auto stage = [&](double& acc, hipStream_t s) {
-    if (!prof) return;
+// Host wall clock of the fits' stages (profile mode only): stage k ends at a call; the stream
+// is drained first.
+struct StageClock {
+  bool on;
+  std::chrono::steady_clock::time_point t_last = std::chrono::steady_clock::now();
+  explicit StageClock(bool on_) : on(on_) {}
+  void operator()(double& acc, hipStream_t s) {
+    if (!on) return;
     (void)hipStreamSynchronize(s);
     const auto now = std::chrono::steady_clock::now();
     acc += std::chrono::duration<double, std::milli>(now - t_last).count();
     t_last = now;
-  };
-  Packed P;
-  CHK(validate_and_pack(ctx, b, &P));
-  if (start_only) {
-    if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
-    celeste_fit_opts o2 = *o;
-    o2.max_iter = 1;
-    CHK(check_opts(&o2));
-  } else {
-    CHK(check_opts(o));
   }
-  if (!theta_inout || (!res && !start_only)) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+};
+
+// The common start of the trust-region and L-BFGS fits: validation, packing, metadata upload
+// and pixel check, the fit state (F), and the start (plain, surrogate with fallback, or as
+// given) with its ELBO in F.f; a source whose start is not finite is not fitted.  th receives
+// the host copy of theta_inout.
+int fit_begin(celeste_ctx* ctx, const celeste_batch* b, const double* theta_inout, int init_mode,
+              const FitParams& fp, hipStream_t st, StageClock& stage, Packed* Pp, FitDev* Fp,
+              std::vector<double>* thp) {
+  Packed& P = *Pp;
+  FitDev& F = *Fp;
+  std::vector<double>& th = *thp;
   HIPCHK(hipSetDevice(ctx->device));
   const int S = P.n_src;
-  std::vector<double> th(NP * (size_t)S);
+  th.resize(NP * (size_t)S);
   if (b->mem_kind == CELESTE_MEM_HOST)
     std::memcpy(th.data(), theta_inout, sizeof(double) * th.size());
   else {
     HIPCHK(hipMemcpyAsync(th.data(), theta_inout, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
-  if (o->init_mode == CELESTE_INIT_SURROGATE && !ctx->net)
+  if (init_mode == CELESTE_INIT_SURROGATE && !ctx->net)
     return fail(CELESTE_E_INVALID, "CELESTE_INIT_SURROGATE needs a network (celeste_ctx_set_surrogate)");
   for (int s = 0; s < S; ++s) {
-    if (o->init_mode != CELESTE_INIT_AS_GIVEN) {
+    if (init_mode != CELESTE_INIT_AS_GIVEN) {
       if (!finite(th[(size_t)s * NP]) || !finite(th[(size_t)s * NP + 1]))
         return fail(CELESTE_E_INVALID, "theta[%d]: position must be finite", s);
     } else {
@@ -1202,26 +1213,16 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   stage(ctx->stats.ms_host_pack, st);
   CHK(prepare(ctx, b, &P, st));
   stage(ctx->stats.ms_prepare, st);
-  FitDev F;
   CHK(alloc_fit(ctx, S, &F));
-  FitParams fp;
-  fp.max_iter = o->max_iter;
-  fp.pred_rtol = o->pred_rtol;
-  fp.curv_tol = o->curv_tol;
-  fp.delta0 = o->delta0;
-  fp.delta_max = o->delta_max;
-  fp.delta_min = o->delta_min;
-  fp.eta = o->eta;
-  fp.u_box = o->u_box;
   HIPCHK(hipMemcpyAsync(F.theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st));
   HIPCHK(launch_zero_int(F.flags, S, st));
   const ImgDev* imgs0 = as<ImgDev>(ctx->imgs);
-  if (o->init_mode == CELESTE_INIT_SURROGATE) {
+  if (init_mode == CELESTE_INIT_SURROGATE) {
     // network start (from the catalog positions in F.theta) into theta_trial, plain start into theta,
     // both evaluated; the better one is kept
     CHK(ensure(ctx->sur, sizeof(float) * NP * (size_t)S));
     CHK(surrogate_predict(ctx->net, as<SrcDev>(ctx->srcs), S, imgs0, F.theta, as<float>(ctx->sur), st));
-    HIPCHK(launch_psi_to_theta(as<float>(ctx->sur), F.theta, F.theta_trial, S, o->u_box, st));
+    HIPCHK(launch_psi_to_theta(as<float>(ctx->sur), F.theta, F.theta_trial, S, fp.u_box, st));
     HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
     for (int k = 0; k < 2; ++k) {
       double* tk = k == 0 ? F.theta : F.theta_trial;
@@ -1235,11 +1236,11 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
       ctx->stats.value_launches += 1;
     }
     HIPCHK(launch_choose_start(F, S, st));
-  } else if (o->init_mode == CELESTE_INIT_PLAIN) {
+  } else if (init_mode == CELESTE_INIT_PLAIN) {
     HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
   }
   HIPCHK(launch_fit_init(F, S, fp, st));
-  if (o->init_mode != CELESTE_INIT_SURROGATE) {
+  if (init_mode != CELESTE_INIT_SURROGATE) {
     // the start's ELBO (the surrogate path has it from choosing between the two starts: both lie
     // inside the boxes, where the transform round trip of the fit set-up moves a parameter by
     // rounding, or by at most 1e-9 of its box where a start sits on the box edge)
@@ -1253,68 +1254,12 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     ctx->stats.value_launches += 1;
   }
   HIPCHK(launch_fit_start(F, S, st));
-  if (start_only) {
-    if (b->mem_kind == CELESTE_MEM_HOST) {
-      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
-      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
-    } else {
-      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToDevice, st));
-      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    return CELESTE_OK;
-  }
-  stage(ctx->stats.ms_start, st);
-  PhaseTimer T;
-  CHK(T.init(ctx->profile != 0));
+  return CELESTE_OK;
+}
 
-  const int max_loops = o->max_iter + 1;
-  const int poll = (batched && !T.on) ? std::max(1, o->poll_every) : 1;
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  if (batched && ctx->use_graph && !T.on) {
-    PhaseTimer none;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iteration(ctx, P, F, fp, st, &none);
-    hipError_t e2 = hipStreamEndCapture(st, &graph);
-    if (rc != CELESTE_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
-    HIPCHK(e2);
-    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  }
-  int rc = CELESTE_OK;
-  int n_active = 1;
-  for (int it = 0; it < max_loops && n_active > 0; ++it) {
-    if (exec) {
-      hipError_t e = hipGraphLaunch(exec, st);
-      if (e != hipSuccess) {
-        rc = fail(CELESTE_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
-        break;
-      }
-    } else {
-      rc = enqueue_iteration(ctx, P, F, fp, st, &T);
-      if (rc != CELESTE_OK) break;
-    }
-    ctx->stats.iterations += 1;
-    ctx->stats.full_launches += 1;
-    ctx->stats.value_launches += 1;
-    if ((it + 1) % poll == 0 || it + 1 == max_loops) {
-      hipError_t e = hipMemcpyAsync(&n_active, F.n_active, sizeof(int), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) {
-        rc = fail(CELESTE_E_DEVICE, "active-count readback: %s", hipGetErrorString(e));
-        break;
-      }
-      accumulate_phases(ctx, T);
-    }
-  }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  if (rc != CELESTE_OK) return rc;
-  stage(ctx->stats.ms_loop, st);
-  // results
+// Per-source results of a fit from its device state; theta_inout receives the parameters.
+int fit_results(celeste_ctx* ctx, const celeste_batch* b, const FitDev& F, int S, std::vector<double>& th,
+                double* theta_inout, celeste_fit_result* res, hipStream_t st, StageClock& stage) {
   std::vector<double> fv(S), pred(S), delta(S);
   std::vector<int> iter(S), status(S), nfull(S), flags(S);
   HIPCHK(hipMemcpyAsync(th.data(), F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
@@ -1345,6 +1290,230 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   return CELESTE_OK;
 }
 
+// Replays (graph) or enqueues (eager) `iteration` until no source is active or max_loops loop
+// steps; the host reads the device's active count every `poll` steps.
+// count(stats) records the launches of one executed step (replayed or enqueued).
+template <class Iter, class Count>
+int run_loop(celeste_ctx* ctx, hipStream_t st, int max_loops, int poll, bool use_graph, const int* n_active_dev,
+             PhaseTimer& T, Iter iteration, Count count, void (*account)(celeste_ctx*, PhaseTimer&)) {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    PhaseTimer none;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = iteration(&none);
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (rc != CELESTE_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIPCHK(e2);
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  int rc = CELESTE_OK;
+  int n_active = 1;
+  for (int it = 0; it < max_loops && n_active > 0; ++it) {
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) {
+        rc = fail(CELESTE_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+        break;
+      }
+    } else {
+      rc = iteration(&T);
+      if (rc != CELESTE_OK) break;
+    }
+    ctx->stats.iterations += 1;
+    count(ctx->stats);
+    if ((it + 1) % poll == 0 || it + 1 == max_loops) {
+      hipError_t e = hipMemcpyAsync(&n_active, n_active_dev, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        rc = fail(CELESTE_E_DEVICE, "active-count readback: %s", hipGetErrorString(e));
+        break;
+      }
+      account(ctx, T);
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  return rc;
+}
+
+int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
+            celeste_fit_result* res, hipStream_t st, bool batched, double* start_elbo = nullptr,
+            bool start_only = false) {
+  StageClock stage(ctx->profile != 0);
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  if (start_only) {
+    if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
+    celeste_fit_opts o2 = *o;
+    o2.max_iter = 1;
+    CHK(check_opts(&o2));
+  } else {
+    CHK(check_opts(o));
+  }
+  if (!theta_inout || (!res && !start_only)) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+  const int S = P.n_src;
+  FitParams fp;
+  fp.max_iter = o->max_iter;
+  fp.pred_rtol = o->pred_rtol;
+  fp.curv_tol = o->curv_tol;
+  fp.delta0 = o->delta0;
+  fp.delta_max = o->delta_max;
+  fp.delta_min = o->delta_min;
+  fp.eta = o->eta;
+  fp.u_box = o->u_box;
+  FitDev F;
+  std::vector<double> th;
+  CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
+  if (start_only) {
+    if (b->mem_kind == CELESTE_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    } else {
+      HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToDevice, st));
+      if (start_elbo) HIPCHK(hipMemcpyAsync(start_elbo, F.f, sizeof(double) * S, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return CELESTE_OK;
+  }
+  stage(ctx->stats.ms_start, st);
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
+  const int poll = (batched && !T.on) ? std::max(1, o->poll_every) : 1;
+  const bool graph = batched && ctx->use_graph && !T.on;
+  CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
+               [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t); },
+               [](celeste_stats& c) {
+                 c.full_launches += 1;
+                 c.value_launches += 1;
+               },
+               accumulate_phases));
+  stage(ctx->stats.ms_loop, st);
+  return fit_results(ctx, b, F, S, th, theta_inout, res, st, stage);
+}
+
+int check_lbfgs_opts(const celeste_lbfgs_opts* o) {
+  if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
+  if (o->max_iter < 1 || o->max_iter > 1000000) return fail(CELESTE_E_INVALID, "max_iter must be in 1..1e6");
+  if (o->memory < 1 || o->memory > LBFGS_MAX_MEMORY) return fail(CELESTE_E_INVALID, "memory must be in 1..32");
+  if (o->max_backtracks < 1 || o->max_backtracks > 60) return fail(CELESTE_E_INVALID, "max_backtracks must be in 1..60");
+  if (o->init_mode != CELESTE_INIT_AS_GIVEN && o->init_mode != CELESTE_INIT_PLAIN &&
+      o->init_mode != CELESTE_INIT_SURROGATE)
+    return fail(CELESTE_E_INVALID, "unknown init_mode %d", o->init_mode);
+  if (o->max_loops < 0) return fail(CELESTE_E_INVALID, "max_loops must be >= 0");
+  if (!(o->pred_rtol > 0.0) || !(o->armijo_c1 > 0.0 && o->armijo_c1 < 0.5) || !(o->u_box > 0.0))
+    return fail(CELESTE_E_INVALID, "pred_rtol and u_box must be > 0 and armijo_c1 in (0, 1/2)");
+  return CELESTE_OK;
+}
+
+void accumulate_lbfgs_phases(celeste_ctx* ctx, PhaseTimer& T) {
+  if (!T.on) return;
+  celeste_stats& s = ctx->stats;
+  s.ms_setup += T.span(0, 1) + T.span(4, 5);
+  s.ms_grad += T.span(1, 2);
+  s.ms_reduce_grad += T.span(2, 3);
+  s.ms_lbfgs += T.span(3, 4) + T.span(7, 8);
+  s.ms_value += T.span(5, 6);
+  s.ms_reduce_value += T.span(6, 7);
+}
+
+int run_lbfgs(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_lbfgs_opts* o,
+              celeste_fit_result* res, hipStream_t st) {
+  StageClock stage(ctx->profile != 0);
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_lbfgs_opts(o));
+  if (!theta_inout || !res) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+  const int S = P.n_src;
+  FitParams fp{};
+  fp.max_iter = o->max_iter;
+  fp.delta0 = 1.0;
+  fp.u_box = o->u_box;
+  FitDev F;
+  std::vector<double> th;
+  CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
+  // L-BFGS state: pairs, rho, gradients and scalars, then the integer counters
+  const int m = o->memory;
+  const size_t nd = (size_t)S * (2 * (size_t)m * NP + m + NP + 1);
+  const size_t ni = (size_t)S * 5;
+  CHK(ensure(ctx->lb_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
+  LbfgsDev X;
+  {
+    double* d = as<double>(ctx->lb_buf);
+    auto take = [&d](size_t n) {
+      double* r = d;
+      d += n;
+      return r;
+    };
+    X.S = take((size_t)S * m * NP);
+    X.Y = take((size_t)S * m * NP);
+    X.rho = take((size_t)S * m);
+    X.gpsi = take((size_t)S * NP);
+    X.gp = take(S);
+    int* ip = reinterpret_cast<int*>(d);
+    X.n_pairs = ip;
+    X.head = ip + S;
+    X.ls = ip + 2 * S;
+    X.n_val = ip + 3 * S;
+    X.in_ls = ip + 4 * S;
+  }
+  LbfgsParams lp;
+  lp.max_iter = o->max_iter;
+  lp.memory = m;
+  lp.max_backtracks = o->max_backtracks;
+  lp.pred_rtol = o->pred_rtol;
+  lp.c1 = o->armijo_c1;
+  lp.u_box = o->u_box;
+  HIPCHK(launch_lbfgs_init(X, S, st));
+  stage(ctx->stats.ms_start, st);
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  const WorkItem* items = as<WorkItem>(ctx->items);
+  const SrcDev* srcs = as<SrcDev>(ctx->srcs);
+  float* tables = as<float>(ctx->tables);
+  double* parts = as<double>(ctx->partials);
+  const double* ic = as<double>(ctx->img_const);
+  auto iteration = [&](PhaseTimer* t) -> int {
+    t->mark(0, st);
+    HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
+    t->mark(1, st);
+    HIPCHK(launch_eval_grad(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full,
+                            parts, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
+    t->mark(2, st);
+    HIPCHK(launch_reduce_grad(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g,
+                              ctr_grad(ctx), st));
+    t->mark(3, st);
+    HIPCHK(launch_zero_int(F.n_active, 1, st));
+    HIPCHK(launch_lbfgs_dir(F, X, P.n_src, lp, st));
+    t->mark(4, st);
+    HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, X.in_ls, P.prof, tables, P.tstride, st));
+    t->mark(5, st);
+    HIPCHK(launch_eval_value(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, X.in_ls, parts,
+                             ctx->vblock, ctx->variant, ctx->vtile_log2, st));
+    t->mark(6, st);
+    HIPCHK(launch_reduce_value(srcs, P.n_src, imgs, parts, ic, F.theta_trial, P.prior, X.in_ls, F.f_trial,
+                               ctr_value(ctx), st));
+    t->mark(7, st);
+    HIPCHK(launch_lbfgs_accept(F, X, P.n_src, lp, st));
+    t->mark(8, st);
+    return CELESTE_OK;
+  };
+  const int max_loops = o->max_loops > 0 ? o->max_loops : 4 * o->max_iter + 64;
+  const int poll = T.on ? 1 : std::max(1, o->poll_every);
+  CHK(run_loop(ctx, st, max_loops, poll, ctx->use_graph && !T.on, F.n_active, T, iteration,
+               [](celeste_stats& c) {
+                 c.grad_launches += 1;
+                 c.value_launches += 1;
+               },
+               accumulate_lbfgs_phases));
+  stage(ctx->stats.ms_loop, st);
+  return fit_results(ctx, b, F, S, th, theta_inout, res, st, stage);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1361,6 +1530,26 @@ int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_in
                       celeste_fit_result* results, void* stream) {
   if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
   return run_fit(ctx, b, theta_inout, opts, results, pick(ctx, stream), true);
+}
+
+void celeste_lbfgs_opts_default(celeste_lbfgs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iter = 1000;
+  o->memory = 10;
+  o->max_backtracks = 30;
+  o->init_mode = CELESTE_INIT_PLAIN;
+  o->poll_every = 4;
+  o->max_loops = 0;
+  o->pred_rtol = 1e-8;
+  o->armijo_c1 = 1e-4;
+  o->u_box = 3.0;
+}
+
+int celeste_lbfgs_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_lbfgs_opts* opts,
+                      celeste_fit_result* results, void* stream) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  return run_lbfgs(ctx, b, theta_inout, opts, results, pick(ctx, stream));
 }
 
 }  // extern "C"

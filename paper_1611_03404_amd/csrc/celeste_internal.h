@@ -109,6 +109,13 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
                             int block, int variant, int tw_log2, float e_zero, hipStream_t st,
                             const int* kept = nullptr);
+// Value and z-gradient only: one partial of NGRAD = 1 + NZ doubles per work item (value, 11
+// gradient entries); arguments as launch_eval_full (variant: bit 1 only).
+constexpr int NGRAD = 1 + NZ;
+hipError_t launch_eval_grad(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
+                            int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
+                            int block, int variant, int tw_log2, float e_zero, hipStream_t st,
+                            const int* kept = nullptr);
 // out[i] = the pixel kernels' exp2(in[i]) on the device (i < n).
 hipError_t launch_exp2_probe(const float* in, float* out, int n, hipStream_t st);
 hipError_t launch_eval_value(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
@@ -121,6 +128,11 @@ hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs,
                               const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                               double* elbo, double* grad, double* hess, unsigned long long* px_ctr,
                               hipStream_t st, double px_weight = 1.0);
+// Value and natural gradient per source from gradient partials (NGRAD per work item).
+hipError_t launch_reduce_grad(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
+                              const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
+                              double* elbo, double* grad, unsigned long long* px_ctr, hipStream_t st,
+                              double px_weight = 1.0);
 hipError_t launch_reduce_value(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
                                const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
                                double* elbo, unsigned long long* px_ctr, hipStream_t st,
@@ -174,6 +186,36 @@ hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_psi_to_theta(const float* psi, const double* theta_cat, double* theta_out, int n_src,
                                double u_box, hipStream_t s);
 hipError_t launch_choose_start(FitDev st, int n_src, hipStream_t s);
+
+// ---------------------------------------------------------------- L-BFGS state
+// Beyond the fit state, whose fields keep their meaning with need_full = "needs a gradient",
+// delta = the current step length and n_full = gradient evaluations.
+constexpr int LBFGS_MAX_MEMORY = 32;
+struct LbfgsDev {
+  double* gpsi;     // S x 27 psi-gradient of -L at the current point
+  double* S;        // S x memory x 27 curvature pairs: steps
+  double* Y;        // S x memory x 27 curvature pairs: gradient changes
+  double* rho;      // S x memory: 1 / s'y
+  double* gp;       // S: g'p of the current direction
+  int* n_pairs;     // S: stored pairs
+  int* head;        // S: ring slot of the next pair
+  int* ls;          // S: halvings in the current line search
+  int* n_val;       // S: trial value evaluations
+  int* in_ls;       // S: 1 while a trial point awaits its value
+};
+
+struct LbfgsParams {
+  int max_iter, memory, max_backtracks;
+  double pred_rtol, c1, u_box;
+};
+
+hipError_t launch_lbfgs_init(LbfgsDev X, int n_src, hipStream_t s);
+// One wavefront per source with a new gradient: curvature pair, two-loop direction, stopping
+// rule, first trial point.  n_active must be zeroed before launch_lbfgs_accept counts into it.
+hipError_t launch_lbfgs_dir(FitDev F, LbfgsDev X, int n_src, LbfgsParams lp, hipStream_t s);
+// One thread per source: sufficient-decrease test of the trial point, step or halving; counts the
+// sources still being fitted into F.n_active.
+hipError_t launch_lbfgs_accept(FitDev F, LbfgsDev X, int n_src, LbfgsParams lp, hipStream_t s);
 
 // context accessors used by the network code, and the shared error slot
 int ctx_device(const celeste_ctx* c);

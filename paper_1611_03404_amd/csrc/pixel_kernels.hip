@@ -648,6 +648,173 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
   }
 }
 
+// First-order Hermite moments of one galaxy profile type: the value, its position gradient
+// and the nu-weighted second moments that give the shape gradient (dN/dC = 1/2 d2N/dmu2).
+struct GalAcc1 {
+  float a0, a1x, a1y;
+  float b2xx, b2xy, b2yy;
+};
+
+// One galaxy component, first order only; false (on every lane) when it is exactly 0 on the tile.
+__device__ __forceinline__ bool gal_comp1(const float* __restrict__ r, float dx, float dy, float dxx, float dxy,
+                                          float dyy, float e_zero, GalAcc1& A) {
+  const float e = fmaf(r[R_QXX], dxx, fmaf(r[R_QXY], dxy, fmaf(r[R_QYY], dyy, r[R_C0])));
+  if (!wave_any(e >= e_zero)) return false;
+  const float N = ex2(e);
+  const float Pxx = r[R_PXX], Pxy = r[R_PXY], Pyy = r[R_PYY];
+  const float bx = fmaf(Pxx, dx, Pxy * dy);
+  const float by = fmaf(Pxy, dx, Pyy * dy);
+  const float Nn = N * r[R_NU];
+  A.a0 += N;
+  A.a1x = fmaf(N, bx, A.a1x);
+  A.a1y = fmaf(N, by, A.a1y);
+  A.b2xx = fmaf(Nn, fmaf(bx, bx, -Pxx), A.b2xx);
+  A.b2xy = fmaf(Nn, fmaf(bx, by, -Pxy), A.b2xy);
+  A.b2yy = fmaf(Nn, fmaf(by, by, -Pyy), A.b2yy);
+  return true;
+}
+
+constexpr int NG = NGRAD;   // entries of a gradient partial: value and the 11 z-gradient entries
+
+// Value and z-gradient of the pixel sum (no Hessian): the same per-pixel model as k_eval_full
+// with first-order moments only (6 sums per galaxy component instead of 18) and no second-
+// order terms; value and gradient accumulated per lane in FP64.  One partial of NG doubles per
+// work item.  Exactly-zero components, galaxy groups and tiles are skipped as in k_eval_full.
+template <int BLOCK, int NE, int ND>
+__global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict__ items,
+                                                     const ImgDev* __restrict__ imgs,
+                                                     const float* __restrict__ tables, int tstride, int n_exp_rt,
+                                                     int n_dev_rt, const int* __restrict__ src_flag, int tw_log2,
+                                                     float e_zero, const int* __restrict__ kept,
+                                                     double* __restrict__ partials) {
+  __shared__ double red[BLOCK / 64][NG];
+  const WorkItem wi = items[blockIdx.x];
+  if (src_flag && !src_flag[wi.src]) return;
+  const int ne = NE > 0 ? NE : n_exp_rt;
+  const int ncomp = NE > 0 ? NE + ND : n_exp_rt + n_dev_rt;
+  const ImgDev& im = imgs[wi.img];
+  const float* __restrict__ T = tables + (size_t)wi.img * tstride;
+  const int w = im.w, pitch = im.pitch, npitch = im.nbr_pitch, npsf = im.n_psf;
+  const float* __restrict__ pix = im.pix;
+  const float* __restrict__ nbrE = im.nbr_mean;
+  const float* __restrict__ nbrV = im.nbr_var;
+  const float psx = T[PSX], psy = T[PSY], io = T[CALIB], sky = T[SKY];
+  const float io2 = io * io;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const TileMap tm(wi, w, im.h, tw_log2, kept);
+  double acc[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) acc[j] = 0.0;
+  for (int t = wv; t < tm.n_tiles; t += BLOCK / 64) {
+    int row, col;
+    bool live;
+    tm.pixel(t, lane, row, col, live);   // (row, col) is inside the image on every lane
+    const float x = live ? pix[(size_t)row * pitch + col] : 0.f;
+    const float ebg = sky + (nbrE && live ? nbrE[(size_t)row * npitch + col] : 0.f);
+    const float vbg = nbrV && live ? nbrV[(size_t)row * npitch + col] : 0.f;
+    const float dx0 = live ? (float)col - psx : FAR, dy0 = live ? (float)row - psy : FAR;
+
+    bool hit = false;
+    float s0 = 0.f, s1x = 0.f, s1y = 0.f;
+    for (int k = 0; k < npsf; ++k) {
+      const float* __restrict__ r = T + STAR + k * STAR_REC;
+      const float dx = dx0 - r[S_XIX], dy = dy0 - r[S_XIY];
+      const float e = fmaf(r[R_QXX], dx * dx, fmaf(r[R_QXY], dx * dy, fmaf(r[R_QYY], dy * dy, r[R_C0])));
+      if (!wave_any(e >= e_zero)) continue;
+      hit = true;
+      const float N = ex2(e);
+      s0 += N;
+      s1x = fmaf(N, fmaf(r[R_PXX], dx, r[R_PXY] * dy), s1x);
+      s1y = fmaf(N, fmaf(r[R_PXY], dx, r[R_PYY] * dy), s1y);
+    }
+    GalAcc1 X = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, D = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < npsf; ++k) {
+      const float* __restrict__ sr = T + STAR + k * STAR_REC;
+      const float dx = dx0 - sr[S_XIX], dy = dy0 - sr[S_XIY];
+      const float dxx = dx * dx, dxy = dx * dy, dyy = dy * dy;
+      if (!wave_any(fmaf(sr[S_GMU], dxx + dyy, sr[S_GC0]) >= e_zero - 1.f)) continue;
+      const float* __restrict__ base = T + GAL + k * ncomp * GAL_REC;
+      if constexpr (NE > 0) {
+#pragma unroll
+        for (int j = 0; j < NE; ++j) hit |= gal_comp1(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, X);
+#pragma unroll
+        for (int j = NE; j < NE + ND; ++j) hit |= gal_comp1(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, D);
+      } else {
+        for (int j = 0; j < ne; ++j) hit |= gal_comp1(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, X);
+        for (int j = ne; j < ncomp; ++j) hit |= gal_comp1(base + j * GAL_REC, dx, dy, dxx, dxy, dyy, e_zero, D);
+      }
+    }
+    if (!hit) {
+      // no component reaches the tile: only the neighbour-variance part of the pixel term
+      const float rE = __builtin_amdgcn_rcpf(ebg);
+      acc[0] += (double)(0.f - 0.5f * vbg * ((x * rE) * rE));
+      continue;
+    }
+    const float ed = T[EDEV];
+    auto mix = [ed](float d, float x_) { return fmaf(ed, d - x_, x_); };
+    const float Gg = mix(D.a0, X.a0);
+    float dG[6];
+    dG[0] = mix(D.a1x, X.a1x);
+    dG[1] = mix(D.a1y, X.a1y);
+    dG[2] = D.a0 - X.a0;
+    const float b2c[3] = {mix(D.b2xx, X.b2xx), mix(D.b2xy, X.b2xy), mix(D.b2yy, X.b2yy)};
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      dG[3 + e] = fmaf(T[W1 + 3 * e], b2c[0], fmaf(T[W1 + 3 * e + 1], b2c[1], T[W1 + 3 * e + 2] * b2c[2]));
+    const float cs = T[CS], cg = T[CG], mus = T[MU_S], mug = T[MU_G];
+    const float Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+    const float Gs = s0;
+    const float Gs2 = Gs * Gs, Gg2 = Gg * Gg, Gsg = Gs * Gg;
+    const float Tv = fmaf(cs, Gs, cg * Gg);
+    const float Uv = fmaf(Ks, Gs2, fmaf(Kg, Gg2, Ksg * Gsg));
+    const float rhos = fmaf(2.f * Ks, Gs, Ksg * Gg), rhog = fmaf(2.f * Kg, Gg, Ksg * Gs);
+    float Tz[NZ], Uz[NZ];
+    Tz[0] = fmaf(mus, Gs, -mug * Gg);
+    Tz[1] = cs * Gs;
+    Tz[2] = 0.5f * Tz[1];
+    Tz[3] = cg * Gg;
+    Tz[4] = 0.5f * Tz[3];
+    Uz[0] = fmaf(T[KA_S], Gs2, fmaf(T[KA_G], Gg2, T[KA_SG] * Gsg));
+    Uz[1] = fmaf(2.f * Ks, Gs2, Ksg * Gsg);
+    Uz[2] = fmaf(T[KV_S], Gs2, 0.5f * Ksg * Gsg);
+    Uz[3] = fmaf(2.f * Kg, Gg2, Ksg * Gsg);
+    Uz[4] = fmaf(T[KV_G], Gg2, 0.5f * Ksg * Gsg);
+    const float dGs[2] = {s1x, s1y};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float gs = k < 2 ? dGs[k] : 0.f;
+      Tz[5 + k] = fmaf(cs, gs, cg * dG[k]);
+      Uz[5 + k] = fmaf(rhos, gs, rhog * dG[k]);
+    }
+    const float E = fmaf(io, Tv, ebg);
+    const float V = fmaf(io2, Uv, vbg);
+    const float rE = __builtin_amdgcn_rcpf(E);
+    const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
+    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
+    const float wT = io * fmaf(x - E, rE, V * xr3), wU = io2 * (-0.5f * xr2);
+    acc[0] += (double)lval;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) acc[1 + j] += (double)fmaf(wT, Tz[j], wU * Uz[j]);
+  }
+  // fixed-order reduction: wavefront butterfly, then the waves in index order
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NG; ++j) red[wv][j] = acc[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < NG) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[k][threadIdx.x];
+    partials[(size_t)blockIdx.x * NG + threadIdx.x] = s;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
@@ -679,6 +846,24 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
     }
   }
 #undef CELESTE_LAUNCH_FULL
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_grad(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
+                            int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
+                            int tw_log2, float e_zero, hipStream_t st, const int* kept) {
+  if (n_items <= 0) return hipSuccess;
+  const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
+  const dim3 g(n_items);
+#define CELESTE_LAUNCH_GRAD(B, E, D) \
+  hipLaunchKernelGGL((k_eval_grad<B, E, D>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
+                     src_flag, tw_log2, e_zero, kept, partials)
+  if (block == 128) {
+    if (unroll) CELESTE_LAUNCH_GRAD(128, 6, 8); else CELESTE_LAUNCH_GRAD(128, 0, 0);
+  } else {
+    if (unroll) CELESTE_LAUNCH_GRAD(256, 6, 8); else CELESTE_LAUNCH_GRAD(256, 0, 0);
+  }
+#undef CELESTE_LAUNCH_GRAD
   return hipGetLastError();
 }
 

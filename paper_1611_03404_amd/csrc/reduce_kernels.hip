@@ -214,6 +214,48 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
   }
 }
 
+// One 64-thread block per source: value and natural gradient from gradient partials (NGRAD per
+// work item), images in order, each image's z-gradient mapped through its band and WCS matrix.
+__global__ __launch_bounds__(64) void k_reduce_grad(const SrcDev* __restrict__ srcs, const ImgDev* __restrict__ imgs,
+                                                    const double* __restrict__ partials,
+                                                    const double* __restrict__ img_const,
+                                                    const double* __restrict__ theta, PriorDev prior,
+                                                    const int* __restrict__ src_flag, double* __restrict__ elbo,
+                                                    double* __restrict__ grad, unsigned long long* __restrict__ px_ctr,
+                                                    double px_weight) {
+  __shared__ double tmp[NGRAD];
+  __shared__ KL kl;
+  const int s = blockIdx.x;
+  if (src_flag && !src_flag[s]) return;
+  const int t = threadIdx.x;
+  const SrcDev sr = srcs[s];
+  double gt = 0.0, vt = 0.0;
+  for (int i = sr.img_begin; i < sr.img_end; ++i) {
+    const ImgDev& im = imgs[i];
+    if (t < NGRAD) {
+      double a = 0.0;
+      for (int it = im.item_begin; it < im.item_end; ++it) a += partials[(size_t)it * NGRAD + t];
+      tmp[t] = a * px_weight;
+    }
+    __syncthreads();
+    if (t == 0) vt += tmp[0] + img_const[i];
+    if (t < NP) {
+      int zr[2];
+      double cr[2];
+      const int nr = theta_to_z(t, im.band, im.wcs, zr, cr);
+      for (int u = 0; u < nr; ++u) gt += cr[u] * tmp[1 + zr[u]];
+    }
+    __syncthreads();
+  }
+  if (t == 0) kl_value_grad(theta + (size_t)s * NP, prior, kl);
+  __syncthreads();
+  if (t == 0) {
+    elbo[s] = vt + kl.val;
+    if (px_ctr) atomicAdd(px_ctr, (unsigned long long)sr.npix);
+  }
+  if (t < NP) grad[(size_t)s * NP + t] = gt + kl.g[t];
+}
+
 // One thread per source: fixed-order sum of the source's value partials.
 __global__ __launch_bounds__(64) void k_reduce_value_t(const SrcDev* __restrict__ srcs, int n_src,
                                                        const ImgDev* __restrict__ imgs,
@@ -264,6 +306,16 @@ hipError_t launch_reduce_full(const SrcDev* srcs, int n_src, const ImgDev* imgs,
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_full, dim3(n_src), dim3(RB), 0, st, srcs, imgs, partials, img_const, theta, prior,
                      src_flag, elbo, grad, hess, px_ctr, px_weight);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_grad(const SrcDev* srcs, int n_src, const ImgDev* imgs, const double* partials,
+                              const double* img_const, const double* theta, PriorDev prior, const int* src_flag,
+                              double* elbo, double* grad, unsigned long long* px_ctr, hipStream_t st,
+                              double px_weight) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_grad, dim3(n_src), dim3(64), 0, st, srcs, imgs, partials, img_const, theta, prior,
+                     src_flag, elbo, grad, px_ctr, px_weight);
   return hipGetLastError();
 }
 
