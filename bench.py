@@ -187,7 +187,7 @@ def _oracle_fit_worker(s):
     t0 = time.perf_counter()
     th0 = oinit.plain_init(sb.u_cat[s], imgs, sb.prior)
     r = newton.fit(th0, imgs, sb.prior, sb.profiles)
-    return time.perf_counter() - t0, float(r.f), int(r.iters), int(r.status)
+    return time.perf_counter() - t0, float(r.elbo), int(r.iters), int(r.status)
 
 
 def oracle_fit_baseline(sb, n, gpu_plain_elbo, gpu_head_elbo, log):
@@ -418,12 +418,14 @@ def main():
                     help="batched workload: also fit a size-stratified sample of this many sources with the oracle "
                          "(complete fits on the host cores; 200 = 1%% of the workload takes about 15 minutes on 16 "
                          "cores) and check the GPU fits' final ELBO against the oracle-converged one")
-    ap.add_argument("--workload", choices=("batched", "field", "sampled", "lbfgs"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "field", "sampled", "lbfgs", "twophase"), default="batched",
                     help="batched: 20,000 independent uneven sources (default); field: crowded 2048x2048 field, "
                          "100,000 sources, 5 bands x 4 epochs, 3 block-coordinate sweeps; sampled: pixel-subsampled "
                          "evaluations of the batched workload; lbfgs: L-BFGS against trust-region Newton from the "
                          "plain start on the 1,000 isolated sources, their bright variant and the batched workload")
     ap.add_argument("--lbfgs-max-iter", type=int, default=1000, help="lbfgs workload: L-BFGS iteration cap")
+    ap.add_argument("--switch-rtol", type=float, default=1e-5,
+                    help="twophase workload: predicted-gain tolerance of the subsampled early phase")
     ap.add_argument("--keep-prob", type=float, default=0.25,
                     help="sampled workload: probability of keeping each 8-row block of an image")
     ap.add_argument("--sweep-probs", default="1,0.5,0.25,0.1",
@@ -464,6 +466,8 @@ def main():
         return probe(args, ctx, log)
     if args.workload == "lbfgs":
         return lbfgs_bench(args, ctx, log)
+    if args.workload == "twophase":
+        return twophase_bench(args, ctx, log)
     if args.workload == "sampled":
         if not all(0.0 < float(x) <= 1.0 for x in args.sweep_probs.split(",") + [args.keep_prob] if x != ""):
             sys.exit("--keep-prob and --sweep-probs must be in (0, 1]")
@@ -784,6 +788,68 @@ def lr_measure(ctx, batch, theta, sb, log):
     }
     log(f"lr covariance: {info}")
     return info
+
+
+def twophase_bench(args, ctx, log):
+    """Trust-region fits of the batched-uneven workload from the plain start, plain against a
+    pixel-subsampled early phase (each source fits the subsampled ELBO estimate until its model's
+    predicted gain falls to --switch-rtol max(1, |L|), then the full ELBO): wall time per fit
+    (graph path, steps of each variant), iterations, pixel evaluations and sources converged at
+    the tolerance rule against the better optimum of the variants, for keep probabilities
+    --sweep-probs below 1 (a fresh seeded mask per step)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from synth.subsample import block_masks
+    from paper_1611_03404_amd import celeste as cb
+    sb = synth.make_config(2, n_sources=args.sources, device="cuda")
+    batch = cb.Batch.from_synth(sb)
+    theta0 = np.zeros((sb.n_sources, 27))
+    theta0[:, 0:2] = sb.u_cat
+    th_start, _ = ctx.start(batch, theta0, cb.default_opts(init_mode=cb.INIT_PLAIN))
+    tune = None if args.no_autotune else ctx.autotune(batch, th_start, cache_path=args.tune_cache)
+    opts = cb.default_opts(init_mode=cb.INIT_PLAIN)
+    probs = sorted({float(x) for x in args.sweep_probs.split(",") if x and float(x) < 1.0}, reverse=True)
+    variants = [("plain", None)] + [(f"p={p}", p) for p in probs]
+    runs = {}
+    for name, p in variants:
+        masks = [block_masks(sb.img_h, p, 161103420 + k) for k in range(args.warmup + args.steps)] if p else None
+        for w in range(args.warmup):
+            if p:
+                ctx.batch_fit_sampled(batch, theta0, masks[w][0], masks[w][1], p, args.switch_rtol, opts)
+            else:
+                ctx.batch_fit(batch, theta0, opts)
+        ctx.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            if p:
+                keep, off = masks[args.warmup + k]
+                th, res = ctx.batch_fit_sampled(batch, theta0, keep, off, p, args.switch_rtol, opts)
+            else:
+                th, res = ctx.batch_fit(batch, theta0, opts)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        runs[name] = dict(res=res, wall=wall, stats=ctx.stats())
+        log(f"twophase {name}: {wall:.3f} s per fit, iterations mean {np.mean(res['iters']):.2f}")
+    best = np.max(np.stack([r["res"]["elbo"] for r in runs.values()]), axis=0)
+    out = {"metric": "converged sources/s, trust-region fits with and without a pixel-subsampled early phase",
+           "workload": f"batched uneven sources ({sb.n_sources}), plain start", "switch_rtol": args.switch_rtol,
+           "steps": args.steps, "autotune": tune, "variants": {}}
+    for name, r in runs.items():
+        res, st = r["res"], r["stats"]
+        ok = (res["status"] == cb.CONVERGED) & (res["elbo"] >= best - 1e-5 * np.abs(best))
+        out["variants"][name] = {
+            "ms_per_fit": 1e3 * r["wall"], "converged_at_tol": int(ok.sum()),
+            "converged_per_s": int(ok.sum()) / r["wall"], "converged_status": int(np.sum(res["status"] == cb.CONVERGED)),
+            "iterations_mean": float(np.mean(res["iters"])), "iterations_max": int(np.max(res["iters"])),
+            "full_evals_mean": float(np.mean(res["n_full_evals"])),
+            "full_pixel_evals_per_fit": st["full_px"] / args.steps, "value_pixel_evals_per_fit": st["value_px"] / args.steps,
+            "elbo_shortfall_vs_best_max_rel": float(np.max((best - res["elbo"]) / np.abs(best))),
+        }
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def lbfgs_bench(args, ctx, log):

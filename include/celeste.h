@@ -333,6 +333,22 @@ int celeste_newton_fit(celeste_ctx* ctx, const celeste_batch* batch, double* the
 int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
                       const celeste_fit_opts* opts, celeste_fit_result* results, void* stream);
 
+/* celeste_batch_fit with a pixel-subsampled early phase (the paper's closing section proposes
+ * subsampling pixels, a second source of randomness in stochastic optimisation, as a speed-up).
+ * Every source first fits the unbiased subsampled estimate of its ELBO that
+ * celeste_elbo_eval_sampled computes for the same keep / keep_off / keep_prob (kept 8-row blocks
+ * weighted 1 / keep_prob, the theta-free part of every pixel summed whole): trust-region
+ * iterations whose gradient, Hessian and trial values come from the kept blocks only.  When the
+ * model's predicted gain there is at most switch_rtol max(1, |L|), the source re-evaluates its
+ * current point on the full ELBO (that step is not an iteration) and continues with full
+ * evaluations, the trust radius it reached and opts' stopping rule; max_iter counts both
+ * phases.  Masks as in celeste_elbo_eval_sampled (host arrays, read before the call returns);
+ * other arguments and results as celeste_batch_fit.  Errors as there; E_INVALID for NULL masks,
+ * keep_prob outside (0, 1], switch_rtol <= 0 or offsets that do not match the image heights. */
+int celeste_batch_fit_sampled(celeste_ctx* ctx, const celeste_batch* batch, double* theta_inout,
+                              const celeste_fit_opts* opts, const uint8_t* keep, const int64_t* keep_off,
+                              double keep_prob, double switch_rtol, celeste_fit_result* results, void* stream);
+
 /* Options of the L-BFGS fit (celeste_lbfgs_fit). */
 typedef struct celeste_lbfgs_opts {
   int32_t max_iter;             /* accepted steps (gradient evaluations - 1), >= 1 (default 1000) */

@@ -145,8 +145,10 @@ def band_moments(theta, band):
 
 
 def lognormal_moments(m, v):
-    """E[l] and E[l^2] for log l ~ N(m, v)."""
-    return math.exp(m + 0.5 * v), math.exp(2.0 * m + 2.0 * v)
+    """E[l] and E[l^2] for log l ~ N(m, v); inf where they overflow (a trial point that far out
+    gets a non-finite ELBO, which the fits reject)."""
+    with np.errstate(over="ignore"):
+        return float(np.exp(m + 0.5 * v)), float(np.exp(2.0 * m + 2.0 * v))
 
 
 # ----------------------------------------------------------------------------

@@ -108,34 +108,34 @@ def tr_subproblem(g, H, delta):
     return p, pred, s, lam
 
 
-def fit(theta0, images, prior, profiles, opts: FitOpts = FitOpts(), record=False):
-    """Maximise the ELBO of one source from theta0 by trust-region Newton in psi coordinates."""
-    theta0 = np.asarray(theta0, dtype=np.float64)
-    u0 = theta0[0:2].copy()
-    psi = transforms.to_psi(theta0, u0, opts.box)
-    theta, d1, d2 = transforms.to_theta(psi, u0, opts.box)
-    f, gt, Ht = model.elbo(theta, images, prior, profiles)
-    g, H = transforms.grad_hess_psi(gt, Ht, d1, d2)
-    delta = opts.delta0
-    hist = []
+def _tr_loop(psi, u0, objective, opts, it0, delta, switch_rtol=None, record=False, hist=None):
+    """The trust-region iteration from psi (f, g, H of objective(psi, want) in psi coordinates).
+
+    Without switch_rtol: the fit proper (stopping rule of the module docstring).  With it: the
+    early phase on a subsampled objective, which stops instead when its model's predicted gain
+    is at most switch_rtol max(1, |f|) (status None: go on with the full objective).  Iterations
+    are counted from it0 against opts.max_iter.  Returns (psi, f, iterations, status, pred, delta)."""
+    f, g, H = objective(psi, "hess")
     status = MAX_ITER
     pred = float("nan")
-    it = 0
+    it = it0
     if not np.isfinite(f):
-        return FitResult(theta, f, 0, NONFINITE, pred, hist)
-    for it in range(opts.max_iter + 1):
+        return psi, f, it, NONFINITE, pred, delta
+    while True:
         p, pred, s, lam = tr_subproblem(g, H, delta)
-        curv_ok = lam[0] >= -opts.curv_tol * max(1.0, np.max(np.abs(lam)))
         if record:
-            hist.append(dict(it=it, elbo=f, pred=pred, delta=delta, lam0=lam[0]))
-        if pred <= opts.pred_rtol * max(1.0, abs(f)) and curv_ok:
+            hist.append(dict(it=it, elbo=f, pred=pred, delta=delta, lam0=lam[0], sampled=switch_rtol is not None))
+        if switch_rtol is not None:
+            if pred <= switch_rtol * max(1.0, abs(f)):
+                status = None
+                break
+        elif pred <= opts.pred_rtol * max(1.0, abs(f)) and lam[0] >= -opts.curv_tol * max(1.0, np.max(np.abs(lam))):
             status = CONVERGED
             break
-        if it == opts.max_iter:
+        if it >= opts.max_iter:
             status = MAX_ITER
             break
-        th_new, _, _ = transforms.to_theta(psi + p, u0, opts.box)
-        f_new = model.elbo_value(th_new, images, prior, profiles)
+        f_new = objective(psi + p, "value")
         rho = (f_new - f) / pred if np.isfinite(f_new) else -np.inf
         pn = np.linalg.norm(p)
         if rho < 0.25:
@@ -144,10 +144,57 @@ def fit(theta0, images, prior, profiles, opts: FitOpts = FitOpts(), record=False
             delta = min(2.0 * delta, opts.delta_max)
         if rho > opts.eta:
             psi = psi + p
-            theta, d1, d2 = transforms.to_theta(psi, u0, opts.box)
-            f, gt, Ht = model.elbo(theta, images, prior, profiles)
-            g, H = transforms.grad_hess_psi(gt, Ht, d1, d2)
+            f, g, H = objective(psi, "hess")
+        it += 1
         if delta < opts.delta_min:
             status = TR_COLLAPSED
             break
-    return FitResult(theta, f, it, status, pred, hist)
+    return psi, f, it, status, pred, delta
+
+
+def _objective(images, prior, profiles, u0, box):
+    def objective(psi, want):
+        theta, d1, d2 = transforms.to_theta(psi, u0, box)
+        if want == "value":
+            return model.elbo_value(theta, images, prior, profiles)
+        f, gt, Ht = model.elbo(theta, images, prior, profiles)
+        g, H = transforms.grad_hess_psi(gt, Ht, d1, d2)
+        return f, g, H
+    return objective
+
+
+def fit(theta0, images, prior, profiles, opts: FitOpts = FitOpts(), record=False):
+    """Maximise the ELBO of one source from theta0 by trust-region Newton in psi coordinates."""
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    u0 = theta0[0:2].copy()
+    psi = transforms.to_psi(theta0, u0, opts.box)
+    hist = []
+    psi, f, it, status, pred, _ = _tr_loop(psi, u0, _objective(images, prior, profiles, u0, opts.box), opts, 0,
+                                           opts.delta0, record=record, hist=hist)
+    return FitResult(transforms.to_theta(psi, u0, opts.box)[0], f, it, status, pred, hist)
+
+
+def fit_sampled(theta0, images, sampled_images, prior, profiles, switch_rtol, opts: FitOpts = FitOpts(),
+                record=False):
+    """Trust-region Newton with a subsampled early phase (the paper's closing section proposes
+    subsampling pixels to speed up the optimisation).  sampled_images are the source's images
+    with per-pixel weights (kept blocks 1/p, dropped blocks 0; the theta-free part of every
+    pixel is kept whole, model.image_sums).  Phase 1 is the trust-region fit of that unbiased
+    estimate of the ELBO, until its model's predicted gain is at most switch_rtol max(1, |L_s|)
+    (no curvature condition) or the iteration cap; phase 2 continues from there on the full
+    ELBO with the trust radius it reached and the fit's own stopping rule.  The switch is not an
+    iteration; the cap counts both phases."""
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    u0 = theta0[0:2].copy()
+    psi = transforms.to_psi(theta0, u0, opts.box)
+    hist = []
+    psi, f, it, status, pred, delta = _tr_loop(psi, u0, _objective(sampled_images, prior, profiles, u0, opts.box),
+                                               opts, 0, opts.delta0, switch_rtol=switch_rtol, record=record,
+                                               hist=hist)
+    n_sampled = it
+    if status is None:
+        psi, f, it, status, pred, _ = _tr_loop(psi, u0, _objective(images, prior, profiles, u0, opts.box), opts,
+                                               it, delta, record=record, hist=hist)
+    r = FitResult(transforms.to_theta(psi, u0, opts.box)[0], f, it, status, pred, hist)
+    r.sampled_iters = n_sampled
+    return r

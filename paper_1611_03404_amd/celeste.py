@@ -115,6 +115,8 @@ def load():
     lib.celeste_lbfgs_opts_default.argtypes = [ctypes.POINTER(LbfgsOpts)]
     lib.celeste_lbfgs_opts_default.restype = None
     lib.celeste_lbfgs_fit.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(LbfgsOpts), vp, vp]
+    lib.celeste_batch_fit_sampled.argtypes = [vp, ctypes.POINTER(CBatch), vp, ctypes.POINTER(FitOpts), vp, vp,
+                                              ctypes.c_double, ctypes.c_double, vp, vp]
     lib.celeste_elbo_eval.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_elbo_eval_noalloc.argtypes = [vp, ctypes.POINTER(CBatch), vp, vp, vp, vp, vp]
     lib.celeste_lr_covariance_from_hessian.argtypes = [vp, i64, ctypes.c_int, vp, vp, ctypes.c_double, vp, vp, vp,
@@ -543,6 +545,24 @@ class Context:
         imf = np.ascontiguousarray(img_field, dtype=np.int32)
         f = CFields(int(n_fields), int(height), int(width), 0, imf.ctypes.data, _ptr(arrays[0]), _ptr(arrays[1]))
         return f, imf
+
+    def batch_fit_sampled(self, batch: Batch, theta0, keep, keep_off, keep_prob, switch_rtol=1e-5, opts=None):
+        """batch_fit with a pixel-subsampled early phase (celeste_batch_fit_sampled): keep (uint8)
+        and keep_off (int64, n_images + 1) select each image's kept 8-row blocks."""
+        S = batch.n_sources
+        th = batch.as_input(theta0, copy=True)
+        if tuple(th.shape) != (S, NP):
+            raise ValueError(f"theta0 must have shape ({S}, {NP})")
+        kp = np.ascontiguousarray(keep, dtype=np.uint8)
+        ko = np.ascontiguousarray(keep_off, dtype=np.int64)
+        if ko.ndim != 1 or kp.ndim != 1 or ko.size != len(batch.images) + 1 or ko[-1] != kp.size:
+            raise ValueError("keep_off must hold n_images + 1 offsets ending at keep.size")
+        res = np.zeros(S, dtype=RESULT_DT)
+        o = opts if opts is not None else default_opts()
+        _check(load().celeste_batch_fit_sampled(self._h, ctypes.byref(batch.c), _ptr(th), ctypes.byref(o),
+                                                kp.ctypes.data, ko.ctypes.data, float(keep_prob),
+                                                float(switch_rtol), res.ctypes.data, self._stream(batch)))
+        return th, res
 
     def lbfgs_fit(self, batch: Batch, theta0, opts=None):
         """L-BFGS fit of every source (celeste_lbfgs_fit); returns (theta, results) like batch_fit

@@ -89,6 +89,7 @@ struct celeste_ctx {
   DevBuf lr_in, lr_cov, lr_status, lr_eval;        // linear-response covariance staging
   DevBuf lfact;                                    // log n! table of the pixel constants
   DevBuf lb_buf;                                   // L-BFGS state beyond the fit state
+  DevBuf imgs_s, items_s, srcs_s, partials_s;      // the pixel-subsampled pack of a fit's early phase
   bool lfact_ready = false;
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
@@ -703,7 +704,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
                     &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
                     &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval,
-                    &c->lfact, &c->lb_buf};
+                    &c->lfact, &c->lb_buf, &c->imgs_s, &c->items_s, &c->srcs_s, &c->partials_s};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
@@ -1073,7 +1074,7 @@ struct FitBufs {
 
 int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   const size_t nd = (size_t)S * (NP * 5 + 2 * NP * NP + 2 + 7);
-  const size_t ni = (size_t)S * 6 + 1;
+  const size_t ni = (size_t)S * 10 + 1;
   CHK(ensure(ctx->st_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
   double* d = as<double>(ctx->st_buf);
   auto take = [&](size_t n) {
@@ -1103,7 +1104,11 @@ int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   f->need_full = ip + 3 * S;
   f->n_full = ip + 4 * S;
   f->flags = ip + 5 * S;
-  f->n_active = ip + 6 * S;
+  f->samp = ip + 6 * S;
+  f->sw = ip + 7 * S;
+  f->fa = ip + 8 * S;
+  f->fb = ip + 9 * S;
+  f->n_active = ip + 10 * S;
   return CELESTE_OK;
 }
 
@@ -1395,6 +1400,127 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   return fit_results(ctx, b, F, S, th, theta_inout, res, st, stage);
 }
 
+// Trust-region fit whose early phase fits a pixel-subsampled estimate of the ELBO (8-row
+// blocks kept by `keep`, weighted 1 / keep_prob): each source moves to the full ELBO when its
+// model's predicted gain on the estimate falls to switch_rtol max(1, |L|), and then runs the
+// fit's own stopping rule.  One iteration evaluates, per source, on whichever objective it is in.
+int run_fit_sampled(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const celeste_fit_opts* o,
+                    const uint8_t* keep, const int64_t* keep_off, double keep_prob, double switch_rtol,
+                    celeste_fit_result* res, hipStream_t st) {
+  StageClock stage(ctx->profile != 0);
+  if (!keep || !keep_off) return fail(CELESTE_E_INVALID, "keep and keep_off must not be NULL");
+  if (!(keep_prob > 0.0 && keep_prob <= 1.0)) return fail(CELESTE_E_INVALID, "keep_prob must be in (0, 1]");
+  if (!(switch_rtol > 0.0)) return fail(CELESTE_E_INVALID, "switch_rtol must be > 0");
+  Packed P;
+  CHK(validate_and_pack(ctx, b, &P));
+  CHK(check_opts(o));
+  if (!theta_inout || !res) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
+  if (keep_off[0] != 0) return fail(CELESTE_E_INVALID, "keep_off[0] must be 0");
+  for (int i = 0; i < P.n_img; ++i)
+    if (keep_off[i + 1] - keep_off[i] != (b->images[i].h + 7) / 8)
+      return fail(CELESTE_E_INVALID, "image %d: keep_off must give (h + 7) / 8 blocks", i);
+  const int S = P.n_src;
+  FitParams fp;
+  fp.max_iter = o->max_iter;
+  fp.pred_rtol = o->pred_rtol;
+  fp.curv_tol = o->curv_tol;
+  fp.delta0 = o->delta0;
+  fp.delta_max = o->delta_max;
+  fp.delta_min = o->delta_min;
+  fp.eta = o->eta;
+  fp.u_box = o->u_box;
+  fp.switch_rtol = switch_rtol;
+  FitDev F;
+  std::vector<double> th;
+  CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
+  // the subsampled pack: the dense image records (pixels already staged) with work items over
+  // the kept blocks only
+  HostPack hs;
+  hs.imgs.assign(P.imgs, P.imgs + P.n_img);
+  hs.srcs.assign(P.srcs, P.srcs + P.n_src);
+  Packed Ps = P;
+  Ps.imgs = hs.imgs.data();
+  Ps.srcs = hs.srcs.data();
+  std::vector<int> kept_rows;
+  CHK(subsample_items(ctx, b, &Ps, keep, keep_off, kept_rows));
+  CHK(ensure(ctx->imgs_s, sizeof(ImgDev) * Ps.n_img));
+  CHK(ensure(ctx->items_s, sizeof(WorkItem) * std::max(1, Ps.n_items)));
+  CHK(ensure(ctx->srcs_s, sizeof(SrcDev) * Ps.n_src));
+  CHK(ensure(ctx->partials_s, sizeof(double) * (size_t)NACC * std::max(1, Ps.n_items)));
+  CHK(ensure(ctx->kept, sizeof(int) * std::max<size_t>(1, kept_rows.size())));
+  HIPCHK(hipMemcpyAsync(ctx->imgs_s.p, Ps.imgs, sizeof(ImgDev) * Ps.n_img, hipMemcpyHostToDevice, st));
+  if (Ps.n_items > 0)
+    HIPCHK(hipMemcpyAsync(ctx->items_s.p, Ps.items, sizeof(WorkItem) * Ps.n_items, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->srcs_s.p, Ps.srcs, sizeof(SrcDev) * Ps.n_src, hipMemcpyHostToDevice, st));
+  if (!kept_rows.empty())
+    HIPCHK(hipMemcpyAsync(ctx->kept.p, kept_rows.data(), sizeof(int) * kept_rows.size(), hipMemcpyHostToDevice, st));
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  const WorkItem* items = as<WorkItem>(ctx->items);
+  const SrcDev* srcs = as<SrcDev>(ctx->srcs);
+  const ImgDev* imgs_s = as<ImgDev>(ctx->imgs_s);
+  const WorkItem* items_s = as<WorkItem>(ctx->items_s);
+  const SrcDev* srcs_s = as<SrcDev>(ctx->srcs_s);
+  const int* kept = as<int>(ctx->kept);
+  float* tables = as<float>(ctx->tables);
+  double* parts = as<double>(ctx->partials);
+  double* parts_s = as<double>(ctx->partials_s);
+  const double* ic = as<double>(ctx->img_const);
+  const double w = 1.0 / keep_prob;
+  // every fitted source starts on the subsampled objective: its value there at the start
+  HIPCHK(launch_fill_int(F.samp, S, 1, st));
+  HIPCHK(launch_split(F.active, F.samp, F.fa, F.fb, S, st));
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.fb, P.prof, tables, P.tstride, st));
+  HIPCHK(launch_eval_value(items_s, Ps.n_items, imgs_s, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fb, parts_s,
+                           ctx->vblock, ctx->variant, ctx->vtile_log2, st, kept));
+  HIPCHK(launch_reduce_value(srcs_s, S, imgs_s, parts_s, ic, F.theta, P.prior, F.fb, F.f, ctr_value(ctx), st, w));
+  stage(ctx->stats.ms_start, st);
+  PhaseTimer T;
+  CHK(T.init(ctx->profile != 0));
+  auto iteration = [&](PhaseTimer* t) -> int {
+    t->mark(0, st);
+    HIPCHK(launch_split(F.need_full, F.samp, F.fa, F.fb, S, st));
+    HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
+    t->mark(1, st);
+    HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fa, parts,
+                            ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
+    HIPCHK(launch_eval_full(items_s, Ps.n_items, imgs_s, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fb, parts_s,
+                            ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
+    t->mark(2, st);
+    HIPCHK(launch_reduce_full(srcs, S, imgs, parts, ic, F.theta, P.prior, F.fa, F.f_full, F.g, F.H, ctr_full(ctx), st));
+    HIPCHK(launch_reduce_full(srcs_s, S, imgs_s, parts_s, ic, F.theta, P.prior, F.fb, F.f_full, F.g, F.H,
+                              ctr_full(ctx), st, w));
+    t->mark(3, st);
+    HIPCHK(launch_zero_int(F.n_active, 1, st));
+    HIPCHK(launch_tr_step(F, S, fp, st));
+    t->mark(4, st);
+    HIPCHK(launch_split(F.active, F.samp, F.fa, F.fb, S, st));
+    HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, F.active, P.prof, tables, P.tstride, st));
+    t->mark(5, st);
+    HIPCHK(launch_eval_value(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fa, parts,
+                             ctx->vblock, ctx->variant, ctx->vtile_log2, st));
+    HIPCHK(launch_eval_value(items_s, Ps.n_items, imgs_s, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fb, parts_s,
+                             ctx->vblock, ctx->variant, ctx->vtile_log2, st, kept));
+    t->mark(6, st);
+    HIPCHK(launch_reduce_value(srcs, S, imgs, parts, ic, F.theta_trial, P.prior, F.fa, F.f_trial, ctr_value(ctx), st));
+    HIPCHK(launch_reduce_value(srcs_s, S, imgs_s, parts_s, ic, F.theta_trial, P.prior, F.fb, F.f_trial,
+                               ctr_value(ctx), st, w));
+    t->mark(7, st);
+    HIPCHK(launch_accept(F, S, fp, st));
+    t->mark(8, st);
+    return CELESTE_OK;
+  };
+  const int poll = T.on ? 1 : std::max(1, o->poll_every);
+  // the switches are loop steps that are not iterations: room for one per source
+  CHK(run_loop(ctx, st, o->max_iter + 2, poll, ctx->use_graph && !T.on, F.n_active, T, iteration,
+               [](celeste_stats& c) {
+                 c.full_launches += 1;
+                 c.value_launches += 1;
+               },
+               accumulate_phases));
+  stage(ctx->stats.ms_loop, st);
+  return fit_results(ctx, b, F, S, th, theta_inout, res, st, stage);
+}
+
 int check_lbfgs_opts(const celeste_lbfgs_opts* o) {
   if (!o) return fail(CELESTE_E_INVALID, "opts is NULL");
   if (o->max_iter < 1 || o->max_iter > 1000000) return fail(CELESTE_E_INVALID, "max_iter must be in 1..1e6");
@@ -1530,6 +1656,14 @@ int celeste_batch_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_in
                       celeste_fit_result* results, void* stream) {
   if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
   return run_fit(ctx, b, theta_inout, opts, results, pick(ctx, stream), true);
+}
+
+int celeste_batch_fit_sampled(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout,
+                              const celeste_fit_opts* opts, const uint8_t* keep, const int64_t* keep_off,
+                              double keep_prob, double switch_rtol, celeste_fit_result* results, void* stream) {
+  if (!ctx) return fail(CELESTE_E_INVALID, "context is NULL");
+  return run_fit_sampled(ctx, b, theta_inout, opts, keep, keep_off, keep_prob, switch_rtol, results,
+                         pick(ctx, stream));
 }
 
 void celeste_lbfgs_opts_default(celeste_lbfgs_opts* o) {

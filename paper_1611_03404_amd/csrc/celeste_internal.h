@@ -174,12 +174,18 @@ struct FitDev {
   int* need_full;       // S  1 when g/H must be recomputed at theta
   int* n_full;          // S
   int* flags;           // S  CELESTE_FLAG_* bits
+  int* samp;            // S  1 while the source fits the pixel-subsampled objective (early phase)
+  int* sw;              // S  1 in the iteration that moves the source from the subsampled to the full
+                        //    objective (its trial point is its current point, to re-evaluate the ELBO)
+  int* fa;              // S  gating flags of the current phase on the full objective ...
+  int* fb;              // S  ... and on the subsampled one (launch_split)
   int* n_active;        // 1 counter
 };
 
 struct FitParams {
   int max_iter;
   double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
+  double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);
@@ -230,6 +236,9 @@ hipError_t launch_plain_init(const SrcDev* srcs, int n_src, const ImgDev* imgs, 
 hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
+// fa[s] = flag[s] && !samp[s], fb[s] = flag[s] && samp[s] for every source
+hipError_t launch_split(const int* flag, const int* samp, int* fa, int* fb, int n_src, hipStream_t s);
 // Linear-response covariance per source from the natural gradient and Hessian at theta (u0:
 // S x 2 position-box centres of the fit's coordinates); cov S x 27 x 27, status S.
 hipError_t launch_lr_cov(const double* theta, const double* u0, double u_box, const double* grad, const double* hess,

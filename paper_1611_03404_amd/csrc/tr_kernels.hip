@@ -42,6 +42,8 @@ __global__ void k_fit_init(FitDev st, int n_src, FitParams fp) {
   st.need_full[s] = 1;
   st.n_full[s] = 0;
   st.pred[s] = 0.0;
+  st.samp[s] = 0;
+  st.sw[s] = 0;
 }
 
 // Surrogate start: theta = T(psi) with the position box centred on the catalog position.
@@ -316,10 +318,19 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
     if (on) pt[t] = pti;
     const double pred = wsum(on ? gi * pti - 0.5 * li * pti * pti : 0.0);
     if (t == 0) {
-      // convergence and iteration cap
+      // convergence and iteration cap; on the subsampled objective, the switch to the full one
       const double f = st.f[s];
       int d = 0;
-      if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
+      if (st.samp[s]) {
+        if (pred <= fp.switch_rtol * fmax(1.0, fabs(f))) {
+          st.samp[s] = 0;
+          st.sw[s] = 1;
+          d = 2;
+        } else if (st.iter[s] >= fp.max_iter) {
+          st.status[s] = CELESTE_MAX_ITER;
+          d = 1;
+        }
+      } else if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
         st.status[s] = CELESTE_CONVERGED;
         d = 1;
       } else if (st.iter[s] >= fp.max_iter) {
@@ -327,11 +338,17 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         d = 1;
       }
       st.pred[s] = pred;
-      if (d) st.active[s] = 0;
+      if (d == 1) st.active[s] = 0;
       done = d;
     }
   }
   __syncthreads();
+  if (done == 2) {
+    // the switch: the trial point is the current point, whose ELBO on the full objective the
+    // value pass evaluates (k_accept takes it as the current value)
+    if (t < NP) st.theta_trial[(size_t)s * NP + t] = st.theta[(size_t)s * NP + t];
+    return;
+  }
   if (done) return;
   // ---- step in psi and the trial point
   double* pp = st.p + (size_t)s * NP;
@@ -353,6 +370,20 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
 __global__ void k_accept(FitDev st, int n_src, FitParams fp) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_src || !st.active[s]) return;
+  if (st.sw[s]) {
+    // moved to the full objective: its value at the current point, then its gradient and Hessian
+    st.sw[s] = 0;
+    st.f[s] = st.f_trial[s];
+    st.need_full[s] = 1;
+    if (!isfinite(st.f[s])) {
+      st.status[s] = CELESTE_NONFINITE;
+      st.active[s] = 0;
+      st.need_full[s] = 0;
+      return;
+    }
+    atomicAdd(st.n_active, 1);
+    return;
+  }
   const double ft = st.f_trial[s], f = st.f[s], pred = st.pred[s];
   const double rho = isfinite(ft) ? (ft - f) / pred : -INFINITY;
   const double pn = st.pnorm[s];
@@ -382,6 +413,20 @@ __global__ void k_accept(FitDev st, int n_src, FitParams fp) {
     return;
   }
   atomicAdd(st.n_active, 1);
+}
+
+__global__ void k_fill(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_split(const int* __restrict__ flag, const int* __restrict__ samp, int* __restrict__ fa,
+                        int* __restrict__ fb, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int f = flag[i] != 0, sm = samp[i] != 0;
+  fa[i] = f && !sm;
+  fb[i] = f && sm;
 }
 
 __global__ void k_zero(int* p, int n) {
@@ -517,6 +562,18 @@ hipError_t launch_lr_cov(const double* theta, const double* u0, double u_box, co
                          int n_src, double* cov, int* status, hipStream_t s) {
   if (n_src <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lr_cov, dim3(n_src), dim3(64), 0, s, theta, u0, u_box, grad, hess, cov, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const int* flag, const int* samp, int* fa, int* fb, int n_src, hipStream_t s) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split, dim3((n_src + 255) / 256), dim3(256), 0, s, flag, samp, fa, fb, n_src);
   return hipGetLastError();
 }
 

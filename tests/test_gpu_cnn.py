@@ -58,26 +58,49 @@ def test_forward_matches_reference(cb, ctx):
     net.close()
 
 
+# Per-layer bounds of the GPU gradient (BF16 weights, activations and back-propagated gradients,
+# FP32 accumulation) against the FP64 reference on the same BF16-rounded weights and inputs:
+# relative L2 error of each layer's gradient, and for the dense layers (few roundings between the
+# loss and the weights) the 99th percentile of the element-wise error relative to
+# max(|g*|, 0.05 max|g*|).  Measured on two seeds: relative L2 <= 0.113 (first convolution: its
+# weight gradient sums products of a gradient rounded to BF16 after each of the four layers above
+# it, with heavy cancellation), <= 0.061 (other convolutions), <= 0.011 (dense); element p99 <=
+# 0.012 (dense).  The bounds leave 2-4x margin; a scale error (a missing 1/B, a factor 2 in the
+# loss derivative) moves the norm ratio by far more than its 2e-2 bound (measured <= 0.008).
+REL_L2_BOUND = [0.25, 0.08, 0.15, 0.08, 0.08, 0.08, 0.06, 0.06, 0.03, 0.03, 0.03, 0.03]
+ELEM_P99_BOUND = {8: 0.05, 9: 0.05, 10: 0.05, 11: 0.05}
+
+
 def test_gradient_matches_reference(cb, ctx):
     import torch
-    rng = np.random.default_rng(1)
-    p = init_params(12)
-    net = cb.Net(ctx, p, np.zeros(27), np.ones(27))
-    B = 12
-    x = rng.normal(size=(B, 5, 32, 32)).astype(np.float32)
-    t = rng.normal(size=(B, 27)).astype(np.float32)
-    loss, g = net.loss_grad(torch.from_numpy(x).to(torch.bfloat16).cuda(), torch.from_numpy(t).cuda())
-    lr_, gr = cnn.loss_and_grad(p, _bf16_round(x).reshape(x.shape), t.astype(np.float64))
-    cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
-    _say("loss", loss, lr_, "grad cosine", cos)
-    assert abs(loss - lr_) <= 2e-2 * abs(lr_)
-    assert cos >= 0.999
     offs = np.cumsum([0] + [int(np.prod(s)) for s in cnn.param_shapes()])
-    for k in range(12):
-        a, b_ = g[offs[k]:offs[k + 1]], gr[offs[k]:offs[k + 1]]
-        c = float(a @ b_ / (np.linalg.norm(a) * np.linalg.norm(b_) + 1e-30))
-        _say("layer", k, "cosine", c)
-        assert c >= 0.99
+    for seed in (12, 21):
+        rng = np.random.default_rng(seed)
+        p = init_params(seed)
+        net = cb.Net(ctx, p, np.zeros(27), np.ones(27))
+        B = 12
+        x = rng.normal(size=(B, 5, 32, 32)).astype(np.float32)
+        t = rng.normal(size=(B, 27)).astype(np.float32)
+        loss, g = net.loss_grad(torch.from_numpy(x).to(torch.bfloat16).cuda(), torch.from_numpy(t).cuda())
+        pr = p.copy()
+        for k in range(0, 12, 2):                     # weights are used in BF16, biases in FP32
+            pr[offs[k]:offs[k + 1]] = _bf16_round(p[offs[k]:offs[k + 1]])
+        lr_, gr = cnn.loss_and_grad(pr, _bf16_round(x).reshape(x.shape), t.astype(np.float64))
+        cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+        _say("seed", seed, "loss", loss, lr_, "grad cosine", cos)
+        assert abs(loss - lr_) <= 2e-2 * abs(lr_)
+        assert cos >= 0.999
+        for k in range(12):
+            a, b_ = g[offs[k]:offs[k + 1]], gr[offs[k]:offs[k + 1]]
+            ratio = float(np.linalg.norm(a) / np.linalg.norm(b_))
+            l2 = float(np.linalg.norm(a - b_) / np.linalg.norm(b_))
+            el = np.abs(a - b_) / np.maximum(np.abs(b_), 0.05 * np.abs(b_).max())
+            _say("layer", k, "norm ratio", ratio, "rel L2", l2, "elem p99", float(np.quantile(el, 0.99)))
+            assert abs(ratio - 1.0) <= 2e-2, (seed, k, ratio)
+            assert l2 <= REL_L2_BOUND[k], (seed, k, l2)
+            if k in ELEM_P99_BOUND:
+                assert np.quantile(el, 0.99) <= ELEM_P99_BOUND[k], (seed, k)
+        net.close()
 
 
 def test_training_reduces_loss(cb, ctx):

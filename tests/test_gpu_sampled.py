@@ -195,3 +195,85 @@ def test_invalid_masks_rejected(cb, ctx, bad):
     with pytest.raises(cb.CelesteError) as ei:
         ctx.elbo_eval_sampled(b, th, keep, off, p)
     assert ei.value.code == cb.E_INVALID
+
+
+def test_fit_with_subsampled_early_phase(cb, ctx):
+    """celeste_batch_fit_sampled: trust-region fits that start on the subsampled estimate
+    (p = 0.25) and switch to the full ELBO.  Config 0 reaches the optimum of the oracle's
+    two-phase fit with the same mask (A22: within 1e-5 |L*| or above) and reports the oracle's
+    ELBO at its parameters; on a ragged config-1 subset every source converges, the two smallest
+    reach the oracle's two-phase optimum and most the plain batched fit's;
+    graph replay gives the eager results bit for bit; bad arguments are refused.""" 
+    from oracle import init as oinit
+    from oracle import newton
+    c0 = synth.make_config(0)
+    keep, off = block_masks(c0.img_h, 0.25, 3)
+    b = cb.Batch.from_synth(c0)
+    th0 = np.zeros((1, 27))
+    th0[:, 0:2] = c0.u_cat
+    th, res = ctx.batch_fit_sampled(b, th0, keep, off, 0.25, switch_rtol=1e-5,
+                                    opts=cb.default_opts(init_mode=cb.INIT_PLAIN))
+    imgs = model.source_images(c0, 0)
+    simgs = []
+    for j, img in enumerate(imgs):
+        w = np.repeat(keep[off[j]:off[j + 1]].astype(np.float64) / 0.25, 8)[: img["h"]]
+        simgs.append(dict(img, weights=np.repeat(w[:, None], img["w"], axis=1)))
+    ref = newton.fit_sampled(oinit.plain_init(c0.u_cat[0], imgs, c0.prior), imgs, simgs, c0.prior, c0.profiles,
+                             switch_rtol=1e-5)
+    _say("cfg0 two-phase: gpu", res[0]["elbo"], res[0]["iters"], res[0]["status"], "oracle", ref.elbo, ref.iters,
+         ref.sampled_iters)
+    assert res[0]["status"] == cb.CONVERGED and ref.status == newton.CONVERGED
+    assert abs(res[0]["elbo"] - ref.elbo) <= 1e-5 * abs(ref.elbo) or res[0]["elbo"] >= ref.elbo
+    assert_elbo_close(res[0]["elbo"], model.elbo_value(th[0], imgs, c0.prior, c0.profiles), what="cfg0 two-phase")
+
+    full = synth.make_config(1, n_sources=40)
+    side = full.truth["side"]
+    small = list(np.argsort(side, kind="stable")[:2])
+    sb = full.subset(small + list(np.argsort(side)[-4:]) + [3, 17, 29])
+    keep, off = block_masks(sb.img_h, 0.25, 5)
+    b = cb.Batch.from_synth(sb)
+    th0 = np.zeros((sb.n_sources, 27))
+    th0[:, 0:2] = sb.u_cat
+    opts = cb.default_opts(init_mode=cb.INIT_PLAIN)
+    _, plain = ctx.batch_fit(b, th0, opts)
+    th_s, samp = ctx.batch_fit_sampled(b, th0, keep, off, 0.25, switch_rtol=1e-5, opts=opts)
+    at_plain = 0
+    for s in range(sb.n_sources):
+        _say("source", s, "plain", plain[s]["elbo"], plain[s]["iters"], "two-phase", samp[s]["elbo"], samp[s]["iters"])
+        assert samp[s]["status"] == cb.CONVERGED
+        L = plain[s]["elbo"]
+        at_plain += abs(samp[s]["elbo"] - L) <= 1e-5 * abs(L) or samp[s]["elbo"] >= L
+    # the early phase can lead a source to another of its local optima (star/galaxy modes, flat
+    # shape directions): most sources end at the plain fit's optimum, and the oracle's two-phase
+    # fit with the same mask pins the small ones
+    assert at_plain >= 0.7 * sb.n_sources, at_plain
+    for s in range(2):
+        imgs = model.source_images(sb, s)
+        simgs = []
+        for j, img in enumerate(imgs):
+            i = int(sb.src_img_off[s]) + j
+            w = np.repeat(keep[off[i]:off[i + 1]].astype(np.float64) / 0.25, 8)[: img["h"]]
+            simgs.append(dict(img, weights=np.repeat(w[:, None], img["w"], axis=1)))
+        ref = newton.fit_sampled(oinit.plain_init(sb.u_cat[s], imgs, sb.prior), imgs, simgs, sb.prior, sb.profiles,
+                                 switch_rtol=1e-5)
+        _say("source", s, "oracle two-phase", ref.elbo, ref.iters, ref.sampled_iters)
+        assert abs(samp[s]["elbo"] - ref.elbo) <= 1e-5 * abs(ref.elbo) or samp[s]["elbo"] >= ref.elbo, s
+        assert_elbo_close(samp[s]["elbo"], model.elbo_value(th_s[s], imgs, sb.prior, sb.profiles), what=f"src {s}")
+    try:
+        ctx.set_option(cb.OPT_USE_GRAPH, 0)
+        th_e, eager = ctx.batch_fit_sampled(b, th0, keep, off, 0.25, switch_rtol=1e-5, opts=opts)
+    finally:
+        ctx.set_option(cb.OPT_USE_GRAPH, 1)
+    assert np.array_equal(th_e, th_s) and np.array_equal(eager["elbo"], samp["elbo"])
+    assert np.array_equal(eager["iters"], samp["iters"])
+    for kw in (dict(keep_prob=0.0), dict(switch_rtol=0.0)):
+        args = dict(keep_prob=0.25, switch_rtol=1e-5)
+        args.update(kw)
+        with pytest.raises(cb.CelesteError) as ei:
+            ctx.batch_fit_sampled(b, th0, keep, off, args["keep_prob"], switch_rtol=args["switch_rtol"], opts=opts)
+        assert ei.value.code == cb.E_INVALID
+    bad = off.copy()
+    bad[1:] += 1
+    with pytest.raises(cb.CelesteError):
+        ctx.batch_fit_sampled(b, th0, np.concatenate([keep, np.zeros(sb.n_images, np.uint8)])[: bad[-1]], bad, 0.25,
+                              opts=opts)

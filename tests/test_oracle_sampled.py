@@ -5,10 +5,12 @@ Hessian (unbiasedness)."""
 import itertools
 
 import numpy as np
+import pytest
 
 import synth
 from synth.generate import perturb_theta
 from oracle import model
+from synth.subsample import block_masks
 
 
 def _weights(img, keep_blocks, p):
@@ -63,3 +65,34 @@ def test_block_masks_shape_and_rate():
     assert keep.dtype == np.uint8 and keep.size == 23
     k2, _ = synth.subsample.block_masks(np.full(4000, 64), 0.25, seed=4)
     assert abs(k2.mean() - 0.25) < 0.01
+
+
+def test_fit_with_subsampled_early_phase():
+    """Trust-region fit whose early phase fits the subsampled estimate: with every block kept the
+    estimate is the ELBO, and the two-phase fit ends at the plain fit's optimum; with p = 0.25 it
+    spends its first iterations on the estimate, switches, and still reaches the plain fit's
+    optimum (A22: within 1e-5 |L*| or above) from the same start."""
+    from oracle import init as oinit
+    from oracle import newton
+    sb = synth.make_config(0)
+    imgs = model.source_images(sb, 0)
+    th0 = oinit.plain_init(sb.u_cat[0], imgs, sb.prior)
+    ref = newton.fit(th0, imgs, sb.prior, sb.profiles)
+    for p, seed in ((1.0, 0), (0.25, 3)):
+        keep, off = block_masks(sb.img_h, p, seed)
+        simgs = []
+        for j, img in enumerate(imgs):
+            w = np.repeat(keep[off[j]:off[j + 1]].astype(np.float64) / p, 8)[: img["h"]]
+            simgs.append(dict(img, weights=np.repeat(w[:, None], img["w"], axis=1)))
+        r = newton.fit_sampled(th0, imgs, simgs, sb.prior, sb.profiles, switch_rtol=1e-5, record=True)
+        assert r.status == newton.CONVERGED
+        assert abs(r.elbo - ref.elbo) <= 1e-5 * abs(ref.elbo) or r.elbo >= ref.elbo
+        assert r.sampled_iters >= 1 and r.iters > r.sampled_iters
+        phases = [h["sampled"] for h in r.history]
+        assert phases == sorted(phases, reverse=True)           # the estimate first, then the ELBO
+        if p == 1.0:
+            # the estimate equals the ELBO: the first phase is the plain fit's first iterations
+            for a, b in zip(r.history, ref.history):
+                if not a["sampled"]:
+                    break
+                assert a["elbo"] == pytest.approx(b["elbo"], rel=1e-12)
