@@ -7,12 +7,14 @@
 // three) and dense 2048->256 (ReLU) -> 27.  Every matrix product (convolution
 // forward, data gradient and weight gradient as implicit GEMMs, dense layers)
 // runs on one gather-GEMM kernel on the BF16 matrix cores (16x16x32 MFMA, FP32
-// accumulation, split-K partials summed in a fixed order).  Activations and
+// accumulation, split-K partials summed in a fixed order; the convolution forward's bias,
+// ReLU and BF16 store fused into the product where it needs no split).  Activations and
 // gradients feeding a product are BF16; master weights, Adam moments, biases and
 // all reductions are FP32.
 #include <math.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <new>
 #include <string>
@@ -34,20 +36,58 @@ __device__ __forceinline__ float from_bf16(bf16 x) { return (float)x; }
 constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;
 
 // ------------------------------------------------------------------ gather loaders
-// Each loader returns A(m, k) and B(k, n) of the product C[m][n] = sum_k A(m,k) B(k,n)
-// (callers guarantee m < M, n < N, k < K).
+// Each loader gives 8 consecutive k of A(m, k) (a8) and of B(k, n) (b8) of the product
+// C[m][n] = sum_k A(m,k) B(k,n), zero for k >= kend or an index out of range; the index
+// decomposition is done once per run of 8, not per element.
+
+// kk -> (ky, kx) of a 3x3 kernel tap
+__device__ __forceinline__ int tap_y(int kk) { return (kk * 11) >> 5; }   // kk / 3 for kk < 9
+__device__ __forceinline__ int tap_x(int kk) { return kk - 3 * tap_y(kk); }
+
+typedef __attribute__((ext_vector_type(8))) unsigned short u16x8_t;
+
+__device__ __forceinline__ bf16x8_t zero8() {
+  bf16x8_t z;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) z[j] = (bf16)0.f;
+  return z;
+}
+
+// 8 contiguous BF16 values at p: one 16-byte load where p is aligned and all 8 are wanted, else
+// element by element (the first n_valid).
+__device__ __forceinline__ bf16x8_t load8(const bf16* p, int n_valid, bool aligned) {
+  if (n_valid >= 8 && aligned && ((uintptr_t)p & 15) == 0) return *reinterpret_cast<const bf16x8_t*>(p);
+  bf16x8_t v = zero8();
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < n_valid) v[j] = p[j];
+  return v;
+}
 
 struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img][ci][p + off(kk)]
   const bf16* W;
   const bf16* X;
   int Cin, H, Wd;
-  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)m * Cin * 9 + k]); }
-  __device__ float b(int k, int n) const {
-    const int ci = k / 9, kk = k - ci * 9;
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    const size_t o = (size_t)m * Cin * 9 + k;
+    return load8(W + o, kend - k, (o & 7) == 0);
+  }
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    bf16x8_t v = zero8();
     const int HW = H * Wd, img = n / HW, p = n - img * HW;
-    const int y = p / Wd + kk / 3 - 1, x = p % Wd + kk % 3 - 1;
-    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
-    return from_bf16(X[((size_t)img * Cin + ci) * HW + y * Wd + x]);
+    const int py = p / Wd, px = p - py * Wd;
+    int ci = k / 9, kk = k - ci * 9;
+    const bf16* Xi = X + (size_t)img * Cin * HW;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int y = py + tap_y(kk) - 1, x = px + tap_x(kk) - 1;
+      if (k + j < kend && y >= 0 && y < H && x >= 0 && x < Wd) v[j] = Xi[(size_t)ci * HW + y * Wd + x];
+      if (++kk == 9) {
+        kk = 0;
+        ++ci;
+      }
+    }
+    return v;
   }
 };
 
@@ -55,16 +95,35 @@ struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img
   const bf16* W;
   const bf16* dY;
   int Cin, Cout, H, Wd;
-  __device__ float a(int m, int k) const {
-    const int co = k / 9, kk = k - co * 9;
-    return from_bf16(W[((size_t)co * Cin + m) * 9 + kk]);
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    bf16x8_t v = zero8();
+    int co = k / 9, kk = k - co * 9;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (k + j < kend) v[j] = W[((size_t)co * Cin + m) * 9 + kk];
+      if (++kk == 9) {
+        kk = 0;
+        ++co;
+      }
+    }
+    return v;
   }
-  __device__ float b(int k, int n) const {
-    const int co = k / 9, kk = k - co * 9;
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    bf16x8_t v = zero8();
     const int HW = H * Wd, img = n / HW, p = n - img * HW;
-    const int y = p / Wd - kk / 3 + 1, x = p % Wd - kk % 3 + 1;
-    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
-    return from_bf16(dY[((size_t)img * Cout + co) * HW + y * Wd + x]);
+    const int py = p / Wd, px = p - py * Wd;
+    int co = k / 9, kk = k - co * 9;
+    const bf16* Di = dY + (size_t)img * Cout * HW;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int y = py - tap_y(kk) + 1, x = px - tap_x(kk) + 1;
+      if (k + j < kend && y >= 0 && y < H && x >= 0 && x < Wd) v[j] = Di[(size_t)co * HW + y * Wd + x];
+      if (++kk == 9) {
+        kk = 0;
+        ++co;
+      }
+    }
+    return v;
   }
 };
 
@@ -72,16 +131,26 @@ struct LdConvWgrad {      // dW[co][ci*9+kk] = sum_{img,p} dY[img][co][p] X[img]
   const bf16* dY;
   const bf16* X;
   int Cin, Cout, H, Wd;
-  __device__ float a(int m, int k) const {
+  // k = img*HW + p; HW and the run's first k are multiples of 8, so a run stays in one image
+  // (and, with Wd >= 8 a multiple of 8, in one image row)
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
     const int HW = H * Wd, img = k / HW, p = k - img * HW;
-    return from_bf16(dY[((size_t)img * Cout + m) * HW + p]);
+    return load8(dY + ((size_t)img * Cout + m) * HW + p, kend - k, true);
   }
-  __device__ float b(int k, int n) const {
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    bf16x8_t v = zero8();
     const int HW = H * Wd, img = k / HW, p = k - img * HW;
+    const int py = p / Wd, px = p - py * Wd;
     const int ci = n / 9, kk = n - ci * 9;
-    const int y = p / Wd + kk / 3 - 1, x = p % Wd + kk % 3 - 1;
-    if (y < 0 || y >= H || x < 0 || x >= Wd) return 0.f;
-    return from_bf16(X[((size_t)img * Cin + ci) * HW + y * Wd + x]);
+    const int y = py + tap_y(kk) - 1, x0 = px + tap_x(kk) - 1;
+    if (y < 0 || y >= H) return v;
+    const bf16* row = X + ((size_t)img * Cin + ci) * HW + (size_t)y * Wd;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int x = x0 + j;
+      if (k + j < kend && x >= 0 && x < Wd) v[j] = row[x];
+    }
+    return v;
   }
 };
 
@@ -89,32 +158,68 @@ struct LdFcFwd {          // Y[o][b] = sum_i W[o][i] X[b][i]
   const bf16* W;
   const bf16* X;
   int In;
-  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)m * In + k]); }
-  __device__ float b(int k, int n) const { return from_bf16(X[(size_t)n * In + k]); }
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    return load8(W + (size_t)m * In + k, kend - k, (In & 7) == 0);
+  }
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    return load8(X + (size_t)n * In + k, kend - k, (In & 7) == 0);
+  }
 };
 
 struct LdFcDgrad {        // dX[i][b] = sum_o W[o][i] dY[b][o]
   const bf16* W;
   const bf16* dY;
   int In, Out;
-  __device__ float a(int m, int k) const { return from_bf16(W[(size_t)k * In + m]); }
-  __device__ float b(int k, int n) const { return from_bf16(dY[(size_t)n * Out + k]); }
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    bf16x8_t v = zero8();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k + j < kend) v[j] = W[(size_t)(k + j) * In + m];
+    return v;
+  }
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    return load8(dY + (size_t)n * Out + k, kend - k, ((size_t)n * Out + k) % 8 == 0);
+  }
 };
 
 struct LdFcWgrad {        // dW[o][i] = sum_b dY[b][o] X[b][i]
   const bf16* dY;
   const bf16* X;
   int In, Out;
-  __device__ float a(int m, int k) const { return from_bf16(dY[(size_t)k * Out + m]); }
-  __device__ float b(int k, int n) const { return from_bf16(X[(size_t)k * In + n]); }
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    bf16x8_t v = zero8();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k + j < kend) v[j] = dY[(size_t)(k + j) * Out + m];
+    return v;
+  }
+  __device__ bf16x8_t b8(int k, int n, int kend) const {
+    bf16x8_t v = zero8();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k + j < kend) v[j] = X[(size_t)(k + j) * In + n];
+    return v;
+  }
+};
+
+// Optional fused epilogue of a product with one K split: the convolution forward's
+// act[img][co][p] = bf16(relu(C[co][img*HW+p] + bias[co])) instead of storing C.
+struct EpConvFwd {
+  const float* bias;
+  bf16* act;
+  int HW;
 };
 
 // C[z][m][n] = sum over the z-th K split of A(m,k) B(k,n).  Block 256 = 4 waves in a
-// 2x2 arrangement, each wave a 32x32 sub-tile of 2x2 MFMA 16x16x32 tiles.
+// 2x2 arrangement, each wave a 32x32 sub-tile of 2x2 MFMA 16x16x32 tiles.  Operand runs of
+// 8 BF16 go to LDS and come back as single 16-byte accesses; the next K step's operands are
+// loaded into registers while the current step's products run.  With ep.act set (and one
+// split) the convolution forward epilogue is applied in place of the C store.
 template <class LD>
-__global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kchunk, float* __restrict__ C) {
-  __shared__ bf16 As[TM][TKP];
-  __shared__ bf16 Bs[TN][TKP];
+__global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kchunk, float* __restrict__ C,
+                                              EpConvFwd ep) {
+  __shared__ __align__(16) bf16 As[TM][TKP];
+  __shared__ __align__(16) bf16 Bs[TN][TKP];
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -125,33 +230,26 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const int lr = t >> 2, lk = (t & 3) * 8;
+  const int m = m0 + lr, n = n0 + lr;
+  auto fetch = [&](int k0, bf16x8_t& av, bf16x8_t& bv) {
+    const int k = k0 + lk;
+    av = (m < M && k < kend) ? ld.a8(m, k, kend) : zero8();
+    bv = (n < N && k < kend) ? ld.b8(k, n, kend) : zero8();
+  };
+  bf16x8_t an, bn;
+  fetch(kbeg, an, bn);
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
-    {
-      const int m = m0 + lr;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + lk + j;
-        As[lr][lk + j] = to_bf16((m < M && k < kend) ? ld.a(m, k) : 0.f);
-      }
-      const int n = n0 + lr;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + lk + j;
-        Bs[lr][lk + j] = to_bf16((n < N && k < kend) ? ld.b(k, n) : 0.f);
-      }
-    }
+    *reinterpret_cast<bf16x8_t*>(&As[lr][lk]) = an;
+    *reinterpret_cast<bf16x8_t*>(&Bs[lr][lk]) = bn;
     __syncthreads();
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    if (k0 + TK < kend) fetch(k0 + TK, an, bn);   // next step's operands, in flight during the products
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      bf16x8_t av;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = As[wm + i * 16 + r16][kq + e];
+      const bf16x8_t av = *reinterpret_cast<const bf16x8_t*>(&As[wm + i * 16 + r16][kq]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        bf16x8_t bv;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = Bs[wn + j * 16 + r16][kq + e];
+        const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + j * 16 + r16][kq]);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
       }
     }
@@ -164,15 +262,31 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-        const int n = n0 + wn + j * 16 + (lane & 15);
-        if (m < M && n < N) Cz[(size_t)m * N + n] = acc[i][j][r];
+        const int mm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int nn = n0 + wn + j * 16 + (lane & 15);
+        if (mm < M && nn < N) {
+          if (ep.act) {
+            const int img = nn / ep.HW, p = nn - img * ep.HW;
+            ep.act[((size_t)img * M + mm) * ep.HW + p] = to_bf16(fmaxf(acc[i][j][r] + ep.bias[mm], 0.f));
+          } else {
+            Cz[(size_t)mm * N + nn] = acc[i][j][r];
+          }
+        }
       }
 }
 
+// Sum over the K splits in split order; 8 loads in flight at a time.
 __device__ __forceinline__ float split_sum(const float* C, int S, size_t MN, size_t idx) {
   float s = C[idx];
-  for (int z = 1; z < S; ++z) s += C[(size_t)z * MN + idx];
+  int z = 1;
+  for (; z + 8 <= S; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = C[(size_t)(z + j) * MN + idx];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; z < S; ++z) s += C[(size_t)z * MN + idx];
   return s;
 }
 
@@ -423,13 +537,15 @@ __global__ __launch_bounds__(256) void k_patches(const SrcDev* __restrict__ srcs
 
 // Launches the product with at most `splits` K-splits; *splits is set to the number used
 // (the count the epilogue must sum).
+// ep (optional): the convolution forward epilogue, applied in the product when it has one split.
 template <class LD>
-hipError_t gemm(LD ld, int M, int N, int K, float* C, int& splits, hipStream_t st) {
+hipError_t gemm(LD ld, int M, int N, int K, float* C, int& splits, hipStream_t st, EpConvFwd ep = EpConvFwd{}) {
   const int kchunk = ((K + splits - 1) / splits + TK - 1) / TK * TK;
   const int S = (K + kchunk - 1) / kchunk;
   splits = S;
+  if (S != 1) ep.act = nullptr;
   dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, S);
-  hipLaunchKernelGGL(k_gemm<LD>, grid, dim3(256), 0, st, ld, M, N, K, kchunk, C);
+  hipLaunchKernelGGL(k_gemm<LD>, grid, dim3(256), 0, st, ld, M, N, K, kchunk, C, ep);
   return hipGetLastError();
 }
 
@@ -569,9 +685,12 @@ hipError_t net_forward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
     const size_t M = L.cout[l], N = (size_t)B * HW, K = (size_t)L.cin[l] * 9;
     int S = splits_for(M, N, K, n->c_cap);
     LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], L.hw[l], L.hw[l]};
-    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ep_conv_fwd, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, L.cout[l], B, HW,
-                       n->w + L.off[2 * l + 1], n->r[l]);
+    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, EpConvFwd{n->w + L.off[2 * l + 1], n->r[l], HW})) !=
+        hipSuccess)
+      return e;
+    if (S > 1)   // split products: the epilogue sums the splits
+      hipLaunchKernelGGL(k_ep_conv_fwd, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, L.cout[l], B, HW,
+                         n->w + L.off[2 * l + 1], n->r[l]);
     if (L.pool[l]) {
       hipLaunchKernelGGL(k_pool_fwd, dim3(nblk((size_t)B * L.cout[l] * HW / 4)), dim3(256), 0, st, n->r[l],
                          B * L.cout[l], L.hw[l], L.hw[l], n->p[l]);
