@@ -437,6 +437,13 @@ def main():
                     help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
                          "sweeps over conflict-free colours")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")
+    ap.add_argument("--persistent", type=int, choices=range(0, 17), default=None, metavar="0..16",
+                    help="trust-region fits: persistent pixel kernels with this many blocks per compute unit "
+                         "drawing from the device work list, or one block per work item (0); default: the "
+                         "library's")
+    ap.add_argument("--tr-cholesky", type=int, choices=(0, 1), default=None,
+                    help="trust-region subproblem: interior Newton step by Cholesky first (1) or always the "
+                         "eigendecomposition (0); default: the library's")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: read the launch shapes from it when it has an entry for this "
                          "device and workload, else time them and add one (runs that must share a launch "
@@ -462,6 +469,10 @@ def main():
         print("[bench]", *a, file=sys.stderr, flush=True)
 
     ctx = cb.Context(0)
+    if args.persistent is not None:
+        ctx.set_option(cb.OPT_PERSISTENT, args.persistent)
+    if args.tr_cholesky is not None:
+        ctx.set_option(cb.OPT_TR_CHOLESKY, args.tr_cholesky)
     if args.probe:
         return probe(args, ctx, log)
     if args.workload == "lbfgs":

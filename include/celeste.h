@@ -91,7 +91,7 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    kernel takes per step: 8, 16, 32 or 64 (default 8) */
   CELESTE_OPT_VALUE_BLOCK = 7,  /* threads per value-kernel block: 128 or 256 (default 256) */
   CELESTE_OPT_VALUE_TILE_W = 8, /* tile width of the value kernel: 8, 16, 32 or 64 (default 8) */
-  CELESTE_OPT_EXACT_ZERO = 9    /* skip threshold of the value+gradient+Hessian kernel: a mixture
+  CELESTE_OPT_EXACT_ZERO = 9,   /* skip threshold of the value+gradient+Hessian kernel: a mixture
                                    component whose density is below 2^-v on a whole tile is skipped.
                                    160 (always exact: below the smallest FP32 subnormal), 127 (exact
                                    where the device's exp2 flushes results below 2^-126 to zero, which
@@ -99,6 +99,18 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    the context's choice (127 where exact, else 160; the default), or
                                    1 to skip nothing: every component, galaxy group and tile is
                                    evaluated (the reference the skips are tested against) */
+  CELESTE_OPT_PERSISTENT = 10,  /* trust-region fits (celeste_newton_fit, celeste_batch_fit): n in
+                                   1..16 = before each value+gradient+Hessian pass the work items of
+                                   the sources still being fitted are compacted into a device list,
+                                   and n blocks per compute unit of a persistent pixel kernel draw
+                                   them in turn (grids do not shrink otherwise: blocks of finished
+                                   sources exit at once; default 2); 0 = one block per work item.
+                                   Results are bitwise the same */
+  CELESTE_OPT_TR_CHOLESKY = 11  /* trust-region subproblem (section III-B): 1 = where -H is positive
+                                   definite and its Newton step lies inside the region, that step is
+                                   taken from one Cholesky factorisation (it solves the subproblem
+                                   exactly); otherwise, and always with 0, the eigendecomposition and
+                                   secular equation (default 1).  The two differ by rounding */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -208,7 +220,8 @@ void celeste_ctx_destroy(celeste_ctx* ctx);
 const char* celeste_last_error(void);
 
 /* Set a tuning option of the context (CELESTE_OPT_*).  The options change only how the
- * pixel sums are grouped (results move by rounding, far inside the stated tolerances);
+ * pixel sums are grouped or how the trust-region subproblem is solved (results move by
+ * rounding, far inside the stated tolerances);
  * CELESTE_OPT_EXACT_ZERO changes only which exactly-zero work is skipped (results are
  * bitwise the same).
  * Errors: E_INVALID (unknown option or value out of range). */

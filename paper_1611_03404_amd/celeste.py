@@ -26,7 +26,7 @@ CONVERGED, MAX_ITER, TR_COLLAPSED, NONFINITE, LINE_SEARCH_FAILED = 0, 1, 2, 3, 4
 INIT_AS_GIVEN, INIT_PLAIN, INIT_SURROGATE = 0, 1, 2
 FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
-OPT_TILE_W, OPT_VALUE_BLOCK, OPT_VALUE_TILE_W, OPT_EXACT_ZERO = 6, 7, 8, 9
+OPT_TILE_W, OPT_VALUE_BLOCK, OPT_VALUE_TILE_W, OPT_EXACT_ZERO, OPT_PERSISTENT, OPT_TR_CHOLESKY = 6, 7, 8, 9, 10, 11
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("nbr_pitch", "<i4"),

@@ -90,6 +90,10 @@ struct celeste_ctx {
   DevBuf lfact;                                    // log n! table of the pixel constants
   DevBuf lb_buf;                                   // L-BFGS state beyond the fit state
   DevBuf imgs_s, items_s, srcs_s, partials_s;      // the pixel-subsampled pack of a fit's early phase
+  int persistent = 2;                              // fits: persistent pixel-kernel blocks per CU (0: off)
+  int tr_chol = 1;                                 // fits: interior Newton step by Cholesky first
+  int n_cu = 0;                                    // compute units of the device
+  DevBuf qbuf;                                     // the fits' device work queue
   bool lfact_ready = false;
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
@@ -642,6 +646,9 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
   celeste_ctx* c = new (std::nothrow) celeste_ctx();
   if (!c) return fail(CELESTE_E_NOMEM, "context allocation failed");
   c->device = hip_device;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
+      c->n_cu < 1)
+    c->n_cu = 256;
   if (scratch_init(hip_device) != CELESTE_OK) {   // device address of the no-allocation scratch
     delete c;
     return CELESTE_E_DEVICE;
@@ -704,7 +711,7 @@ void celeste_ctx_destroy(celeste_ctx* c) {
                     &c->theta, &c->o_elbo, &c->o_grad, &c->o_hess, &c->flag, &c->st_buf, &c->ctr, &c->sur,
                     &c->tile_off, &c->tile_img, &c->img_field, &c->nbr_off, &c->tables2, &c->fsky,
                     &c->kept, &c->lr_in, &c->lr_cov, &c->lr_status, &c->lr_eval,
-                    &c->lfact, &c->lb_buf, &c->imgs_s, &c->items_s, &c->srcs_s, &c->partials_s};
+                    &c->lfact, &c->lb_buf, &c->imgs_s, &c->items_s, &c->srcs_s, &c->partials_s, &c->qbuf};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : {&c->h_imgs, &c->h_items, &c->h_srcs})
@@ -746,6 +753,14 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
     case CELESTE_OPT_VALUE_BLOCK:
       if (value != 128 && value != 256) return fail(CELESTE_E_INVALID, "value block must be 128 or 256");
       c->vblock = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_PERSISTENT:
+      if (value < 0 || value > 16) return fail(CELESTE_E_INVALID, "persistent blocks per compute unit must be 0..16");
+      c->persistent = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_TR_CHOLESKY:
+      if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "trust-region Cholesky path must be 0 or 1");
+      c->tr_chol = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_EXACT_ZERO:
       if (value != 0 && value != 1 && value != 127 && value != 160)
@@ -1126,8 +1141,21 @@ int check_opts(const celeste_fit_opts* o) {
 
 // Enqueues one trust-region iteration over all sources (each kernel skips sources
 // whose flag is clear).
+// Persistent-grid size of the pixel kernels: the chosen number of resident blocks per compute unit.
+int pgrid_items(const celeste_ctx* ctx) { return ctx->n_cu * ctx->persistent; }
+
+// The device work queue of a fit over P's work items (persistent mode).
+int fit_queue(celeste_ctx* ctx, const Packed& P, WorkQueue* q) {
+  CHK(ensure(ctx->qbuf, sizeof(int) * ((size_t)P.n_items + 64)));
+  int* b = as<int>(ctx->qbuf);
+  q->hdr = b;
+  q->items = b + 64;
+  q->srcs = as<SrcDev>(ctx->srcs);
+  return CELESTE_OK;
+}
+
 int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const FitParams& fp, hipStream_t st,
-                      PhaseTimer* T) {
+                      PhaseTimer* T, const WorkQueue* Q = nullptr) {
   const ImgDev* imgs = as<ImgDev>(ctx->imgs);
   const WorkItem* items = as<WorkItem>(ctx->items);
   const SrcDev* srcs = as<SrcDev>(ctx->srcs);
@@ -1135,10 +1163,11 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   double* parts = as<double>(ctx->partials);
   const double* ic = as<double>(ctx->img_const);
   T->mark(0, st);
+  if (Q) HIPCHK(launch_build_queue(*Q, P.n_src, F.need_full, st));
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
+                          ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, nullptr, Q, pgrid_items(ctx)));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -1361,7 +1390,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   }
   if (!theta_inout || (!res && !start_only)) return fail(CELESTE_E_INVALID, "theta_inout and results must not be NULL");
   const int S = P.n_src;
-  FitParams fp;
+  FitParams fp{};
   fp.max_iter = o->max_iter;
   fp.pred_rtol = o->pred_rtol;
   fp.curv_tol = o->curv_tol;
@@ -1370,6 +1399,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   fp.delta_min = o->delta_min;
   fp.eta = o->eta;
   fp.u_box = o->u_box;
+  fp.interior_chol = ctx->tr_chol;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
@@ -1389,8 +1419,11 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   CHK(T.init(ctx->profile != 0));
   const int poll = (batched && !T.on) ? std::max(1, o->poll_every) : 1;
   const bool graph = batched && ctx->use_graph && !T.on;
+  WorkQueue Q;
+  if (ctx->persistent) CHK(fit_queue(ctx, P, &Q));
+  const WorkQueue* Qp = ctx->persistent ? &Q : nullptr;
   CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
-               [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t); },
+               [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t, Qp); },
                [](celeste_stats& c) {
                  c.full_launches += 1;
                  c.value_launches += 1;
@@ -1420,7 +1453,7 @@ int run_fit_sampled(celeste_ctx* ctx, const celeste_batch* b, double* theta_inou
     if (keep_off[i + 1] - keep_off[i] != (b->images[i].h + 7) / 8)
       return fail(CELESTE_E_INVALID, "image %d: keep_off must give (h + 7) / 8 blocks", i);
   const int S = P.n_src;
-  FitParams fp;
+  FitParams fp{};
   fp.max_iter = o->max_iter;
   fp.pred_rtol = o->pred_rtol;
   fp.curv_tol = o->curv_tol;
@@ -1558,6 +1591,7 @@ int run_lbfgs(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, con
   fp.max_iter = o->max_iter;
   fp.delta0 = 1.0;
   fp.u_box = o->u_box;
+  fp.interior_chol = ctx->tr_chol;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));

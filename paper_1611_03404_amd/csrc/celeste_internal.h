@@ -90,6 +90,30 @@ inline int table_stride(int max_psf, int n_exp, int n_dev) {
   return (n + 15) & ~15;
 }
 
+// ---------------------------------------------------------------- device work queue
+// The work items of the sources whose flag is set, in source and item order, rebuilt on the
+// device before each phase of a fit iteration; persistent pixel kernels draw the list's entries
+// in turn from a shared counter, so their grids cover only the work of sources still being
+// fitted and uneven items balance across the blocks (the value+gradient+Hessian kernel; the
+// value kernel's items are too cheap to repay the draw).
+struct WorkQueue {
+  int* items;       // capacity n_items: work-item indices
+  int* hdr;         // [0]: entries, [1]: next entry to draw
+  const SrcDev* srcs;
+};
+hipError_t launch_build_queue(WorkQueue q, int n_src, const int* flag, hipStream_t st);
+// The calling block's next work item, or -1 once the list is drawn (the same value on every
+// thread; the leading barrier keeps the block's shared buffers of the previous item intact
+// until every thread has finished with them).
+__device__ __forceinline__ int queue_next(const WorkQueue& q) {
+  __shared__ int pos;
+  __syncthreads();
+  if (threadIdx.x == 0) pos = atomicAdd(q.hdr + 1, 1);
+  __syncthreads();
+  const int w = pos;
+  return w < q.hdr[0] ? q.items[w] : -1;
+}
+
 // ---------------------------------------------------------------- launch wrappers
 hipError_t launch_setup(const ImgDev* imgs, int n_img, const double* theta, const int* src_flag,
                         ProfDev prof, float* tables, int tstride, hipStream_t st);
@@ -105,10 +129,14 @@ hipError_t launch_check_const(const ImgDev* imgs, int n_img, const double* lfact
 // item's [row_begin, row_end) indexes this list instead of rows.
 // e_zero: a component whose log2 density is below e_zero on every lane of a tile is exactly 0
 // there and is skipped (see launch_exp2_probe).
+// queue: NULL = one block per work item (blocks of unflagged sources exit at once); else a
+// persistent grid of min(n_items, persistent_grid) blocks drawing the flagged sources' items from
+// the queue (src_flag is then not read).
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables,
                             int tstride, int n_exp, int n_dev, const int* src_flag, double* partials,
                             int block, int variant, int tw_log2, float e_zero, hipStream_t st,
-                            const int* kept = nullptr);
+                            const int* kept = nullptr, const WorkQueue* queue = nullptr,
+                            int persistent_grid = 0);
 // Value and z-gradient only: one partial of NGRAD = 1 + NZ doubles per work item (value, 11
 // gradient entries); arguments as launch_eval_full (variant: bit 1 only).
 constexpr int NGRAD = 1 + NZ;
@@ -186,6 +214,7 @@ struct FitParams {
   int max_iter;
   double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
   double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
+  int interior_chol;    // try the interior Newton step by Cholesky before the eigendecomposition
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);

@@ -30,6 +30,8 @@
 // pixels of a tile step (a contraction of depth 128) on the matrix cores: FP32 MFMA
 // 16x16x4 in two independent accumulator chains with operands staged through LDS, added
 // to FP64 every JFLUSH steps.
+#include <algorithm>
+
 #include "celeste_internal.h"
 
 namespace celeste {
@@ -241,17 +243,26 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
                                                      const float* __restrict__ tables, int tstride, int n_exp,
                                                      int n_dev, const int* __restrict__ src_flag,
                                                      int tw_log2, float e_zero, const int* __restrict__ kept,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials, WorkQueue q) {
   __shared__ double red[BLOCK / 64][80];
   // per wavefront: [A rows (dT, dU) | B columns (hT, hU)][T or U part][z index][pixel]
   __shared__ __align__(16) float jbuf[MF ? BLOCK / 64 : 1][2][2][MF ? NZ : 1][MF ? JP : 4];
   __shared__ __align__(16) float zrow[64];   // operand row of zeros for the padding rows 11..15
-  const WorkItem wi = items[blockIdx.x];
-  if (src_flag && !src_flag[wi.src]) return;
   if (MF) {
     if (threadIdx.x < 64) zrow[threadIdx.x] = 0.f;
     __syncthreads();
   }
+  // one work item per block, or (with a queue) the items of flagged sources drawn in turn
+  for (int pass = 0;; ++pass) {
+  int it = blockIdx.x;
+  if (q.items) {
+    it = queue_next(q);
+    if (it < 0) break;
+  } else if (pass) {
+    break;
+  }
+  const WorkItem wi = items[it];
+  if (!q.items && src_flag && !src_flag[wi.src]) break;
   const ImgDev& im = imgs[wi.img];
   const float* __restrict__ T = tables + (size_t)wi.img * tstride;
   const int w = im.w, pitch = im.pitch, npitch = im.nbr_pitch, npsf = im.n_psf;
@@ -574,8 +585,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < BLOCK / 64; ++k) s += red[k][threadIdx.x];
-    partials[(size_t)blockIdx.x * NACC + threadIdx.x] = s;
+    partials[(size_t)it * NACC + threadIdx.x] = s;
   }
+  }   // items
 }
 
 template <int BLOCK, int NE, int ND>
@@ -819,15 +831,17 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
 
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
-                            int tw_log2, float e_zero, hipStream_t st, const int* kept) {
+                            int tw_log2, float e_zero, hipStream_t st, const int* kept, const WorkQueue* queue,
+                            int persistent_grid) {
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
   const bool mf = (variant & 4) != 0 && unroll;
-  const dim3 g(n_items);
+  const WorkQueue q = queue ? *queue : WorkQueue{};
+  const dim3 g(queue ? std::min(n_items, persistent_grid) : n_items);
 #define CELESTE_LAUNCH_FULL(B, W, E, D, M) \
   hipLaunchKernelGGL((k_eval_full<B, W, E, D, M>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, tw_log2, e_zero, kept, partials)
+                     src_flag, tw_log2, e_zero, kept, partials, q)
   if (block == 128) {
     if (mf) {
       if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true);

@@ -5,7 +5,9 @@
 // through a cyclic Jacobi eigendecomposition of B = -H (parallel round-robin
 // ordering, 14 disjoint rotations per round held in LDS), followed by the secular
 // equation |(B + sI)^{-1} g| = Delta solved by safeguarded Newton on 1/|p(s)|
-// (More-Sorensen), including the hard case.  A separate kernel applies the
+// (More-Sorensen), including the hard case.  Where B is positive definite and its
+// Newton step lies inside the region, one Cholesky factorisation gives that step
+// instead.  A separate kernel applies the
 // ratio test and updates the radius, one thread per source.
 #include <math.h>
 
@@ -137,6 +139,68 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   }
   if (t < NPAD) g[t] = t < NP ? d1s[t] * gn[t] : 0.0;
   __syncthreads();
+  auto wsum = [](double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return __shfl(x, 0);
+  };
+  const double delta = st.delta[s];
+  // psi step; predicted gain; whether B is positive semi-definite to the curvature tolerance
+  __shared__ double pst[NPAD], y[NPAD];
+  double pred = 0.0;
+  bool curv_ok = true;
+
+  // ---- interior Newton step.  Where B is positive definite and the Newton step B^{-1} g lies
+  // inside the region, that step is the exact solution of the subproblem (zero multiplier in the
+  // optimality conditions of Nocedal & Wright, Theorem 4.1), so one Cholesky factorisation of B
+  // (right-looking in LDS, one column per step, the forward substitution carried along) replaces
+  // the eigendecomposition.  B indefinite or nearly singular (a pivot at most 1e-12 of the
+  // largest diagonal entry), or a step outside the region, takes the eigendecomposition below.
+  bool interior = false;
+  if (fp.interior_chol) {
+    for (int k = t; k < NP * NP; k += 64) W[k / NP][k % NP] = B[k / NP][k % NP];
+    if (t < NPAD) y[t] = g[t];
+    double dmax = t < NP ? B[t][t] : -INFINITY;
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
+    dmax = __shfl(dmax, 0);
+    __syncthreads();
+    bool ok = dmax > 0.0;
+    for (int k = 0; k < NP && ok; ++k) {
+      const double piv = W[k][k];   // the same value on every lane: the decision is uniform
+      if (!(piv > 1e-12 * dmax)) {
+        ok = false;
+        break;
+      }
+      const double lkk = sqrt(piv);
+      // (W[k][k] is read above by every lane and written only after the barrier)
+      if (t > k && t < NP) W[t][k] /= lkk;
+      if (t == k) y[k] /= lkk;
+      __syncthreads();
+      const int m = NP - 1 - k;
+      for (int e = t; e < m * m; e += 64) {
+        const int i = k + 1 + e / m, j = k + 1 + e % m;
+        if (j <= i) W[i][j] -= W[i][k] * W[j][k];
+      }
+      if (t > k && t < NP) y[t] -= W[t][k] * y[k];
+      if (t == k) W[k][k] = lkk;
+      __syncthreads();
+    }
+    if (ok) {
+      // back substitution L' p = y, one unknown per step
+      for (int k = NP - 1; k >= 0; --k) {
+        const double yk = y[k] / W[k][k];
+        if (t == k) pst[k] = yk;
+        if (t < k) y[t] -= W[k][t] * yk;
+        __syncthreads();
+      }
+      const double pi = t < NP ? pst[t] : 0.0;
+      if (wsum(pi * pi) <= delta * delta) {
+        interior = true;
+        pred = 0.5 * wsum(t < NP ? g[t] * pi : 0.0);
+      }
+    }
+  }
+
+  if (!interior) {
   // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
   // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model
   for (int k = t; k < NPAD * NPAD; k += 64) {
@@ -256,10 +320,6 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   {
     const bool on = t < NP;
     const double li = on ? lam[t] : 0.0, gi = on ? gt[t] : 0.0;
-    auto wsum = [](double x) {
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-      return __shfl(x, 0);
-    };
     auto wmin = [](double x) {
       for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
       return __shfl(x, 0);
@@ -268,7 +328,6 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
       for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
       return __shfl(x, 0);
     };
-    const double delta = st.delta[s];
     const double lam0 = wmin(on ? li : INFINITY);
     // first index holding the smallest eigenvalue
     const unsigned long long at_min = __ballot(on && li == lam0);
@@ -316,31 +375,41 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
     }
     if (!hard) pti = on ? gi / (li + sv) : 0.0;
     if (on) pt[t] = pti;
-    const double pred = wsum(on ? gi * pti - 0.5 * li * pti * pti : 0.0);
-    if (t == 0) {
-      // convergence and iteration cap; on the subsampled objective, the switch to the full one
-      const double f = st.f[s];
-      int d = 0;
-      if (st.samp[s]) {
-        if (pred <= fp.switch_rtol * fmax(1.0, fabs(f))) {
-          st.samp[s] = 0;
-          st.sw[s] = 1;
-          d = 2;
-        } else if (st.iter[s] >= fp.max_iter) {
-          st.status[s] = CELESTE_MAX_ITER;
-          d = 1;
-        }
-      } else if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && lam0 >= -fp.curv_tol * scale) {
-        st.status[s] = CELESTE_CONVERGED;
-        d = 1;
+    pred = wsum(on ? gi * pti - 0.5 * li * pti * pti : 0.0);
+    curv_ok = lam0 >= -fp.curv_tol * scale;
+  }
+  __syncthreads();
+  // the step back in psi coordinates
+  if (t < NP) {
+    double a = 0.0;
+    for (int i = 0; i < NP; ++i) a += V[t][i] * pt[i];
+    pst[t] = a;
+  }
+  }   // eigendecomposition
+
+  if (t == 0) {
+    // convergence and iteration cap; on the subsampled objective, the switch to the full one
+    const double f = st.f[s];
+    int d = 0;
+    if (st.samp[s]) {
+      if (pred <= fp.switch_rtol * fmax(1.0, fabs(f))) {
+        st.samp[s] = 0;
+        st.sw[s] = 1;
+        d = 2;
       } else if (st.iter[s] >= fp.max_iter) {
         st.status[s] = CELESTE_MAX_ITER;
         d = 1;
       }
-      st.pred[s] = pred;
-      if (d == 1) st.active[s] = 0;
-      done = d;
+    } else if (pred <= fp.pred_rtol * fmax(1.0, fabs(f)) && curv_ok) {
+      st.status[s] = CELESTE_CONVERGED;
+      d = 1;
+    } else if (st.iter[s] >= fp.max_iter) {
+      st.status[s] = CELESTE_MAX_ITER;
+      d = 1;
     }
+    st.pred[s] = pred;
+    if (d == 1) st.active[s] = 0;
+    done = d;
   }
   __syncthreads();
   if (done == 2) {
@@ -355,8 +424,7 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   double* tht = st.theta_trial + (size_t)s * NP;
   double pn2 = 0.0;
   if (t < NP) {
-    double a = 0.0;
-    for (int i = 0; i < NP; ++i) a += V[t][i] * pt[i];
+    const double a = pst[t];
     pp[t] = a;
     double d1, d2;
     tht[t] = to_theta1(ps[t] + a, box_of(t, u0, fp.u_box), &d1, &d2);

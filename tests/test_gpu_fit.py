@@ -108,6 +108,81 @@ def test_batch_equals_single_and_graph_equals_eager(cb, ctx):
         assert res_s["iters"] == res_b["iters"][s]
 
 
+def test_persistent_work_queue_equals_one_block_per_item(cb, ctx):
+    """Fits whose pixel kernels draw from the device list of the work items still being fitted
+    (persistent grids of 1 and 4 blocks per compute unit) give every bit of the one-block-per-item
+    fits: a ragged config-1 subset and config-2 sources, graph replay and eager, chunks small
+    enough that many sources span several work items."""
+    c1 = synth.make_config(1, n_sources=40)
+    side = c1.truth["side"]
+    sets = [c1.subset(list(np.argsort(side)[:5]) + list(np.argsort(side)[-5:])),
+            synth.make_config(2, n_sources=30).subset(list(range(0, 30, 3)))]
+    try:
+        for sb in sets:
+            b = cb.Batch.from_synth(sb)
+            th0 = np.zeros((sb.n_sources, 27))
+            th0[:, 0:2] = sb.u_cat
+            o = cb.default_opts(init_mode=cb.INIT_PLAIN)
+            for chunk in (4096, 1024):
+                ctx.set_option(cb.OPT_CHUNK_PX, chunk)
+                ctx.set_option(cb.OPT_PERSISTENT, 0)
+                th_a, ra = ctx.batch_fit(b, th0, o)
+                ctx.set_option(cb.OPT_PERSISTENT, 1)
+                th_p, rp = ctx.batch_fit(b, th0, o)
+                ctx.set_option(cb.OPT_PERSISTENT, 4)
+                th_q, rq = ctx.batch_fit(b, th0, o)
+                ctx.set_option(cb.OPT_USE_GRAPH, 0)
+                th_e, re_ = ctx.batch_fit(b, th0, o)
+                ctx.set_option(cb.OPT_USE_GRAPH, 1)
+                for th_x, rx in ((th_p, rp), (th_q, rq), (th_e, re_)):
+                    assert np.array_equal(th_x, th_a) and np.array_equal(rx["elbo"], ra["elbo"])
+                    assert np.array_equal(rx["iters"], ra["iters"]) and np.array_equal(rx["status"], ra["status"])
+            _say("persistent", sb.name, "iterations", ra["iters"].tolist())
+    finally:
+        ctx.set_option(cb.OPT_PERSISTENT, 2)   # the library's default
+        ctx.set_option(cb.OPT_USE_GRAPH, 1)
+        ctx.set_option(cb.OPT_CHUNK_PX, 4096)
+    for bad in (-1, 17):
+        with pytest.raises(cb.CelesteError):
+            ctx.set_option(cb.OPT_PERSISTENT, bad)
+
+
+def test_interior_cholesky_step_matches_eigendecomposition(cb, ctx):
+    """The interior Newton step by Cholesky (the subproblem's exact solution where -H is positive
+    definite and the step lies inside the region) against the eigendecomposition path on every
+    iteration: the same fits up to rounding (ELBO within 1e-9 relative, parameters within 1e-5 of
+    their scale, every source converged both ways, iteration counts within one) on a ragged
+    config-1 subset and config-2 sources, graph replay, and eager with the option cleared."""
+    c1 = synth.make_config(1, n_sources=40)
+    side = c1.truth["side"]
+    sets = [c1.subset(list(np.argsort(side)[:6]) + list(np.argsort(side)[-6:])),
+            synth.make_config(2, n_sources=40).subset(list(range(0, 40, 4)))]
+    try:
+        for sb in sets:
+            b = cb.Batch.from_synth(sb)
+            th0 = np.zeros((sb.n_sources, 27))
+            th0[:, 0:2] = sb.u_cat
+            o = cb.default_opts(init_mode=cb.INIT_PLAIN)
+            ctx.set_option(cb.OPT_TR_CHOLESKY, 1)
+            th_c, rc = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_TR_CHOLESKY, 0)
+            th_e, re_ = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_USE_GRAPH, 0)
+            th_e2, re2 = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_USE_GRAPH, 1)
+            _say(sb.name, "iterations cholesky", rc["iters"].tolist(), "eigen", re_["iters"].tolist())
+            assert np.array_equal(th_e2, th_e) and np.array_equal(re2["iters"], re_["iters"])
+            assert np.all(rc["status"] == cb.CONVERGED) and np.all(re_["status"] == cb.CONVERGED)
+            assert np.all(np.abs(rc["elbo"] - re_["elbo"]) <= 1e-9 * np.abs(re_["elbo"]))
+            assert np.all(np.abs(rc["iters"] - re_["iters"]) <= 1)
+            assert np.max(np.abs(th_c - th_e) / np.maximum(1.0, np.abs(th_e))) <= 1e-5
+    finally:
+        ctx.set_option(cb.OPT_TR_CHOLESKY, 1)
+        ctx.set_option(cb.OPT_USE_GRAPH, 1)
+    with pytest.raises(cb.CelesteError):
+        ctx.set_option(cb.OPT_TR_CHOLESKY, 2)
+
+
 def test_status_paths_forced_from_host(cb, ctx):
     sb = synth.make_config(0)
     b = cb.Batch.from_synth(sb)
