@@ -58,6 +58,13 @@ def pmc_traffic(px_per_launch):
                                     "source": "profiles/pmc_eval_full_batched_uneven_20k.md"}
 
 
+def dtype_str(args, network=True):
+    """The arithmetic types of the timed path (the pixel sums' precision follows --fp64-sums)."""
+    sums = ("f64 pixel sums from the first addition" if args.fp64_sums == 1 else
+            "f64 pixel sums after f32 lane sums of up to 16 pixels and an f32 wavefront butterfly")
+    return "f32 pixel arithmetic, " + sums + ", f64 trust-region solve" + (", bf16 network" if network else "")
+
+
 def flop_full_per_px(K, E, D):
     """Algorithmic FLOPs of one value+gradient+Hessian pixel evaluation (add/mul 1, FMA 2,
     exp/log/rcp 1, FP64 accumulate 1), counted from the formulation: star components
@@ -444,6 +451,9 @@ def main():
     ap.add_argument("--tr-cholesky", type=int, choices=(0, 1), default=None,
                     help="trust-region subproblem: interior Newton step by Cholesky first (1) or always the "
                          "eigendecomposition (0); default: the library's")
+    ap.add_argument("--fp64-sums", type=int, choices=(0, 1), default=None,
+                    help="value+gradient+Hessian kernel: every pixel term summed in FP64 (1) or FP32 lane sums "
+                         "over up to 16 tile steps before FP64 (0); default: the library's")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: read the launch shapes from it when it has an entry for this "
                          "device and workload, else time them and add one (runs that must share a launch "
@@ -473,6 +483,8 @@ def main():
         ctx.set_option(cb.OPT_PERSISTENT, args.persistent)
     if args.tr_cholesky is not None:
         ctx.set_option(cb.OPT_TR_CHOLESKY, args.tr_cholesky)
+    if args.fp64_sums is not None:
+        ctx.set_option(cb.OPT_FP64_SUMS, args.fp64_sums)
     if args.probe:
         return probe(args, ctx, log)
     if args.workload == "lbfgs":
@@ -608,7 +620,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve, bf16 network",
+        "dtype": dtype_str(args, network=True),
         "data": "synthetic",
         "config": {"workload": "batched uneven sources: 20,000 sources, side log-uniform 15-121 px, "
                                "5 bands x 1-10 epochs, per-epoch PSF and sky" if args.sources is None else
@@ -623,6 +635,7 @@ def main():
         "iterations_hist": np.bincount(iters, minlength=52).tolist(),
         "status": status_counts,
         "phase_ms_per_step": {k[3:]: v for k, v in H["prof"].items() if k.startswith("ms_")},
+        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "eigendecomposition": st["tr_eigen"]},
         "phase_source": "the profiled step (eager launches with HIP events), one per start after the timed steps",
         "starts": {name: summary(r) for name, r in runs.items()},
         "autotune": tune,
@@ -733,7 +746,7 @@ def sampled_bench(args, ctx, log):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_eval"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 pixel arithmetic, f64 accumulation",
+        "dtype": dtype_str(args, network=False),
         "data": "synthetic",
         "config": {"workload": f"batched uneven sources ({sb.n_sources} sources, {sb.n_pixels} px) at the plain "
                                f"start, 8-row blocks kept with probability {args.keep_prob}",
@@ -976,16 +989,27 @@ def field_bench(args, ctx, net, sur_info, log):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.stats()
-    f_full = flop_full_per_px(3, len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0]))
-    full_s = st["ms_full"] / 1e3
-    achieved = f_full * st["full_px"] / full_s / 1e12 if full_s > 0 else 0.0
+    # one more sweep in profile mode (eager launches, HIP events around every kernel phase): the
+    # roofline's per-launch durations and the phase split of the fits
+    ctx.set_option(cb.OPT_PROFILE, 1)
+    ctx.stats(reset=True)
+    tp = time.perf_counter()
+    field.bca(ctx, sb, meta, sweeps=1, start_mode=mode, schedule=args.schedule)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - tp
+    st_p = ctx.stats()
+    ctx.set_option(cb.OPT_PROFILE, 0)
+    log(f"profiled sweep: {wall_p:.2f} s")
+    f_full = flop_full_per_px_algorithmic(3, len(sb.profiles["exp"][0]), len(sb.profiles["dev"][0]))
+    full_s = st_p["ms_full"] / 1e3
+    achieved = f_full * st_p["full_px"] / full_s / 1e12 if full_s > 0 else 0.0
     out = {
         "metric": "field-level sources/s (crowded field, block coordinate ascent); pixel-evals/s",
         "value": sb.n_sources * args.steps / wall,
         "unit": "sources/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 pixel arithmetic, f64 accumulation and trust-region solve, bf16 network", "data": "synthetic",
+        "dtype": dtype_str(args, network=True), "data": "synthetic",
         "config": {"workload": f"crowded field {sf.W}x{sf.H} px, {sf.n_fields} images (5 bands x 4 epochs), "
                                f"{sb.n_sources} sources, "
                                + (f"{args.sweeps} " if args.until_rtol is None else
@@ -998,11 +1022,16 @@ def field_bench(args, ctx, net, sur_info, log):
         "autotune": tune,
         "sweeps": info["history"], "timings_s_per_step": {k: v / args.steps for k, v in info["timings"].items()},
         "pixel_evals_per_s": st["full_px"] / wall,
-        "kernel_pixel_evals_per_s": st["full_px"] / full_s if full_s > 0 else None,
+        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "eigendecomposition": st["tr_eigen"]},
+        "profiled_sweep": {"s": wall_p, "phase_ms": {k[3:]: v for k, v in st_p.items() if k.startswith("ms_")},
+                           "kernel_pixel_evals_per_s": st_p["full_px"] / full_s if full_s > 0 else None},
         "roofline": {"kernel": "k_eval_full (value+gradient+Hessian pixel kernel)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
-                     "avg_launch_ms": st["ms_full"] / max(1, st["full_launches"]), "launches": st["full_launches"],
+                     "flop_per_pixel_eval_algorithmic": f_full,
+                     "avg_launch_ms": st_p["ms_full"] / max(1, st_p["full_launches"]),
+                     "launches": st_p["full_launches"],
+                     "over": "the value+gradient+Hessian launches of one profiled colour sweep after the timed steps",
                      "traffic": None},   # counters were taken on the batched workload only
     }
     if not args.no_cpu_baseline:

@@ -106,11 +106,17 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    them in turn (grids do not shrink otherwise: blocks of finished
                                    sources exit at once; default 2); 0 = one block per work item.
                                    Results are bitwise the same */
-  CELESTE_OPT_TR_CHOLESKY = 11  /* trust-region subproblem (section III-B): 1 = where -H is positive
+  CELESTE_OPT_TR_CHOLESKY = 11, /* trust-region subproblem (section III-B): 1 = where -H is positive
                                    definite and its Newton step lies inside the region, that step is
                                    taken from one Cholesky factorisation (it solves the subproblem
                                    exactly); otherwise, and always with 0, the eigendecomposition and
                                    secular equation (default 1).  The two differ by rounding */
+  CELESTE_OPT_FP64_SUMS = 12    /* value+gradient+Hessian kernel: 1 = each tile step's FP32 gradient
+                                   and Hessian pixel terms are summed across the wavefront in FP64,
+                                   so every pixel sum is FP64 from the first addition (about 10%
+                                   slower); 0 = FP32 sums per lane over up to 16 tile steps and an
+                                   FP32 wavefront butterfly before FP64 (default).  The ELBO value is
+                                   summed in FP64 per lane either way */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -135,6 +141,9 @@ typedef struct celeste_stats {
    * and line-search kernels (the milliseconds under CELESTE_OPT_PROFILE only) */
   int64_t grad_px, grad_launches;
   double ms_grad, ms_reduce_grad, ms_lbfgs;
+  /* trust-region subproblems solved by the interior Newton step (one Cholesky factorisation)
+   * and by the eigendecomposition and secular equation (CELESTE_OPT_TR_CHOLESKY) */
+  int64_t tr_interior, tr_eigen;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

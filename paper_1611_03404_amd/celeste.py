@@ -27,6 +27,7 @@ INIT_AS_GIVEN, INIT_PLAIN, INIT_SURROGATE = 0, 1, 2
 FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
 OPT_TILE_W, OPT_VALUE_BLOCK, OPT_VALUE_TILE_W, OPT_EXACT_ZERO, OPT_PERSISTENT, OPT_TR_CHOLESKY = 6, 7, 8, 9, 10, 11
+OPT_FP64_SUMS = 12
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("nbr_pitch", "<i4"),
@@ -67,7 +68,8 @@ class Stats(ctypes.Structure):
                 ("ms_host_pack", ctypes.c_double), ("ms_prepare", ctypes.c_double), ("ms_start", ctypes.c_double),
                 ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double), ("lr_launches", ctypes.c_int64),
                 ("ms_lr", ctypes.c_double), ("grad_px", ctypes.c_int64), ("grad_launches", ctypes.c_int64),
-                ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double)]
+                ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double),
+                ("tr_interior", ctypes.c_int64), ("tr_eigen", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):

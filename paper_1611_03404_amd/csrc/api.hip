@@ -78,9 +78,10 @@ struct celeste_ctx {
   int vtile_log2 = 3;    // log2 tile width of the value kernel
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
-  DevBuf ctr;      // device pixel-evaluation counters [full, value]
+  DevBuf ctr;      // device counters: pixel evaluations [full, value, grad], subproblem paths [interior, eigen]
   int profile = 0;
   celeste_stats stats{};
+
   celeste_net* net = nullptr;   // surrogate network (not owned)
   DevBuf sur;                   // surrogate predictions (float, S x 27)
   DevBuf tile_off, tile_img, img_field, nbr_off;   // crowded-field index buffers
@@ -92,11 +93,17 @@ struct celeste_ctx {
   DevBuf imgs_s, items_s, srcs_s, partials_s;      // the pixel-subsampled pack of a fit's early phase
   int persistent = 2;                              // fits: persistent pixel-kernel blocks per CU (0: off)
   int tr_chol = 1;                                 // fits: interior Newton step by Cholesky first
+  int fp64_sums = 0;                               // value+gradient+Hessian kernel: FP64 sums per tile step
   int n_cu = 0;                                    // compute units of the device
   DevBuf qbuf;                                     // the fits' device work queue
   bool lfact_ready = false;
   DevBuf h_imgs, h_items, h_srcs;                  // pinned host staging of the packed metadata
 };
+
+namespace {
+// The value+gradient+Hessian kernel's variant with the context's summation precision (bit 3).
+int full_variant(const celeste_ctx* c) { return c->variant | (c->fp64_sums ? 8 : 0); }
+}  // namespace
 
 namespace celeste {
 int ctx_device(const celeste_ctx* c) { return c->device; }
@@ -657,8 +664,8 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
-  if (ensure(c->ctr, 3 * sizeof(unsigned long long)) != CELESTE_OK ||
-      hipMemset(c->ctr.p, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
+  if (ensure(c->ctr, 5 * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, 5 * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipStreamDestroy(c->stream);
     if (c->ctr.p) (void)hipFree(c->ctr.p);
     delete c;
@@ -690,11 +697,13 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
 int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
   HIPCHK(hipSetDevice(c->device));
-  unsigned long long h[3] = {0, 0, 0};
+  unsigned long long h[5] = {0, 0, 0, 0, 0};
   HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
   c->stats.full_px = (int64_t)h[0];
   c->stats.value_px = (int64_t)h[1];
   c->stats.grad_px = (int64_t)h[2];
+  c->stats.tr_interior = (int64_t)h[3];
+  c->stats.tr_eigen = (int64_t)h[4];
   *out = c->stats;
   if (reset) {
     HIPCHK(hipMemset(c->ctr.p, 0, sizeof(h)));
@@ -757,6 +766,10 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
     case CELESTE_OPT_PERSISTENT:
       if (value < 0 || value > 16) return fail(CELESTE_E_INVALID, "persistent blocks per compute unit must be 0..16");
       c->persistent = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_FP64_SUMS:
+      if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "FP64 sums must be 0 or 1");
+      c->fp64_sums = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_TR_CHOLESKY:
       if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "trust-region Cholesky path must be 0 or 1");
@@ -955,14 +968,14 @@ int eval_impl(celeste_ctx* ctx, const celeste_batch* b, const double* theta, dou
   T.mark(1, st);
   if (grad && hess) {
     HIPCHK(launch_eval_full(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
-                            B.partials, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
+                            B.partials, ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_full(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
                               d_grad, d_hess, ctr_full(ctx), st, px_weight));
     ctx->stats.full_launches += 1;
   } else if (grad) {
     HIPCHK(launch_eval_grad(B.items, P.n_items, B.imgs, B.tables, P.tstride, P.prof.n_exp, P.prof.n_dev, nullptr,
-                            B.partials, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
+                            B.partials, ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, kept));
     T.mark(2, st);
     HIPCHK(launch_reduce_grad(B.srcs, P.n_src, B.imgs, B.partials, B.img_const, th_dev, P.prior, nullptr, d_elbo,
                               d_grad, ctr_grad(ctx), st, px_weight));
@@ -1167,7 +1180,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, nullptr, Q, pgrid_items(ctx)));
+                          ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, nullptr, Q, pgrid_items(ctx)));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -1400,6 +1413,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   fp.eta = o->eta;
   fp.u_box = o->u_box;
   fp.interior_chol = ctx->tr_chol;
+  fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
@@ -1515,9 +1529,9 @@ int run_fit_sampled(celeste_ctx* ctx, const celeste_batch* b, double* theta_inou
     HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
     t->mark(1, st);
     HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fa, parts,
-                            ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
+                            ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st));
     HIPCHK(launch_eval_full(items_s, Ps.n_items, imgs_s, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.fb, parts_s,
-                            ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st, kept));
+                            ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, kept));
     t->mark(2, st);
     HIPCHK(launch_reduce_full(srcs, S, imgs, parts, ic, F.theta, P.prior, F.fa, F.f_full, F.g, F.H, ctr_full(ctx), st));
     HIPCHK(launch_reduce_full(srcs_s, S, imgs_s, parts_s, ic, F.theta, P.prior, F.fb, F.f_full, F.g, F.H,
@@ -1592,6 +1606,7 @@ int run_lbfgs(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, con
   fp.delta0 = 1.0;
   fp.u_box = o->u_box;
   fp.interior_chol = ctx->tr_chol;
+  fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
@@ -1642,7 +1657,7 @@ int run_lbfgs(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, con
     HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
     t->mark(1, st);
     HIPCHK(launch_eval_grad(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full,
-                            parts, ctx->block, ctx->variant, ctx->tile_log2, ctx->e_zero, st));
+                            parts, ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st));
     t->mark(2, st);
     HIPCHK(launch_reduce_grad(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g,
                               ctr_grad(ctx), st));
@@ -2248,8 +2263,8 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
           double ms = 0.0;
           rc = time_min(st, 3, [&]() {
             return launch_eval_full(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
-                                    P.prof.n_dev, nullptr, as<double>(ctx->partials), block, variant, tl,
-                                    ctx->e_zero, st);
+                                    P.prof.n_dev, nullptr, as<double>(ctx->partials), block,
+                                    variant | (ctx->fp64_sums ? 8 : 0), tl, ctx->e_zero, st);
           }, &ms);
           r.n_candidates += 1;
           double& unit_best = (variant & 4) ? r.matrix_full_ms : r.vector_full_ms;
@@ -2290,8 +2305,8 @@ int autotune(celeste_ctx* ctx, const celeste_batch* b, const double* theta, int6
       float* tables = as<float>(ctx->tables);
       CHK(time_min(st, 9, [&]() {
         return launch_eval_full(as<WorkItem>(ctx->items), P.n_items, di, tables, P.tstride, P.prof.n_exp,
-                                P.prof.n_dev, nullptr, as<double>(ctx->partials), c.block, c.variant, c.tl,
-                                ctx->e_zero, st);
+                                P.prof.n_dev, nullptr, as<double>(ctx->partials), c.block,
+                                c.variant | (ctx->fp64_sums ? 8 : 0), c.tl, ctx->e_zero, st);
       }, &c.ms));
       if (c.is_default()) r.default_full_ms = c.ms;
     }

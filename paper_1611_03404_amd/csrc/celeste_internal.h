@@ -215,6 +215,7 @@ struct FitParams {
   double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
   double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
   int interior_chol;    // try the interior Newton step by Cholesky before the eigendecomposition
+  unsigned long long* tr_ctr;   // subproblems solved [0] by the interior Cholesky step, [1] otherwise
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);

@@ -220,6 +220,38 @@ __device__ __forceinline__ int quad_base(int lane) {
   return ((lane >> 5) & 1) * 40 + ((lane >> 4) & 1) * 20 + ((lane >> 3) & 1) * 10 + ((lane >> 2) & 1) * 5;
 }
 
+template <int N>
+__device__ __forceinline__ void halved(const double* v, double* o, int mask, bool up) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double send = up ? v[i] : v[i + N / 2];
+    const double keep = up ? v[i + N / 2] : v[i];
+    o[i] = keep + __shfl_xor(send, mask);
+  }
+}
+
+// As wave_sum80f with every addition in FP64: the 80 FP32 values of each lane enter FP64
+// before the first exchange.
+__device__ __forceinline__ void wave_sum80d(const float* v, double* out5) {
+  const int lane = threadIdx.x & 63;
+  const bool up = (lane & 32) != 0;
+  double t40[40], t20[20], t10[10];
+#pragma unroll
+  for (int i = 0; i < 40; ++i) {
+    const float send = up ? v[i] : v[i + 40];
+    const float keep = up ? v[i + 40] : v[i];
+    t40[i] = (double)keep + (double)__shfl_xor(send, 32);
+  }
+  halved<40>(t40, t20, 16, lane & 16);
+  halved<20>(t20, t10, 8, lane & 8);
+  halved<10>(t10, out5, 4, lane & 4);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    out5[i] += __shfl_xor(out5[i], 2);
+    out5[i] += __shfl_xor(out5[i], 1);
+  }
+}
+
 __device__ __forceinline__ void wave_sum80f(const float* v, float* out5) {
   const int lane = threadIdx.x & 63;
   float t40[40], t20[20], t10[10];
@@ -237,7 +269,9 @@ __device__ __forceinline__ void wave_sum80f(const float* v, float* out5) {
 // NE, ND > 0: compile-time component counts (fully unrolled loops); 0: runtime counts.
 // MINW: minimum resident waves per SIMD the register allocation must allow.
 // MF: the J^T W J part on the matrix cores (true) or in the per-lane FP32 sums (false).
-template <int BLOCK, int MINW, int NE, int ND, bool MF>
+// S64: every tile step's gradient and Hessian terms are summed across the wavefront in FP64
+// (no FP32 sums across pixels; MF must be false).
+template <int BLOCK, int MINW, int NE, int ND, bool MF, bool S64>
 __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __restrict__ items,
                                                      const ImgDev* __restrict__ imgs,
                                                      const float* __restrict__ tables, int tstride, int n_exp,
@@ -296,10 +330,17 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
     C1 = floatx4{0.f, 0.f, 0.f, 0.f};
   };
   auto flush = [&]() {
-    float part[5];
-    wave_sum80f(accf, part);
+    if constexpr (S64) {
+      double part[5];
+      wave_sum80d(accf, part);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) acc5[i] += (double)part[i];
+      for (int i = 0; i < 5; ++i) acc5[i] += part[i];
+    } else {
+      float part[5];
+      wave_sum80f(accf, part);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) acc5[i] += (double)part[i];
+    }
 #pragma unroll
     for (int i = 0; i < 80; ++i) accf[i] = 0.f;
   };
@@ -548,17 +589,23 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }   // hit
-    // every tile step counts, so the flush points (and every bit of the result) do not depend on
-    // which exactly-zero work was skipped
-    ++since;
-    if (MF && (since % JFLUSH) == 0) flushJ();
-    if (since == FLUSH) {
-      flush();
-      since = 0;
+    if constexpr (S64) {
+      // a skipped tile step's terms are exactly 0, and adding them would leave the FP64 sums as
+      // they are
+      if (hit) flush();
+    } else {
+      // every tile step counts, so the flush points (and every bit of the result) do not depend
+      // on which exactly-zero work was skipped
+      ++since;
+      if (MF && (since % JFLUSH) == 0) flushJ();
+      if (since == FLUSH) {
+        flush();
+        since = 0;
+      }
     }
   }
   if (MF && (since % JFLUSH)) flushJ();
-  if (since > 0) flush();
+  if (!S64 && since > 0) flush();
 
   // ---- block reduction (deterministic order) and one FP64 partial per work item
 #pragma unroll
@@ -836,27 +883,42 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
   if (n_items <= 0) return hipSuccess;
   const bool occ2 = (variant & 1) != 0;
   const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
-  const bool mf = (variant & 4) != 0 && unroll;
+  const bool s64 = (variant & 8) != 0;
+  const bool mf = (variant & 4) != 0 && unroll && !s64;
   const WorkQueue q = queue ? *queue : WorkQueue{};
   const dim3 g(queue ? std::min(n_items, persistent_grid) : n_items);
-#define CELESTE_LAUNCH_FULL(B, W, E, D, M) \
-  hipLaunchKernelGGL((k_eval_full<B, W, E, D, M>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, n_dev, \
-                     src_flag, tw_log2, e_zero, kept, partials, q)
-  if (block == 128) {
-    if (mf) {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true);
-    } else if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false);
+#define CELESTE_LAUNCH_FULL(B, W, E, D, M, S) \
+  hipLaunchKernelGGL((k_eval_full<B, W, E, D, M, S>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, \
+                     n_dev, src_flag, tw_log2, e_zero, kept, partials, q)
+  if (s64) {
+    if (block == 128) {
+      if (unroll) {
+        if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false, true);
+      } else {
+        if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false, true); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false, true);
+      }
     } else {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false);
+      if (unroll) {
+        if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false, true); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false, true);
+      } else {
+        if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false, true); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false, true);
+      }
+    }
+  } else if (block == 128) {
+    if (mf) {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true, false);
+    } else if (unroll) {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false, false);
+    } else {
+      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false, false); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false, false);
     }
   } else {
     if (mf) {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, true); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, true);
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, true, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, true, false);
     } else if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false);
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false, false);
     } else {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false);
+      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false, false); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false, false);
     }
   }
 #undef CELESTE_LAUNCH_FULL

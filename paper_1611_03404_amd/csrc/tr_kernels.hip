@@ -388,6 +388,7 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   }   // eigendecomposition
 
   if (t == 0) {
+    if (fp.tr_ctr) atomicAdd(fp.tr_ctr + (interior ? 0 : 1), 1ull);
     // convergence and iteration cap; on the subsampled objective, the switch to the full one
     const double f = st.f[s];
     int d = 0;

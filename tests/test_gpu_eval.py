@@ -300,6 +300,56 @@ def test_full_size_config2_sampled(cb, ctx):
         assert_derivs_close(g[s], H[s], g0, H0, what=tag)
 
 
+def test_fp64_sums(cb, ctx, cfg0):
+    """CELESTE_OPT_FP64_SUMS: every pixel's FP32 gradient and Hessian terms summed in FP64 from the
+    first addition.  Against the oracle to the same tolerances on config 0 (three points), a ragged
+    config-1 subset with neighbour arrays and small work items, and config-2 sources; and, since
+    only the FP64 summation order then depends on the launch shape, two different launch shapes
+    (block 256 / tile 8 / vector variant, block 128 / tile 32 / unrolled variant) agree to 1e-11 of
+    each array's largest entry (the default FP32 lane sums differ by about 1e-6 there)."""
+    c1 = synth.make_config(1, n_sources=40)
+    side = c1.truth["side"]
+    c1 = c1.subset(list(np.argsort(side)[:3]) + list(np.argsort(side)[-3:]))
+    rng = np.random.default_rng(23)
+    nb = (rng.uniform(0, 30, c1.n_pixels).astype(np.float32), rng.uniform(0, 8, c1.n_pixels).astype(np.float32))
+    c2 = synth.make_config(2, n_sources=60).subset([3, 29, 58])
+    shapes = ((256, 8, 3, 4096), (128, 32, 2, 1024))
+
+    def spread(a, b):
+        return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+    try:
+        ctx.set_option(cb.OPT_FP64_SUMS, 1)
+        _check_batch(cb, ctx, cfg0, _points(cfg0, 4), what="fp64 sums cfg0")
+        ctx.set_option(cb.OPT_CHUNK_PX, 512)
+        _check_batch(cb, ctx, c1, [perturb_theta(c1.theta_truth, 5)], nbr=nb, what="fp64 sums cfg1")
+        ctx.set_option(cb.OPT_CHUNK_PX, 4096)
+        _check_batch(cb, ctx, c2, [perturb_theta(c2.theta_truth, 6)], what="fp64 sums cfg2")
+        for sb, th, n_ in ((c1, perturb_theta(c1.theta_truth, 5), nb), (c2, perturb_theta(c2.theta_truth, 6), None)):
+            b = cb.Batch.from_synth(sb, nbr=n_)
+            out = {}
+            for f64 in (1, 0):
+                ctx.set_option(cb.OPT_FP64_SUMS, f64)
+                res = []
+                for blk, tw, var, chunk in shapes:
+                    ctx.set_option(cb.OPT_BLOCK, blk)
+                    ctx.set_option(cb.OPT_TILE_W, tw)
+                    ctx.set_option(cb.OPT_VARIANT, var)
+                    ctx.set_option(cb.OPT_CHUNK_PX, chunk)
+                    res.append(ctx.elbo_eval(b, th))
+                out[f64] = [(spread(res[0][0][s], res[1][0][s]), spread(res[0][1][s], res[1][1][s]),
+                             spread(res[0][2][s], res[1][2][s])) for s in range(sb.n_sources)]
+            _say(sb.name, "launch-shape spread (elbo, grad, hess) fp64 sums", np.max(out[1], axis=0),
+                 "fp32 lane sums", np.max(out[0], axis=0))
+            for s, (de, dg, dh) in enumerate(out[1]):
+                assert de <= 1e-13 and dg <= 1e-11 and dh <= 1e-11, (sb.name, s, de, dg, dh)
+    finally:
+        ctx.set_option(cb.OPT_FP64_SUMS, 0)
+        _restore_defaults(cb, ctx)
+    with pytest.raises(cb.CelesteError):
+        ctx.set_option(cb.OPT_FP64_SUMS, 2)
+
+
 def _autotune_case(cb):
     full = synth.make_config(1, n_sources=12)
     th = perturb_theta(full.theta_truth, 31)
