@@ -635,7 +635,8 @@ def main():
         "iterations_hist": np.bincount(iters, minlength=52).tolist(),
         "status": status_counts,
         "phase_ms_per_step": {k[3:]: v for k, v in H["prof"].items() if k.startswith("ms_")},
-        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "eigendecomposition": st["tr_eigen"]},
+        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
+                           "eigendecomposition": st["tr_eigen"]},
         "phase_source": "the profiled step (eager launches with HIP events), one per start after the timed steps",
         "starts": {name: summary(r) for name, r in runs.items()},
         "autotune": tune,
@@ -1022,7 +1023,8 @@ def field_bench(args, ctx, net, sur_info, log):
         "autotune": tune,
         "sweeps": info["history"], "timings_s_per_step": {k: v / args.steps for k, v in info["timings"].items()},
         "pixel_evals_per_s": st["full_px"] / wall,
-        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "eigendecomposition": st["tr_eigen"]},
+        "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
+                           "eigendecomposition": st["tr_eigen"]},
         "profiled_sweep": {"s": wall_p, "phase_ms": {k[3:]: v for k, v in st_p.items() if k.startswith("ms_")},
                            "kernel_pixel_evals_per_s": st_p["full_px"] / full_s if full_s > 0 else None},
         "roofline": {"kernel": "k_eval_full (value+gradient+Hessian pixel kernel)", "bound": "alu",

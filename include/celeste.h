@@ -107,10 +107,11 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    sources exit at once; default 2); 0 = one block per work item.
                                    Results are bitwise the same */
   CELESTE_OPT_TR_CHOLESKY = 11, /* trust-region subproblem (section III-B): 1 = where -H is positive
-                                   definite and its Newton step lies inside the region, that step is
-                                   taken from one Cholesky factorisation (it solves the subproblem
-                                   exactly); otherwise, and always with 0, the eigendecomposition and
-                                   secular equation (default 1).  The two differ by rounding */
+                                   definite, Cholesky factorisations of -H + lam I give the exact
+                                   solution (lam = 0 for a Newton step inside the region, else
+                                   Newton's method on lam for the step on the boundary); otherwise,
+                                   and always with 0, the eigendecomposition and secular equation
+                                   (default 1).  The two differ by rounding */
   CELESTE_OPT_FP64_SUMS = 12    /* value+gradient+Hessian kernel: 1 = each tile step's FP32 gradient
                                    and Hessian pixel terms are summed across the wavefront in FP64,
                                    so every pixel sum is FP64 from the first addition (about 10%
@@ -141,9 +142,10 @@ typedef struct celeste_stats {
    * and line-search kernels (the milliseconds under CELESTE_OPT_PROFILE only) */
   int64_t grad_px, grad_launches;
   double ms_grad, ms_reduce_grad, ms_lbfgs;
-  /* trust-region subproblems solved by the interior Newton step (one Cholesky factorisation)
-   * and by the eigendecomposition and secular equation (CELESTE_OPT_TR_CHOLESKY) */
-  int64_t tr_interior, tr_eigen;
+  /* trust-region subproblems solved by the interior Newton step (one Cholesky factorisation),
+   * by the boundary step from Cholesky factorisations of -H + lam I, and by the
+   * eigendecomposition and secular equation (CELESTE_OPT_TR_CHOLESKY) */
+  int64_t tr_interior, tr_boundary, tr_eigen;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

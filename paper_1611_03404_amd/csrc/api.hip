@@ -78,7 +78,7 @@ struct celeste_ctx {
   int vtile_log2 = 3;    // log2 tile width of the value kernel
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
-  DevBuf ctr;      // device counters: pixel evaluations [full, value, grad], subproblem paths [interior, eigen]
+  DevBuf ctr;      // device counters: pixel evaluations [full, value, grad], subproblem paths [3..5]
   int profile = 0;
   celeste_stats stats{};
 
@@ -92,7 +92,7 @@ struct celeste_ctx {
   DevBuf lb_buf;                                   // L-BFGS state beyond the fit state
   DevBuf imgs_s, items_s, srcs_s, partials_s;      // the pixel-subsampled pack of a fit's early phase
   int persistent = 2;                              // fits: persistent pixel-kernel blocks per CU (0: off)
-  int tr_chol = 1;                                 // fits: interior Newton step by Cholesky first
+  int tr_chol = 1;                                 // fits: subproblem by Cholesky where -H is positive definite
   int fp64_sums = 0;                               // value+gradient+Hessian kernel: FP64 sums per tile step
   int n_cu = 0;                                    // compute units of the device
   DevBuf qbuf;                                     // the fits' device work queue
@@ -664,8 +664,8 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
-  if (ensure(c->ctr, 5 * sizeof(unsigned long long)) != CELESTE_OK ||
-      hipMemset(c->ctr.p, 0, 5 * sizeof(unsigned long long)) != hipSuccess) {
+  if (ensure(c->ctr, 6 * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, 6 * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipStreamDestroy(c->stream);
     if (c->ctr.p) (void)hipFree(c->ctr.p);
     delete c;
@@ -697,13 +697,14 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
 int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
   HIPCHK(hipSetDevice(c->device));
-  unsigned long long h[5] = {0, 0, 0, 0, 0};
+  unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
   HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
   c->stats.full_px = (int64_t)h[0];
   c->stats.value_px = (int64_t)h[1];
   c->stats.grad_px = (int64_t)h[2];
   c->stats.tr_interior = (int64_t)h[3];
-  c->stats.tr_eigen = (int64_t)h[4];
+  c->stats.tr_boundary = (int64_t)h[4];
+  c->stats.tr_eigen = (int64_t)h[5];
   *out = c->stats;
   if (reset) {
     HIPCHK(hipMemset(c->ctr.p, 0, sizeof(h)));
@@ -1412,7 +1413,7 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   fp.delta_min = o->delta_min;
   fp.eta = o->eta;
   fp.u_box = o->u_box;
-  fp.interior_chol = ctx->tr_chol;
+  fp.tr_chol = ctx->tr_chol;
   fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
@@ -1477,6 +1478,8 @@ int run_fit_sampled(celeste_ctx* ctx, const celeste_batch* b, double* theta_inou
   fp.eta = o->eta;
   fp.u_box = o->u_box;
   fp.switch_rtol = switch_rtol;
+  fp.tr_chol = ctx->tr_chol;
+  fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
@@ -1605,8 +1608,6 @@ int run_lbfgs(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, con
   fp.max_iter = o->max_iter;
   fp.delta0 = 1.0;
   fp.u_box = o->u_box;
-  fp.interior_chol = ctx->tr_chol;
-  fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));

@@ -214,8 +214,9 @@ struct FitParams {
   int max_iter;
   double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
   double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
-  int interior_chol;    // try the interior Newton step by Cholesky before the eigendecomposition
-  unsigned long long* tr_ctr;   // subproblems solved [0] by the interior Cholesky step, [1] otherwise
+  int tr_chol;          // solve the subproblem by Cholesky factorisations where B is positive definite
+  unsigned long long* tr_ctr;   // subproblems solved: [0] interior step, [1] boundary step by Cholesky,
+                                // [2] by the eigendecomposition
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);

@@ -5,9 +5,9 @@
 // through a cyclic Jacobi eigendecomposition of B = -H (parallel round-robin
 // ordering, 14 disjoint rotations per round held in LDS), followed by the secular
 // equation |(B + sI)^{-1} g| = Delta solved by safeguarded Newton on 1/|p(s)|
-// (More-Sorensen), including the hard case.  Where B is positive definite and its
-// Newton step lies inside the region, one Cholesky factorisation gives that step
-// instead.  A separate kernel applies the
+// (More-Sorensen), including the hard case.  Where B is positive definite, Cholesky
+// factorisations of B + lam I give the step instead (the interior Newton step, or the
+// boundary step by Newton's method on lam).  A separate kernel applies the
 // ratio test and updates the radius, one thread per source.
 #include <math.h>
 
@@ -149,42 +149,47 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   double pred = 0.0;
   bool curv_ok = true;
 
-  // ---- interior Newton step.  Where B is positive definite and the Newton step B^{-1} g lies
-  // inside the region, that step is the exact solution of the subproblem (zero multiplier in the
-  // optimality conditions of Nocedal & Wright, Theorem 4.1), so one Cholesky factorisation of B
-  // (right-looking in LDS, one column per step, the forward substitution carried along) replaces
-  // the eigendecomposition.  B indefinite or nearly singular (a pivot at most 1e-12 of the
-  // largest diagonal entry), or a step outside the region, takes the eigendecomposition below.
-  bool interior = false;
-  if (fp.interior_chol) {
-    for (int k = t; k < NP * NP; k += 64) W[k / NP][k % NP] = B[k / NP][k % NP];
-    if (t < NPAD) y[t] = g[t];
+  // ---- Cholesky paths.  Where B is positive definite, the subproblem's solution is
+  // p(lam) = (B + lam I)^{-1} g with lam = 0 if |p(0)| <= Delta (the interior Newton step), and
+  // otherwise the lam > 0 with |p(lam)| = Delta (optimality conditions of Nocedal & Wright,
+  // Theorem 4.1).  That lam is found by Newton's method on 1/|p(lam)| - 1/Delta from lam = 0
+  // (Nocedal & Wright, Algorithm 4.3, with q = L^{-1} p): the function is concave and increasing
+  // for lam >= 0, so the iterates increase to the root and B + lam I stays positive definite.
+  // Each step costs one Cholesky factorisation (right-looking in LDS, one column per step, the
+  // forward substitution carried along) and two triangular solves, instead of the
+  // eigendecomposition.  B indefinite or nearly singular (a pivot at most 1e-12 of the largest
+  // diagonal entry), or a boundary step not within 1e-9 Delta of the radius after 30 Newton
+  // steps, takes the eigendecomposition below.
+  int path = 2;   // 0: interior step by Cholesky, 1: boundary step by Cholesky, 2: eigendecomposition
+  if (fp.tr_chol) {
     double dmax = t < NP ? B[t][t] : -INFINITY;
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
     dmax = __shfl(dmax, 0);
-    __syncthreads();
-    bool ok = dmax > 0.0;
-    for (int k = 0; k < NP && ok; ++k) {
-      const double piv = W[k][k];   // the same value on every lane: the decision is uniform
-      if (!(piv > 1e-12 * dmax)) {
-        ok = false;
-        break;
+    // W <- the Cholesky factor L of B + lam I (lower triangle), pst <- (B + lam I)^{-1} g
+    auto factor_solve = [&](double lam) -> bool {
+      for (int k = t; k < NP * NP; k += 64) {
+        const int i = k / NP, j = k - i * NP;
+        W[i][j] = B[i][j] + (i == j ? lam : 0.0);
       }
-      const double lkk = sqrt(piv);
-      // (W[k][k] is read above by every lane and written only after the barrier)
-      if (t > k && t < NP) W[t][k] /= lkk;
-      if (t == k) y[k] /= lkk;
+      if (t < NPAD) y[t] = g[t];
       __syncthreads();
-      const int m = NP - 1 - k;
-      for (int e = t; e < m * m; e += 64) {
-        const int i = k + 1 + e / m, j = k + 1 + e % m;
-        if (j <= i) W[i][j] -= W[i][k] * W[j][k];
+      for (int k = 0; k < NP; ++k) {
+        const double piv = W[k][k];   // the same value on every lane: the decision is uniform
+        if (!(piv > 1e-12 * (dmax + lam))) return false;
+        const double lkk = sqrt(piv);
+        // (W[k][k] is read above by every lane and written only after the barrier)
+        if (t > k && t < NP) W[t][k] /= lkk;
+        if (t == k) y[k] /= lkk;
+        __syncthreads();
+        const int m = NP - 1 - k;
+        for (int e = t; e < m * m; e += 64) {
+          const int i = k + 1 + e / m, j = k + 1 + e % m;
+          if (j <= i) W[i][j] -= W[i][k] * W[j][k];
+        }
+        if (t > k && t < NP) y[t] -= W[t][k] * y[k];
+        if (t == k) W[k][k] = lkk;
+        __syncthreads();
       }
-      if (t > k && t < NP) y[t] -= W[t][k] * y[k];
-      if (t == k) W[k][k] = lkk;
-      __syncthreads();
-    }
-    if (ok) {
       // back substitution L' p = y, one unknown per step
       for (int k = NP - 1; k >= 0; --k) {
         const double yk = y[k] / W[k][k];
@@ -192,15 +197,45 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         if (t < k) y[t] -= W[k][t] * yk;
         __syncthreads();
       }
-      const double pi = t < NP ? pst[t] : 0.0;
-      if (wsum(pi * pi) <= delta * delta) {
-        interior = true;
-        pred = 0.5 * wsum(t < NP ? g[t] * pi : 0.0);
+      return true;
+    };
+    if (dmax > 0.0 && factor_solve(0.0)) {
+      double pn2 = wsum(t < NP ? pst[t] * pst[t] : 0.0);
+      if (pn2 <= delta * delta) {
+        path = 0;
+        pred = 0.5 * wsum(t < NP ? g[t] * pst[t] : 0.0);
+      } else {
+        double lam = 0.0;
+        for (int it = 0; it < 30; ++it) {
+          const double pn = sqrt(pn2);
+          if (fabs(pn - delta) <= 1e-9 * delta) {
+            path = 1;
+            break;
+          }
+          // q = L^{-1} p by forward substitution, lane k keeping q_k
+          if (t < NPAD) y[t] = t < NP ? pst[t] : 0.0;
+          __syncthreads();
+          double qk = 0.0;
+          for (int k = 0; k < NP; ++k) {
+            const double yk = y[k] / W[k][k];
+            if (t == k) qk = yk;
+            if (t > k && t < NP) y[t] -= W[t][k] * yk;
+            __syncthreads();
+          }
+          const double qn2 = wsum(qk * qk);
+          lam += (pn2 / qn2) * (pn - delta) / delta;
+          if (!(lam >= 0.0)) lam = 0.0;   // only by rounding: |p(0)| > Delta
+          if (!factor_solve(lam)) break;
+          pn2 = wsum(t < NP ? pst[t] * pst[t] : 0.0);
+        }
+        // predicted gain g'p - p'Bp/2 with (B + lam I) p = g
+        if (path == 1) pred = 0.5 * (wsum(t < NP ? g[t] * pst[t] : 0.0) + lam * pn2);
       }
     }
+    __syncthreads();
   }
 
-  if (!interior) {
+  if (path == 2) {
   // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
   // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model
   for (int k = t; k < NPAD * NPAD; k += 64) {
@@ -388,7 +423,7 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   }   // eigendecomposition
 
   if (t == 0) {
-    if (fp.tr_ctr) atomicAdd(fp.tr_ctr + (interior ? 0 : 1), 1ull);
+    if (fp.tr_ctr) atomicAdd(fp.tr_ctr + path, 1ull);
     // convergence and iteration cap; on the subsampled objective, the switch to the full one
     const double f = st.f[s];
     int d = 0;

@@ -148,11 +148,12 @@ def test_persistent_work_queue_equals_one_block_per_item(cb, ctx):
 
 
 def test_interior_cholesky_step_matches_eigendecomposition(cb, ctx):
-    """The interior Newton step by Cholesky (the subproblem's exact solution where -H is positive
-    definite and the step lies inside the region) against the eigendecomposition path on every
-    iteration: the same fits up to rounding (ELBO within 1e-9 relative, parameters within 1e-5 of
-    their scale, every source converged both ways, iteration counts within one) on a ragged
-    config-1 subset and config-2 sources, graph replay, and eager with the option cleared."""
+    """The Cholesky paths of the subproblem (where -H is positive definite: the interior Newton
+    step, or the boundary step by Newton's method on the multiplier) against the
+    eigendecomposition path on every iteration: the same fits up to rounding (ELBO within 1e-9
+    relative, parameters within 1e-5 of their scale, every source converged both ways, iteration
+    counts within one) on a ragged config-1 subset and config-2 sources, graph replay, and eager
+    with the option cleared; both Cholesky paths are taken."""
     c1 = synth.make_config(1, n_sources=40)
     side = c1.truth["side"]
     sets = [c1.subset(list(np.argsort(side)[:6]) + list(np.argsort(side)[-6:])),
@@ -164,7 +165,13 @@ def test_interior_cholesky_step_matches_eigendecomposition(cb, ctx):
             th0[:, 0:2] = sb.u_cat
             o = cb.default_opts(init_mode=cb.INIT_PLAIN)
             ctx.set_option(cb.OPT_TR_CHOLESKY, 1)
+            ctx.stats(reset=True)
             th_c, rc = ctx.batch_fit(b, th0, o)
+            st = ctx.stats()
+            _say(sb.name, "subproblems: interior", st["tr_interior"], "boundary", st["tr_boundary"],
+                 "eigendecomposition", st["tr_eigen"])
+            assert st["tr_interior"] > 0 and st["tr_boundary"] > 0
+            assert st["tr_interior"] + st["tr_boundary"] + st["tr_eigen"] == int(np.sum(rc["iters"])) + sb.n_sources
             ctx.set_option(cb.OPT_TR_CHOLESKY, 0)
             th_e, re_ = ctx.batch_fit(b, th0, o)
             ctx.set_option(cb.OPT_USE_GRAPH, 0)
