@@ -244,6 +244,25 @@ def oracle_fit_baseline(sb, n, gpu_plain_elbo, gpu_head_elbo, log):
     }
 
 
+def oracle_fits_from(args, log):
+    """The GPU fits saved by --save-fits (run with --host-generated) against complete oracle fits
+    of a size-stratified sample, on this machine's cores: one JSON line."""
+    import numpy as np
+    import synth
+    d = np.load(args.oracle_fits_from, allow_pickle=False)
+    if not bool(d["host_generated"]):
+        sys.exit("the saved fits are not of a host-generated workload (run the GPU side with --host-generated)")
+    n = int(d["n_sources"])
+    t = time.perf_counter()
+    sb = synth.make_config(2, n_sources=n)
+    log(f"workload rebuilt on the host: {sb.n_sources} sources, {sb.n_pixels} px ({time.perf_counter() - t:.0f} s)")
+    res = oracle_fit_baseline(sb, args.cpu_baseline_fits or 200, d["plain_elbo"], d["head_elbo"], log)
+    res["headline_start"] = str(d["head"])
+    res["gpu_converged_status"] = {"plain": int(np.sum(d["plain_status"] == 0)), "headline": int(np.sum(d["head_status"] == 0))}
+    print(json.dumps({"oracle_fits": res, "workload": f"batched uneven sources, {n} sources (host-generated pixels)"}),
+          flush=True)
+
+
 _SAMPLED_JOB = None   # (subset, keep, off, keep_prob, thetas): inherited by forked workers
 
 
@@ -421,6 +440,17 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--no-surrogate", action="store_true", help="plain start only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-generated", action="store_true",
+                    help="batched workload: draw the pixels with NumPy on the host (the same draws on any machine) "
+                         "and move them to the device before the timed region, so that --oracle-fits-from can "
+                         "rebuild the same workload without a GPU")
+    ap.add_argument("--save-fits", default=None,
+                    help="batched workload: write the final ELBO and status of every source, per start, to this "
+                         ".npz file")
+    ap.add_argument("--oracle-fits-from", default=None,
+                    help="no GPU: rebuild the host-generated batched workload and fit a size-stratified sample of "
+                         "--cpu-baseline-fits sources (default 200) with the oracle on the host cores, checking the "
+                         "GPU fits saved by --save-fits against the oracle-converged ELBO")
     ap.add_argument("--cpu-baseline-fits", type=int, default=0,
                     help="batched workload: also fit a size-stratified sample of this many sources with the oracle "
                          "(complete fits on the host cores; 200 = 1%% of the workload takes about 15 minutes on 16 "
@@ -478,6 +508,8 @@ def main():
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
+    if args.oracle_fits_from:
+        return oracle_fits_from(args, log)
     ctx = cb.Context(0)
     if args.persistent is not None:
         ctx.set_option(cb.OPT_PERSISTENT, args.persistent)
@@ -513,10 +545,14 @@ def main():
     if args.workload == "field":
         return field_bench(args, ctx, net, sur_info, log)
     t_gen = time.perf_counter()
-    sb = synth.make_config(2, n_sources=args.sources, device="cuda")
+    if args.host_generated:
+        sb = synth.make_config(2, n_sources=args.sources)
+        sb.pixels = torch.from_numpy(sb.pixels).to("cuda")
+    else:
+        sb = synth.make_config(2, n_sources=args.sources, device="cuda")
     torch.cuda.synchronize()
     log(f"workload: {sb.n_sources} sources, {sb.n_images} images, {sb.n_pixels} px "
-        f"({time.perf_counter() - t_gen:.1f} s to generate)")
+        f"({time.perf_counter() - t_gen:.1f} s to generate{' on the host' if args.host_generated else ''})")
     batch = cb.Batch.from_synth(sb)
     theta0 = np.zeros((sb.n_sources, 27))
     theta0[:, 0:2] = sb.u_cat
@@ -675,6 +711,10 @@ def main():
 
         out["cpu_baseline"] = cpu_baseline(sb, th_np, gpu_eval, st["full_px"] / args.steps,
                                            st["value_px"] / args.steps, conv_tol / args.steps)
+    if args.save_fits:
+        np.savez(args.save_fits, n_sources=sb.n_sources, host_generated=bool(args.host_generated),
+                 plain_elbo=runs["plain"]["res"]["elbo"], plain_status=runs["plain"]["res"]["status"],
+                 head_elbo=H["res"]["elbo"], head_status=H["res"]["status"], head=head)
     if args.cpu_baseline_fits:
         log(f"oracle fits of a size-stratified sample of {args.cpu_baseline_fits} sources ...")
         out["cpu_baseline_fits"] = oracle_fit_baseline(sb, args.cpu_baseline_fits, runs["plain"]["res"]["elbo"],

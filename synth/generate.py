@@ -313,7 +313,15 @@ def make_config(k, n_sources=None, seed=None, bright=False, device=None, pixel_c
 
     # --- sky + assemble ---------------------------------------------------------------
     if device is None:
-        pixels = r_noise.poisson(np.repeat(img_sky, npx)).astype(np.float32)
+        # in chunks of whole images (the draws are taken in pixel order either way)
+        pixels = np.empty(n_pix, dtype=np.float32)
+        ends = np.cumsum(npx)
+        i0 = 0
+        while i0 < I:
+            a = int(img_pix_off[i0])
+            i1 = max(int(np.searchsorted(ends, a + pixel_chunk, side="right")), i0 + 1)
+            pixels[a:int(ends[i1 - 1])] = r_noise.poisson(np.repeat(img_sky[i0:i1], npx[i0:i1]))
+            i0 = i1
         np.add.at(pixels, ph_idx, ph_cnt.astype(np.float32))
     else:
         import torch

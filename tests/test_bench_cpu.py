@@ -32,3 +32,25 @@ def test_stratified_sample_takes_one_source_per_size_stratum():
     assert len(pick) == 40 and len(set(pick)) == 40
     rank = np.argsort(np.argsort(npx, kind="stable"), kind="stable")
     assert sorted(rank[pick] // 50) == list(range(40))
+
+
+def test_host_pixels_drawn_in_chunks_equal_one_draw():
+    """The host-generated workload (bench --host-generated, rebuilt by --oracle-fits-from) draws
+    its sky counts in chunks of whole images; the chunk size changes no value."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import synth
+    a = synth.make_config(1, n_sources=12, pixel_chunk=1)
+    b = synth.make_config(1, n_sources=12, pixel_chunk=1 << 27)
+    c = synth.make_config(1, n_sources=12, pixel_chunk=3000)
+    assert a.pixels.dtype == np.float32 and np.array_equal(a.pixels, b.pixels) and np.array_equal(b.pixels, c.pixels)
+
+
+def test_oracle_fits_from_refuses_device_generated_fits(tmp_path):
+    import numpy as np
+    p = tmp_path / "fits.npz"
+    np.savez(p, n_sources=10, host_generated=False, plain_elbo=np.zeros(10), plain_status=np.zeros(10, np.int32),
+             head_elbo=np.zeros(10), head_status=np.zeros(10, np.int32), head="plain")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-fits-from", str(p)],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "host-generated" in r.stderr
