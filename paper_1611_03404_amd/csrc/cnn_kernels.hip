@@ -33,18 +33,18 @@ typedef __attribute__((ext_vector_type(4))) float f32x4_t;
 __device__ __forceinline__ bf16 to_bf16(float x) { return (bf16)x; }
 __device__ __forceinline__ float from_bf16(bf16 x) { return (float)x; }
 
-constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;
+constexpr int TM = 64, TK = 32, TKP = TK + 8;
 
 // ------------------------------------------------------------------ gather loaders
-// Each loader gives 8 consecutive k of A(m, k) (a8) and of B(k, n) (b8) of the product
-// C[m][n] = sum_k A(m,k) B(k,n), zero for k >= kend or an index out of range; the index
-// decomposition is done once per run of 8, not per element.
+// A loader gives 8 consecutive k of A(m, k) (a8), zero for k >= kend or an index out of range.
+// For B(k, n) it gives either 8 consecutive k at one n (b8; kRunN false) or, for the
+// convolution operands built from images, 8 consecutive n at one k (b8n; kRunN true): n is a
+// multiple of 8 and the images are square with a power-of-two width of at least 8, so the 8
+// pixels lie in one image row and the tap and channel decomposition is done once per run.
 
 // kk -> (ky, kx) of a 3x3 kernel tap
 __device__ __forceinline__ int tap_y(int kk) { return (kk * 11) >> 5; }   // kk / 3 for kk < 9
 __device__ __forceinline__ int tap_x(int kk) { return kk - 3 * tap_y(kk); }
-
-typedef __attribute__((ext_vector_type(8))) unsigned short u16x8_t;
 
 __device__ __forceinline__ bf16x8_t zero8() {
   bf16x8_t z;
@@ -64,70 +64,58 @@ __device__ __forceinline__ bf16x8_t load8(const bf16* p, int n_valid, bool align
   return v;
 }
 
+// The 8 pixels x0 .. x0+7 of one image row (zero outside 0 .. wd-1): one 16-byte load where the
+// run is inside the row and aligned (the centre tap column), else element by element.
+__device__ __forceinline__ bf16x8_t row8(const bf16* row, int x0, int wd) {
+  if (x0 >= 0 && x0 + 8 <= wd && ((uintptr_t)(row + x0) & 15) == 0)
+    return *reinterpret_cast<const bf16x8_t*>(row + x0);
+  bf16x8_t v = zero8();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int x = x0 + j;
+    if (x >= 0 && x < wd) v[j] = row[x];
+  }
+  return v;
+}
+
 struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img][ci][p + off(kk)]
+  static constexpr bool kRunN = true;
   const bf16* W;
   const bf16* X;
-  int Cin, H, Wd;
+  int Cin, hwl, wl;       // image side 2^wl, HW = 2^hwl
   __device__ bf16x8_t a8(int m, int k, int kend) const {
     const size_t o = (size_t)m * Cin * 9 + k;
     return load8(W + o, kend - k, (o & 7) == 0);
   }
-  __device__ bf16x8_t b8(int k, int n, int kend) const {
-    bf16x8_t v = zero8();
-    const int HW = H * Wd, img = n / HW, p = n - img * HW;
-    const int py = p / Wd, px = p - py * Wd;
-    int ci = k / 9, kk = k - ci * 9;
-    const bf16* Xi = X + (size_t)img * Cin * HW;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int y = py + tap_y(kk) - 1, x = px + tap_x(kk) - 1;
-      if (k + j < kend && y >= 0 && y < H && x >= 0 && x < Wd) v[j] = Xi[(size_t)ci * HW + y * Wd + x];
-      if (++kk == 9) {
-        kk = 0;
-        ++ci;
-      }
-    }
-    return v;
+  __device__ bf16x8_t b8n(int k, int n) const {
+    const int img = n >> hwl, p = n & ((1 << hwl) - 1), py = p >> wl, px = p & ((1 << wl) - 1);
+    const int ci = k / 9, kk = k - ci * 9;
+    const int y = py + tap_y(kk) - 1;
+    if (y < 0 || y >= (1 << wl)) return zero8();
+    return row8(X + (((size_t)img * Cin + ci) << hwl) + ((size_t)y << wl), px + tap_x(kk) - 1, 1 << wl);
   }
 };
 
 struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img][co][p - off(kk)]
-  const bf16* W;
+  static constexpr bool kRunN = true;
+  const bf16* Wt;         // the layer's weights as Wt[ci][co*9+kk]
   const bf16* dY;
-  int Cin, Cout, H, Wd;
+  int Cin, Cout, hwl, wl;
   __device__ bf16x8_t a8(int m, int k, int kend) const {
-    bf16x8_t v = zero8();
-    int co = k / 9, kk = k - co * 9;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (k + j < kend) v[j] = W[((size_t)co * Cin + m) * 9 + kk];
-      if (++kk == 9) {
-        kk = 0;
-        ++co;
-      }
-    }
-    return v;
+    const size_t o = (size_t)m * Cout * 9 + k;
+    return load8(Wt + o, kend - k, (o & 7) == 0);
   }
-  __device__ bf16x8_t b8(int k, int n, int kend) const {
-    bf16x8_t v = zero8();
-    const int HW = H * Wd, img = n / HW, p = n - img * HW;
-    const int py = p / Wd, px = p - py * Wd;
-    int co = k / 9, kk = k - co * 9;
-    const bf16* Di = dY + (size_t)img * Cout * HW;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int y = py - tap_y(kk) + 1, x = px - tap_x(kk) + 1;
-      if (k + j < kend && y >= 0 && y < H && x >= 0 && x < Wd) v[j] = Di[(size_t)co * HW + y * Wd + x];
-      if (++kk == 9) {
-        kk = 0;
-        ++co;
-      }
-    }
-    return v;
+  __device__ bf16x8_t b8n(int k, int n) const {
+    const int img = n >> hwl, p = n & ((1 << hwl) - 1), py = p >> wl, px = p & ((1 << wl) - 1);
+    const int co = k / 9, kk = k - co * 9;
+    const int y = py - tap_y(kk) + 1;
+    if (y < 0 || y >= (1 << wl)) return zero8();
+    return row8(dY + (((size_t)img * Cout + co) << hwl) + ((size_t)y << wl), px - tap_x(kk) + 1, 1 << wl);
   }
 };
 
 struct LdConvWgrad {      // dW[co][ci*9+kk] = sum_{img,p} dY[img][co][p] X[img][ci][p + off(kk)]
+  static constexpr bool kRunN = false;
   const bf16* dY;
   const bf16* X;
   int Cin, Cout, H, Wd;
@@ -155,6 +143,7 @@ struct LdConvWgrad {      // dW[co][ci*9+kk] = sum_{img,p} dY[img][co][p] X[img]
 };
 
 struct LdFcFwd {          // Y[o][b] = sum_i W[o][i] X[b][i]
+  static constexpr bool kRunN = false;
   const bf16* W;
   const bf16* X;
   int In;
@@ -167,6 +156,7 @@ struct LdFcFwd {          // Y[o][b] = sum_i W[o][i] X[b][i]
 };
 
 struct LdFcDgrad {        // dX[i][b] = sum_o W[o][i] dY[b][o]
+  static constexpr bool kRunN = false;
   const bf16* W;
   const bf16* dY;
   int In, Out;
@@ -183,6 +173,7 @@ struct LdFcDgrad {        // dX[i][b] = sum_o W[o][i] dY[b][o]
 };
 
 struct LdFcWgrad {        // dW[o][i] = sum_b dY[b][o] X[b][i]
+  static constexpr bool kRunN = false;
   const bf16* dY;
   const bf16* X;
   int In, Out;
@@ -210,56 +201,90 @@ struct EpConvFwd {
   int HW;
 };
 
-// C[z][m][n] = sum over the z-th K split of A(m,k) B(k,n).  Block 256 = 4 waves in a
-// 2x2 arrangement, each wave a 32x32 sub-tile of 2x2 MFMA 16x16x32 tiles.  Operand runs of
-// 8 BF16 go to LDS and come back as single 16-byte accesses; the next K step's operands are
-// loaded into registers while the current step's products run.  With ep.act set (and one
-// split) the convolution forward epilogue is applied in place of the C store.
+// Tile width in N: 128 for the convolution operands built from images (n-runs), 64 otherwise
+// (the dense layers and the weight gradients, whose N is small).
+template <class LD>
+constexpr int tile_n() { return LD::kRunN ? 128 : 64; }
+
+// C[z][m][n] = sum over the z-th K split of A(m,k) B(k,n).  Block 256 = 4 waves in a 2x2
+// arrangement over a 64 x TNB tile, each wave a 32 x TNB/2 sub-tile of 2 x TNB/32 MFMA
+// 16x16x32 tiles.  Operand runs of 8 BF16 go to LDS (k-runs as 16-byte stores, n-runs
+// transposed element by element) and come back as single 16-byte reads; the next K step's
+// operands are loaded into registers while the current step's products run.  With ep.act set
+// (and one split) the convolution forward epilogue is applied in place of the C store.
 template <class LD>
 __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kchunk, float* __restrict__ C,
                                               EpConvFwd ep) {
+  constexpr int TNB = tile_n<LD>(), NJ = TNB / 32, NR = TNB / 64;
   __shared__ __align__(16) bf16 As[TM][TKP];
-  __shared__ __align__(16) bf16 Bs[TN][TKP];
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  __shared__ __align__(16) bf16 Bs[TNB][TKP];
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TNB;
   const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  f32x4_t acc[2][2];
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * (TNB / 2);
+  f32x4_t acc[2][NJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int lr = t >> 2, lk = (t & 3) * 8;
-  const int m = m0 + lr, n = n0 + lr;
-  auto fetch = [&](int k0, bf16x8_t& av, bf16x8_t& bv) {
-    const int k = k0 + lk;
-    av = (m < M && k < kend) ? ld.a8(m, k, kend) : zero8();
-    bv = (n < N && k < kend) ? ld.b8(k, n, kend) : zero8();
-  };
-  bf16x8_t an, bn;
-  fetch(kbeg, an, bn);
-  const int r16 = lane & 15, kq = (lane >> 4) * 8;
-  for (int k0 = kbeg; k0 < kend; k0 += TK) {
-    *reinterpret_cast<bf16x8_t*>(&As[lr][lk]) = an;
-    *reinterpret_cast<bf16x8_t*>(&Bs[lr][lk]) = bn;
-    __syncthreads();
-    if (k0 + TK < kend) fetch(k0 + TK, an, bn);   // next step's operands, in flight during the products
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // A: row t / 4, k-run (t % 4) * 8.  B k-runs: rows t / 4 (+ 64), k-run (t % 4) * 8.  B n-runs
+  // (TNB = 128): k = t % 32, columns 8 (t / 32) .. + 7 and the same + 64 (the 32 lanes of one
+  // n-run write 32 consecutive k of a row of Bs, so the transposed stores spread over the banks).
+  const int ar = t >> 2, ak = (t & 3) * 8;
+  const int nb = 8 * (t >> 5), kb = t & 31;
+  bf16x8_t an, bn[NR];
+  auto fetch = [&](int k0) {
+    {
+      const int m = m0 + ar, k = k0 + ak;
+      an = (m < M && k < kend) ? ld.a8(m, k, kend) : zero8();
+    }
+    if constexpr (LD::kRunN) {
+      const int k = k0 + kb;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bf16x8_t av = *reinterpret_cast<const bf16x8_t*>(&As[wm + i * 16 + r16][kq]);
+      for (int r = 0; r < NR; ++r) {
+        const int n = n0 + nb + 64 * r;
+        bn[r] = (n < N && k < kend) ? ld.b8n(k, n) : zero8();
+      }
+    } else {
+      const int k = k0 + ak;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + j * 16 + r16][kq]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
+      for (int r = 0; r < NR; ++r) {
+        const int n = n0 + ar + 64 * r;
+        bn[r] = (n < N && k < kend) ? ld.b8(k, n, kend) : zero8();
       }
     }
+  };
+  bf16x8_t a[2], b[NJ];
+  fetch(kbeg);
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    *reinterpret_cast<bf16x8_t*>(&As[ar][ak]) = an;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if constexpr (LD::kRunN) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[nb + 64 * r + j][kb] = bn[r][j];
+      } else {
+        *reinterpret_cast<bf16x8_t*>(&Bs[ar + 64 * r][ak]) = bn[r];
+      }
+    }
+    __syncthreads();
+    if (k0 + TK < kend) fetch(k0 + TK);   // next step's operands, in flight during the products
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8_t*>(&As[wm + i * 16 + r16][kq]);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + j * 16 + r16][kq]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   float* Cz = C + (size_t)blockIdx.z * M * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int mm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -478,6 +503,16 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __re
   }
 }
 
+// One convolution layer's weights re-laid for the data-gradient product: Wt[ci][co*9+kk] =
+// W[co][ci*9+kk].
+__global__ void k_wt(const bf16* __restrict__ W, int Cin, int Cout, bf16* __restrict__ Wt) {
+  const int n = Cin * Cout * 9;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int ci = i / (Cout * 9), r = i - ci * Cout * 9, co = r / 9, kk = r - co * 9;
+    Wt[i] = W[((size_t)co * Cin + ci) * 9 + kk];
+  }
+}
+
 __global__ void k_to_bf16(const float* __restrict__ w, bf16* __restrict__ wb, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) wb[i] = to_bf16(w[i]);
 }
@@ -544,12 +579,18 @@ hipError_t gemm(LD ld, int M, int N, int K, float* C, int& splits, hipStream_t s
   const int S = (K + kchunk - 1) / kchunk;
   splits = S;
   if (S != 1) ep.act = nullptr;
-  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, S);
+  dim3 grid((N + tile_n<LD>() - 1) / tile_n<LD>(), (M + TM - 1) / TM, S);
   hipLaunchKernelGGL(k_gemm<LD>, grid, dim3(256), 0, st, ld, M, N, K, kchunk, C, ep);
   return hipGetLastError();
 }
 
 inline int nblk(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 16384); }
+
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
 
 }  // namespace
 
@@ -588,6 +629,7 @@ struct NetState {
   float* v = nullptr;
   float* g = nullptr;     // gradient
   bf16* wb = nullptr;     // BF16 weights
+  bf16* wt = nullptr;     // convolution weights re-laid for the data-gradient products (conv offsets)
   int step = 0;
   int cap_batch = 0;
   // activations (BF16) and gradients for cap_batch images
@@ -605,6 +647,7 @@ hipError_t net_alloc(NetState* n) {
   if ((e = hipMalloc(&n->v, P * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->g, P * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->wb, P * 2)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->wt, n->L.off[8] * 2)) != hipSuccess) return e;
   if ((e = hipMemset(n->m, 0, P * 4)) != hipSuccess) return e;
   if ((e = hipMemset(n->v, 0, P * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->bpart, sizeof(float) * 128 * BP_PARTS)) != hipSuccess) return e;
@@ -631,6 +674,7 @@ void net_free(NetState* n) {
   for (float* q : ff)
     if (q) (void)hipFree(q);
   if (n->wb) (void)hipFree(n->wb);
+  if (n->wt) (void)hipFree(n->wt);
 }
 
 static const int kSplitTarget = 1024;   // aim for about this many GEMM blocks
@@ -668,8 +712,8 @@ hipError_t net_reserve(NetState* n, int B) {
   return hipSuccess;
 }
 
-static int splits_for(size_t M, size_t N, size_t K, size_t cap) {
-  const size_t blocks = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+static int splits_for(size_t M, size_t N, size_t K, size_t cap, size_t tn = 64) {
+  const size_t blocks = ((M + TM - 1) / TM) * ((N + tn - 1) / tn);
   int s = 1;
   while (blocks * s < (size_t)kSplitTarget && K / (size_t)(s * 2) >= 256 && (size_t)(s * 2) * M * N <= cap) s *= 2;
   return s;
@@ -683,8 +727,9 @@ hipError_t net_forward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
   for (int l = 0; l < 4; ++l) {
     const int HW = L.hw[l] * L.hw[l];
     const size_t M = L.cout[l], N = (size_t)B * HW, K = (size_t)L.cin[l] * 9;
-    int S = splits_for(M, N, K, n->c_cap);
-    LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], L.hw[l], L.hw[l]};
+    int S = splits_for(M, N, K, n->c_cap, tile_n<LdConvFwd>());
+    const int wl = ilog2(L.hw[l]);
+    LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], 2 * wl, wl};
     if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, EpConvFwd{n->w + L.off[2 * l + 1], n->r[l], HW})) !=
         hipSuccess)
       return e;
@@ -768,8 +813,11 @@ hipError_t net_backward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
     // data gradient into the previous layer's post-ReLU activation (through its pool)
     {
       const size_t M = L.cin[l], N = (size_t)B * HW, K = (size_t)L.cout[l] * 9;
-      int S = splits_for(M, N, K, n->c_cap);
-      LdConvDgrad ld{n->wb + L.off[2 * l], n->dzb, L.cin[l], L.cout[l], L.hw[l], L.hw[l]};
+      int S = splits_for(M, N, K, n->c_cap, tile_n<LdConvDgrad>());
+      hipLaunchKernelGGL(k_wt, dim3(nblk((size_t)L.cin[l] * L.cout[l] * 9)), dim3(256), 0, st, n->wb + L.off[2 * l],
+                         L.cin[l], L.cout[l], n->wt + L.off[2 * l]);
+      const int wl = ilog2(L.hw[l]);
+      LdConvDgrad ld{n->wt + L.off[2 * l], n->dzb, L.cin[l], L.cout[l], 2 * wl, wl};
       if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
       const int Hp = L.hw[l - 1];
       hipLaunchKernelGGL(k_pool_relu_bwd, dim3(nblk((size_t)B * L.cout[l - 1] * Hp * Hp)), dim3(256), 0, st, n->C, S,
