@@ -132,7 +132,8 @@ typedef struct celeste_stats {
   double ms_setup, ms_full, ms_reduce_full, ms_tr, ms_value, ms_reduce_value, ms_accept;
   /* host wall-clock milliseconds of the fits' other stages (CELESTE_OPT_PROFILE only): packing and
    * validating the batch on the host, uploading metadata and checking pixels, choosing the start
-   * (network, start evaluations), and the iterations' polling and result download */
+   * (start evaluations; the network in ms_net below), and the iterations' polling and result
+   * download */
   double ms_host_pack, ms_prepare, ms_start, ms_loop, ms_results;
   /* linear-response covariance launches, and their kernel milliseconds (CELESTE_OPT_PROFILE only) */
   int64_t lr_launches;
@@ -146,6 +147,10 @@ typedef struct celeste_stats {
    * by the boundary step from Cholesky factorisations of -H + lam I, and by the
    * eigendecomposition and secular equation (CELESTE_OPT_TR_CHOLESKY) */
   int64_t tr_interior, tr_boundary, tr_eigen;
+  /* host wall-clock milliseconds of the surrogate network's inference (patches, forward pass and
+   * the map to parameters) in a surrogate start (CELESTE_OPT_PROFILE only; ms_start then holds the
+   * rest of the start: plain start and the evaluation of both starts) */
+  double ms_net;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

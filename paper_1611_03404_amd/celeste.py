@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("ms_loop", ctypes.c_double), ("ms_results", ctypes.c_double), ("lr_launches", ctypes.c_int64),
                 ("ms_lr", ctypes.c_double), ("grad_px", ctypes.c_int64), ("grad_launches", ctypes.c_int64),
                 ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double),
-                ("tr_interior", ctypes.c_int64), ("tr_boundary", ctypes.c_int64), ("tr_eigen", ctypes.c_int64)]
+                ("tr_interior", ctypes.c_int64), ("tr_boundary", ctypes.c_int64), ("tr_eigen", ctypes.c_int64),
+                ("ms_net", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):

@@ -1271,6 +1271,7 @@ int fit_begin(celeste_ctx* ctx, const celeste_batch* b, const double* theta_inou
     CHK(ensure(ctx->sur, sizeof(float) * NP * (size_t)S));
     CHK(surrogate_predict(ctx->net, as<SrcDev>(ctx->srcs), S, imgs0, F.theta, as<float>(ctx->sur), st));
     HIPCHK(launch_psi_to_theta(as<float>(ctx->sur), F.theta, F.theta_trial, S, fp.u_box, st));
+    stage(ctx->stats.ms_net, st);
     HIPCHK(launch_plain_init(as<SrcDev>(ctx->srcs), S, imgs0, P.prior, F.theta, st));
     for (int k = 0; k < 2; ++k) {
       double* tk = k == 0 ? F.theta : F.theta_trial;
