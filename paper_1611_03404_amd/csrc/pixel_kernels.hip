@@ -42,6 +42,17 @@ using namespace tab;
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// log(1 + u) for u >= 0.  Below u = 1/2: log(1 + u) = 2 atanh(s), s = u / (2 + u) <= 1/5, by the
+// series 2 (s + s^3/3 + s^5/5 + s^7/7 + s^9/9) (the first omitted term is below 1e-8 of the sum),
+// accurate relative to the result however small u is; from u = 1/2 on, the hardware base-2
+// logarithm of 1 + u (log(1 + u) >= 0.4 there, so its absolute error is a small relative one).
+__device__ __forceinline__ float log1p_pos(float u) {
+  const float sv = u * __builtin_amdgcn_rcpf(2.f + u), s2 = sv * sv;
+  const float ser = 2.f * fmaf(sv * s2, fmaf(s2, fmaf(s2, fmaf(s2, 1.f / 9.f, 1.f / 7.f), 1.f / 5.f), 1.f / 3.f), sv);
+  const float lg = __builtin_amdgcn_logf(1.f + u) * 0.693147180559945309f;
+  return u < 0.5f ? ser : lg;
+}
+
 // Exact-zero threshold on log2 of a component's density, a launch argument: -160 in general
 // (2^-160 lies below the smallest FP32 subnormal), -127 where v_exp_f32 flushes results below
 // 2^-126 to zero, which the library checks on the device when a context is created.
@@ -483,7 +494,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float V = fmaf(io2, Uv, vbg);
       const float rE = __builtin_amdgcn_rcpf(E);
       const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
-      const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
+      const float lval = fmaf(x, log1p_pos(io * Tv * __builtin_amdgcn_rcpf(ebg)), -io * Tv) - 0.5f * V * xr2;
       const float lE = fmaf(x - E, rE, V * xr3);
       const float lV = -0.5f * xr2;
       const float lEE = -fmaf(3.f * V * xr3, rE, xr2);
@@ -693,7 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_value(const WorkItem* __restrict
     const float E = fmaf(io, Tv, ebg);
     const float V = fmaf(io * io, Uv, vbg);
     const float rE = __builtin_amdgcn_rcpf(E);
-    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * (x * rE * rE);
+    const float lval = fmaf(x, log1p_pos(io * Tv * __builtin_amdgcn_rcpf(ebg)), -io * Tv) - 0.5f * V * (x * rE * rE);
     acc += (double)lval;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -849,7 +860,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
     const float V = fmaf(io2, Uv, vbg);
     const float rE = __builtin_amdgcn_rcpf(E);
     const float xr = x * rE, xr2 = xr * rE, xr3 = xr2 * rE;
-    const float lval = fmaf(x, log1pf(io * Tv / ebg), -io * Tv) - 0.5f * V * xr2;
+    const float lval = fmaf(x, log1p_pos(io * Tv * __builtin_amdgcn_rcpf(ebg)), -io * Tv) - 0.5f * V * xr2;
     const float wT = io * fmaf(x - E, rE, V * xr3), wU = io2 * (-0.5f * xr2);
     acc[0] += (double)lval;
 #pragma unroll
