@@ -431,9 +431,12 @@ int celeste_net_create(celeste_ctx* ctx, const float* params, int64_t n_params, 
                        const float* psi_std, celeste_net** out);
 void celeste_net_destroy(celeste_net* net);
 int celeste_net_get_params(celeste_net* net, float* params_out /* host */);
-/* Mean squared error over batch x 27 outputs and its gradient (host, n_params; may be NULL). */
+/* Mean squared error over batch x 27 outputs and its gradient (host, n_params; may be NULL).
+ * x must be 16-byte aligned (E_INVALID otherwise), as for celeste_net_forward. */
 int celeste_net_loss_grad(celeste_net* net, const void* x, const float* t, int batch, float* loss_out,
                           float* grad_out);
+/* Forward pass of n inputs; x must be 16-byte aligned (the first layer reads its image rows in
+ * 16-byte pieces); E_INVALID otherwise. */
 int celeste_net_forward(celeste_net* net, const void* x, int64_t n, float* y);
 /* Adam (lr, betas 0.9 / 0.999, eps 1e-8) over minibatches in the given orders; epoch_loss
  * (host, epochs entries, may be NULL) receives the mean minibatch loss of each epoch. */

@@ -64,19 +64,35 @@ __device__ __forceinline__ bf16x8_t load8(const bf16* p, int n_valid, bool align
   return v;
 }
 
-// The 8 pixels x0 .. x0+7 of one image row (zero outside 0 .. wd-1): one 16-byte load where the
-// run is inside the row and aligned (the centre tap column), else element by element.
-__device__ __forceinline__ bf16x8_t row8(const bf16* row, int x0, int wd) {
-  if (x0 >= 0 && x0 + 8 <= wd && ((uintptr_t)(row + x0) & 15) == 0)
-    return *reinterpret_cast<const bf16x8_t*>(row + x0);
-  bf16x8_t v = zero8();
+// The 8 pixels px + sh .. px + sh + 7 of one image row (zero outside 0 .. wd-1), px a multiple of 8,
+// sh in {-1, 0, 1}, row 16-byte aligned: the aligned 16 bytes at px and, for sh = -1 (+1), the 16 bytes
+// before (after) them, shifted by one element with funnel shifts; a neighbour chunk outside the row
+// reads as zeros.
+__device__ __forceinline__ bf16x8_t row8(const bf16* __restrict__ row, int px, int sh, int wd) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+  const u32x4_t zero = {0u, 0u, 0u, 0u};
+  const u32x4_t mid = *reinterpret_cast<const u32x4_t*>(row + px);
+  const u32x4_t lo = (sh < 0 && px > 0) ? *reinterpret_cast<const u32x4_t*>(row + px - 8) : zero;
+  const u32x4_t hi = (sh > 0 && px + 8 < wd) ? *reinterpret_cast<const u32x4_t*>(row + px + 8) : zero;
+  // window w = {lo.w, mid.x, mid.y, mid.z, mid.w, hi.x}; output dword i = (w[i+1+up] : w[i+up]) >> bits
+  const unsigned w[6] = {lo.w, mid.x, mid.y, mid.z, mid.w, hi.x};
+  const unsigned bits = sh == 0 ? 0u : 16u;
+  const int up = sh < 0 ? 0 : 1;
+  u32x4_t o;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int x = x0 + j;
-    if (x >= 0 && x < wd) v[j] = row[x];
+  for (int i = 0; i < 4; ++i) {
+    const unsigned a = up ? w[i + 2] : w[i + 1], b = up ? w[i + 1] : w[i];
+    o[i] = __builtin_amdgcn_alignbit(a, b, bits);
   }
-  return v;
+  return __builtin_bit_cast(bf16x8_t, o);
 }
+
+// Per-thread state of an n-run of a convolution operand: the run's image plane 0 and its first
+// pixel (row py, column px, a multiple of 8); fixed over the K loop.
+struct RunState {
+  const bf16* plane0;
+  int py, px;
+};
 
 struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img][ci][p + off(kk)]
   static constexpr bool kRunN = true;
@@ -87,12 +103,15 @@ struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img]
     const size_t o = (size_t)m * Cin * 9 + k;
     return load8(W + o, kend - k, (o & 7) == 0);
   }
-  __device__ bf16x8_t b8n(int k, int n) const {
-    const int img = n >> hwl, p = n & ((1 << hwl) - 1), py = p >> wl, px = p & ((1 << wl) - 1);
+  __device__ RunState run(int n) const {
+    const int img = n >> hwl, p = n & ((1 << hwl) - 1);
+    return RunState{X + (((size_t)img * Cin) << hwl), p >> wl, p & ((1 << wl) - 1)};
+  }
+  __device__ bf16x8_t b8n(int k, const RunState& r) const {
     const int ci = k / 9, kk = k - ci * 9;
-    const int y = py + tap_y(kk) - 1;
+    const int y = r.py + tap_y(kk) - 1;
     if (y < 0 || y >= (1 << wl)) return zero8();
-    return row8(X + (((size_t)img * Cin + ci) << hwl) + ((size_t)y << wl), px + tap_x(kk) - 1, 1 << wl);
+    return row8(r.plane0 + ((size_t)ci << hwl) + ((size_t)y << wl), r.px, tap_x(kk) - 1, 1 << wl);
   }
 };
 
@@ -105,12 +124,15 @@ struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img
     const size_t o = (size_t)m * Cout * 9 + k;
     return load8(Wt + o, kend - k, (o & 7) == 0);
   }
-  __device__ bf16x8_t b8n(int k, int n) const {
-    const int img = n >> hwl, p = n & ((1 << hwl) - 1), py = p >> wl, px = p & ((1 << wl) - 1);
+  __device__ RunState run(int n) const {
+    const int img = n >> hwl, p = n & ((1 << hwl) - 1);
+    return RunState{dY + (((size_t)img * Cout) << hwl), p >> wl, p & ((1 << wl) - 1)};
+  }
+  __device__ bf16x8_t b8n(int k, const RunState& r) const {
     const int co = k / 9, kk = k - co * 9;
-    const int y = py - tap_y(kk) + 1;
+    const int y = r.py - tap_y(kk) + 1;
     if (y < 0 || y >= (1 << wl)) return zero8();
-    return row8(dY + (((size_t)img * Cout + co) << hwl) + ((size_t)y << wl), px - tap_x(kk) + 1, 1 << wl);
+    return row8(r.plane0 + ((size_t)co << hwl) + ((size_t)y << wl), r.px, 1 - tap_x(kk), 1 << wl);
   }
 };
 
@@ -118,27 +140,19 @@ struct LdConvWgrad {      // dW[co][ci*9+kk] = sum_{img,p} dY[img][co][p] X[img]
   static constexpr bool kRunN = false;
   const bf16* dY;
   const bf16* X;
-  int Cin, Cout, H, Wd;
-  // k = img*HW + p; HW and the run's first k are multiples of 8, so a run stays in one image
-  // (and, with Wd >= 8 a multiple of 8, in one image row)
+  int Cin, Cout, hwl, wl;   // image side 2^wl, HW = 2^hwl
+  // k = img*HW + p; HW, the K splits and the run's first k are multiples of 8, so a run is whole
+  // and stays in one image row (the image side is a power of two of at least 8)
   __device__ bf16x8_t a8(int m, int k, int kend) const {
-    const int HW = H * Wd, img = k / HW, p = k - img * HW;
-    return load8(dY + ((size_t)img * Cout + m) * HW + p, kend - k, true);
+    const int img = k >> hwl, p = k & ((1 << hwl) - 1);
+    return load8(dY + ((((size_t)img * Cout + m) << hwl) + p), kend - k, true);
   }
-  __device__ bf16x8_t b8(int k, int n, int kend) const {
-    bf16x8_t v = zero8();
-    const int HW = H * Wd, img = k / HW, p = k - img * HW;
-    const int py = p / Wd, px = p - py * Wd;
+  __device__ bf16x8_t b8(int k, int n, int) const {
+    const int img = k >> hwl, p = k & ((1 << hwl) - 1), py = p >> wl, px = p & ((1 << wl) - 1);
     const int ci = n / 9, kk = n - ci * 9;
-    const int y = py + tap_y(kk) - 1, x0 = px + tap_x(kk) - 1;
-    if (y < 0 || y >= H) return v;
-    const bf16* row = X + ((size_t)img * Cin + ci) * HW + (size_t)y * Wd;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int x = x0 + j;
-      if (k + j < kend && x >= 0 && x < Wd) v[j] = row[x];
-    }
-    return v;
+    const int y = py + tap_y(kk) - 1;
+    if (y < 0 || y >= (1 << wl)) return zero8();
+    return row8(X + ((((size_t)img * Cin + ci) << hwl) + ((size_t)y << wl)), px, tap_x(kk) - 1, 1 << wl);
   }
 };
 
@@ -198,7 +212,7 @@ struct LdFcWgrad {        // dW[o][i] = sum_b dY[b][o] X[b][i]
 struct EpConvFwd {
   const float* bias;
   bf16* act;
-  int HW;
+  int hwl;                // HW = 2^hwl pixels per image
 };
 
 // Tile width in N: 128 for the convolution operands built from images (n-runs), 64 otherwise
@@ -233,6 +247,17 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
   const int ar = t >> 2, ak = (t & 3) * 8;
   const int nb = 8 * (t >> 5), kb = t & 31;
   bf16x8_t an, bn[NR];
+  // n-run states (fixed over the K loop; unused for k-run operands)
+  RunState rs[NR];
+  bool rv[NR];
+  if constexpr (LD::kRunN) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int n = n0 + nb + 64 * r;
+      rv[r] = n < N;
+      rs[r] = ld.run(rv[r] ? n : 0);
+    }
+  }
   auto fetch = [&](int k0) {
     {
       const int m = m0 + ar, k = k0 + ak;
@@ -241,10 +266,7 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
     if constexpr (LD::kRunN) {
       const int k = k0 + kb;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int n = n0 + nb + 64 * r;
-        bn[r] = (n < N && k < kend) ? ld.b8n(k, n) : zero8();
-      }
+      for (int r = 0; r < NR; ++r) bn[r] = (rv[r] && k < kend) ? ld.b8n(k, rs[r]) : zero8();
     } else {
       const int k = k0 + ak;
 #pragma unroll
@@ -291,8 +313,8 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
         const int nn = n0 + wn + j * 16 + (lane & 15);
         if (mm < M && nn < N) {
           if (ep.act) {
-            const int img = nn / ep.HW, p = nn - img * ep.HW;
-            ep.act[((size_t)img * M + mm) * ep.HW + p] = to_bf16(fmaxf(acc[i][j][r] + ep.bias[mm], 0.f));
+            const int img = nn >> ep.hwl, p = nn & ((1 << ep.hwl) - 1);
+            ep.act[((((size_t)img * M + mm) << ep.hwl) + p)] = to_bf16(fmaxf(acc[i][j][r] + ep.bias[mm], 0.f));
           } else {
             Cz[(size_t)mm * N + nn] = acc[i][j][r];
           }
@@ -730,7 +752,7 @@ hipError_t net_forward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
     int S = splits_for(M, N, K, n->c_cap, tile_n<LdConvFwd>());
     const int wl = ilog2(L.hw[l]);
     LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], 2 * wl, wl};
-    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, EpConvFwd{n->w + L.off[2 * l + 1], n->r[l], HW})) !=
+    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, EpConvFwd{n->w + L.off[2 * l + 1], n->r[l], 2 * wl})) !=
         hipSuccess)
       return e;
     if (S > 1)   // split products: the epilogue sums the splits
@@ -801,7 +823,8 @@ hipError_t net_backward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
     {
       const size_t M = L.cout[l], N = (size_t)L.cin[l] * 9, K = (size_t)B * HW;
       int S = splits_for(M, N, K, n->c_cap);
-      LdConvWgrad ld{n->dzb, xin, L.cin[l], L.cout[l], L.hw[l], L.hw[l]};
+      const int wl = ilog2(L.hw[l]);
+      LdConvWgrad ld{n->dzb, xin, L.cin[l], L.cout[l], 2 * wl, wl};
       if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_ep_sum, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, (int)(M * N), n->g + L.off[2 * l]);
       hipLaunchKernelGGL(k_bias_part, dim3(L.cout[l], BP_PARTS), dim3(256), 0, st, n->dz, B, L.cout[l], HW,
@@ -989,6 +1012,7 @@ int celeste_net_get_params(celeste_net* net, float* out) {
 
 int celeste_net_loss_grad(celeste_net* net, const void* x, const float* t, int batch, float* loss, float* grad) {
   if (!net || !x || !t || !loss || batch < 1) return net_fail(CELESTE_E_INVALID, "bad argument");
+  if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) return net_fail(CELESTE_E_INVALID, "x must be 16-byte aligned");
   NETCHK(hipSetDevice(net->device), "set device");
   hipStream_t st = net->stream;
   NETCHK(celeste::net_reserve(&net->s, batch), "network workspace");
@@ -1003,6 +1027,7 @@ int celeste_net_loss_grad(celeste_net* net, const void* x, const float* t, int b
 
 int celeste_net_forward(celeste_net* net, const void* x, int64_t n, float* y) {
   if (!net || !x || !y || n < 1) return net_fail(CELESTE_E_INVALID, "bad argument");
+  if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) return net_fail(CELESTE_E_INVALID, "x must be 16-byte aligned");
   NETCHK(hipSetDevice(net->device), "set device");
   hipStream_t st = net->stream;
   const int chunk = 4096;

@@ -55,6 +55,15 @@ def test_forward_matches_reference(cb, ctx):
     err = np.max(np.abs(y - yr)) / np.max(np.abs(yr))
     _say("forward rel err", err)
     assert err < 2e-2
+    # an input that is not 16-byte aligned is refused (the first layer reads rows in 16-byte pieces)
+    flat = torch.zeros(70 * 5 * 1024 + 8, dtype=torch.bfloat16, device="cuda")
+    flat[1:1 + xg.numel()] = xg.reshape(-1)
+    with pytest.raises(cb.CelesteError) as ei:
+        net.forward(flat[1:1 + xg.numel()].view(70, 5, 32, 32))
+    assert ei.value.code == cb.E_INVALID
+    # the same values in an aligned copy give the same outputs
+    y2 = net.forward(flat[1:1 + xg.numel()].view(70, 5, 32, 32).clone()).cpu().numpy()
+    assert np.array_equal(y2, y)
     net.close()
 
 
