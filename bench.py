@@ -672,7 +672,8 @@ def main():
         "status": status_counts,
         "phase_ms_per_step": {k[3:]: v for k, v in H["prof"].items() if k.startswith("ms_")},
         "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
-                           "eigendecomposition": st["tr_eigen"]},
+                           "eigendecomposition": st["tr_eigen"], "jacobi_sweeps": st["tr_sweeps"],
+                           "jacobi_sweep_cap": st["tr_sweep_cap"], "newton_steps": st["tr_newton_steps"]},
         "phase_source": "the profiled step (eager launches with HIP events), one per start after the timed steps",
         "starts": {name: summary(r) for name, r in runs.items()},
         "autotune": tune,
@@ -1064,7 +1065,8 @@ def field_bench(args, ctx, net, sur_info, log):
         "sweeps": info["history"], "timings_s_last_step": dict(info["timings"]),
         "pixel_evals_per_s": st["full_px"] / wall,
         "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
-                           "eigendecomposition": st["tr_eigen"]},
+                           "eigendecomposition": st["tr_eigen"], "jacobi_sweeps": st["tr_sweeps"],
+                           "jacobi_sweep_cap": st["tr_sweep_cap"], "newton_steps": st["tr_newton_steps"]},
         "profiled_sweep": {"s": wall_p, "phase_ms": {k[3:]: v for k, v in st_p.items() if k.startswith("ms_")},
                            "kernel_pixel_evals_per_s": st_p["full_px"] / full_s if full_s > 0 else None},
         "roofline": {"kernel": "k_eval_full (value+gradient+Hessian pixel kernel)", "bound": "alu",

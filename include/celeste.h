@@ -151,6 +151,9 @@ typedef struct celeste_stats {
    * the map to parameters) in a surrogate start (CELESTE_OPT_PROFILE only; ms_start then holds the
    * rest of the start: plain start and the evaluation of both starts) */
   double ms_net;
+  /* Jacobi sweeps of the eigendecomposition solves, the solves that reached the 40-sweep cap, and
+   * Newton steps on the multiplier of the boundary solves by Cholesky */
+  int64_t tr_sweeps, tr_sweep_cap, tr_newton_steps;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

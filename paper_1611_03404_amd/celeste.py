@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("ms_lr", ctypes.c_double), ("grad_px", ctypes.c_int64), ("grad_launches", ctypes.c_int64),
                 ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double),
                 ("tr_interior", ctypes.c_int64), ("tr_boundary", ctypes.c_int64), ("tr_eigen", ctypes.c_int64),
-                ("ms_net", ctypes.c_double)]
+                ("ms_net", ctypes.c_double), ("tr_sweeps", ctypes.c_int64), ("tr_sweep_cap", ctypes.c_int64),
+                ("tr_newton_steps", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):

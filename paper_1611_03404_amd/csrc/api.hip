@@ -78,7 +78,7 @@ struct celeste_ctx {
   int vtile_log2 = 3;    // log2 tile width of the value kernel
   DevBuf imgs, items, srcs, tables, partials, img_const, staging, theta, o_elbo, o_grad, o_hess, flag;
   DevBuf st_buf;   // all trust-region state in one allocation
-  DevBuf ctr;      // device counters: pixel evaluations [full, value, grad], subproblem paths [3..5]
+  DevBuf ctr;      // device counters: pixel evaluations [full, value, grad], subproblem paths and work [3..8]
   int profile = 0;
   celeste_stats stats{};
 
@@ -664,8 +664,8 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
-  if (ensure(c->ctr, 6 * sizeof(unsigned long long)) != CELESTE_OK ||
-      hipMemset(c->ctr.p, 0, 6 * sizeof(unsigned long long)) != hipSuccess) {
+  if (ensure(c->ctr, 9 * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, 9 * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipStreamDestroy(c->stream);
     if (c->ctr.p) (void)hipFree(c->ctr.p);
     delete c;
@@ -697,7 +697,7 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
 int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
   HIPCHK(hipSetDevice(c->device));
-  unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
   c->stats.full_px = (int64_t)h[0];
   c->stats.value_px = (int64_t)h[1];
@@ -705,6 +705,9 @@ int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   c->stats.tr_interior = (int64_t)h[3];
   c->stats.tr_boundary = (int64_t)h[4];
   c->stats.tr_eigen = (int64_t)h[5];
+  c->stats.tr_sweeps = (int64_t)h[6];
+  c->stats.tr_sweep_cap = (int64_t)h[7];
+  c->stats.tr_newton_steps = (int64_t)h[8];
   *out = c->stats;
   if (reset) {
     HIPCHK(hipMemset(c->ctr.p, 0, sizeof(h)));

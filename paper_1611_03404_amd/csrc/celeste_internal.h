@@ -216,7 +216,8 @@ struct FitParams {
   double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
   int tr_chol;          // solve the subproblem by Cholesky factorisations where B is positive definite
   unsigned long long* tr_ctr;   // subproblems solved: [0] interior step, [1] boundary step by Cholesky,
-                                // [2] by the eigendecomposition
+                                // [2] by the eigendecomposition; [3] Jacobi sweeps, [4] solves that
+                                // reached the 40-sweep cap, [5] Newton steps on the multiplier
 };
 
 hipError_t launch_fit_init(FitDev st, int n_src, FitParams fp, hipStream_t s);

@@ -3,7 +3,8 @@
 // source).  One wavefront per active source solves the 27x27 FP64 subproblem
 //     maximise g'p + p'Hp/2  subject to |p| <= Delta     (unconstrained coordinates)
 // through a cyclic Jacobi eigendecomposition of B = -H (parallel round-robin
-// ordering, 14 disjoint rotations per round held in LDS), followed by the secular
+// ordering, 14 disjoint rotations per round applied to B in LDS by 2x2 blocks, one
+// barrier after the rotation parameters and one after the update), followed by the secular
 // equation |(B + sI)^{-1} g| = Delta solved by safeguarded Newton on 1/|p(s)|
 // (More-Sorensen), including the hard case.  Where B is positive definite, Cholesky
 // factorisations of B + lam I give the step instead (the interior Newton step, or the
@@ -206,7 +207,8 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         pred = 0.5 * wsum(t < NP ? g[t] * pst[t] : 0.0);
       } else {
         double lam = 0.0;
-        for (int it = 0; it < 30; ++it) {
+        int it = 0;
+        for (; it < 30; ++it) {
           const double pn = sqrt(pn2);
           if (fabs(pn - delta) <= 1e-9 * delta) {
             path = 1;
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
           if (!factor_solve(lam)) break;
           pn2 = wsum(t < NP ? pst[t] * pst[t] : 0.0);
         }
+        if (t == 0 && fp.tr_ctr) atomicAdd(fp.tr_ctr + 5, (unsigned long long)it);
         // predicted gain g'p - p'Bp/2 with (B + lam I) p = g
         if (path == 1) pred = 0.5 * (wsum(t < NP ? g[t] * pst[t] : 0.0) + lam * pn2);
       }
@@ -264,7 +267,8 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __syncthreads();
 
   // ---- cyclic Jacobi, round-robin parallel ordering
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  int sweeps = 0;
+  for (; sweeps < 40; ++sweeps) {
     double off = 0.0, fro = 0.0;
     for (int k = t; k < NPAD * NPAD; k += 64) {
       const int i = k / NPAD, j = k - i * NPAD;
@@ -304,40 +308,58 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         raqq[t] = aqq;
       }
       __syncthreads();
-      // columns: B <- B J
+      // B <- J^T B J and V <- V J in one pass: B by 2x2 blocks (pair a's rows x pair b's columns),
+      // each block read and written by one lane, so no entry is touched twice; an off-diagonal
+      // block is transformed columns first, then rows, and mirrored; a diagonal block takes the
+      // rotated eigenvalue estimates and exact zeros
+      for (int k = t; k < NPAD / 2 + (NPAD / 2) * (NPAD / 2 - 1) / 2; k += 64) {
+        if (k < NPAD / 2) {
+          if (rt[k] != 0.0) {
+            const int p = rp[k], q = rq[k];
+            B[p][p] = rapp[k] - rt[k] * rapq[k];
+            B[q][q] = raqq[k] + rt[k] * rapq[k];
+            B[p][q] = 0.0;
+            B[q][p] = 0.0;
+          }
+          continue;
+        }
+        int a = 0, idx = k - NPAD / 2;
+        while (idx >= NPAD / 2 - 1 - a) {
+          idx -= NPAD / 2 - 1 - a;
+          ++a;
+        }
+        const int b = a + 1 + idx;
+        const int p1 = rp[a], q1 = rq[a], p2 = rp[b], q2 = rq[b];
+        const double c1 = rc[a], s1 = rs[a], c2 = rc[b], s2 = rs[b];
+        const double x00 = B[p1][p2], x01 = B[p1][q2], x10 = B[q1][p2], x11 = B[q1][q2];
+        const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
+        const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
+        const double z00 = c1 * y00 - s1 * y10, z10 = s1 * y00 + c1 * y10;
+        const double z01 = c1 * y01 - s1 * y11, z11 = s1 * y01 + c1 * y11;
+        B[p1][p2] = z00;
+        B[p1][q2] = z01;
+        B[q1][p2] = z10;
+        B[q1][q2] = z11;
+        B[p2][p1] = z00;
+        B[q2][p1] = z01;
+        B[p2][q1] = z10;
+        B[q2][q1] = z11;
+      }
       for (int k = t; k < (NPAD / 2) * NPAD; k += 64) {
         const int pr = k / NPAD, r = k - pr * NPAD;
         const int p = rp[pr], q = rq[pr];
         const double c = rc[pr], sn = rs[pr];
-        const double bp = B[r][p], bq = B[r][q];
-        B[r][p] = c * bp - sn * bq;
-        B[r][q] = sn * bp + c * bq;
         const double vp = V[r][p], vq = V[r][q];
         V[r][p] = c * vp - sn * vq;
         V[r][q] = sn * vp + c * vq;
       }
       __syncthreads();
-      // rows: B <- J^T B
-      for (int k = t; k < (NPAD / 2) * NPAD; k += 64) {
-        const int pr = k / NPAD, r = k - pr * NPAD;
-        const int p = rp[pr], q = rq[pr];
-        const double c = rc[pr], sn = rs[pr];
-        const double bp = B[p][r], bq = B[q][r];
-        B[p][r] = c * bp - sn * bq;
-        B[q][r] = sn * bp + c * bq;
-      }
-      __syncthreads();
-      if (t < NPAD / 2) {
-        const int p = rp[t], q = rq[t];
-        if (rt[t] != 0.0) {
-          B[p][p] = rapp[t] - rt[t] * rapq[t];
-          B[q][q] = raqq[t] + rt[t] * rapq[t];
-          B[p][q] = 0.0;
-          B[q][p] = 0.0;
-        }
-      }
-      __syncthreads();
     }
+  }
+
+  if (t == 0 && fp.tr_ctr) {
+    atomicAdd(fp.tr_ctr + 3, (unsigned long long)sweeps);
+    if (sweeps == 40) atomicAdd(fp.tr_ctr + 4, 1ull);
   }
 
   // ---- eigen-coordinates of g; the eigenvectors are kept for the next iteration's start
