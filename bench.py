@@ -66,12 +66,14 @@ def dtype_str(args, network=True):
 
 
 def flop_full_per_px(K, E, D):
-    """Algorithmic FLOPs of one value+gradient+Hessian pixel evaluation (add/mul 1, FMA 2,
-    exp/log/rcp 1, FP64 accumulate 1), counted from the formulation: star components
-    35 each, 5 per PSF component for the offsets, 84 per galaxy component (Gaussian,
-    Hermite moments to order 4, 18 accumulations), and 1079 per pixel for the shape
-    contractions, rate moments, delta-method weights and the 78 FP64 accumulations."""
-    return 2 + 35 * K + 5 * K + 84 * K * (E + D) + 1079
+    """FLOPs of the kernel's own arithmetic for one value+gradient+Hessian pixel evaluation
+    without exact-zero skipping (add/mul 1, FMA 2, exp/log/rcp 1): star components 35 each,
+    5 per PSF component for the offsets, 84 per galaxy component (Gaussian, Hermite moments
+    to order 4, 18 accumulations), and 661 per pixel, the per-pixel block as compiled (profile
+    mixing, shape contractions, rate moments, delta-method weights, the geometry entries in the
+    basis of the two profile gradients, 12 brightness product sums and the FP32 lane
+    accumulations)."""
+    return 2 + 35 * K + 5 * K + 84 * K * (E + D) + 661
 
 
 def flop_value_per_px(K, E, D):
@@ -474,10 +476,10 @@ def main():
                     help="field workload: Jacobi sweeps (all sources see the previous sweep) or Gauss-Seidel "
                          "sweeps over conflict-free colours")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pixel-kernel launch shapes")
-    ap.add_argument("--persistent", type=int, choices=range(0, 17), default=None, metavar="0..16",
+    ap.add_argument("--persistent", type=int, choices=range(-1, 17), default=None, metavar="-1..16",
                     help="trust-region fits: persistent pixel kernels with this many blocks per compute unit "
-                         "drawing from the device work list, or one block per work item (0); default: the "
-                         "library's")
+                         "drawing from the device work list, as many as the kernel keeps resident (-1), or one "
+                         "block per work item (0); default: the library's (-1)")
     ap.add_argument("--tr-cholesky", type=int, choices=(0, 1), default=None,
                     help="trust-region subproblem: interior Newton step by Cholesky first (1) or always the "
                          "eigendecomposition (0); default: the library's")
@@ -674,6 +676,7 @@ def main():
         "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
                            "eigendecomposition": st["tr_eigen"], "jacobi_sweeps": st["tr_sweeps"],
                            "jacobi_sweep_cap": st["tr_sweep_cap"], "newton_steps": st["tr_newton_steps"]},
+        "fit_grid_blocks": st["fit_grid_blocks"],
         "phase_source": "the profiled step (eager launches with HIP events), one per start after the timed steps",
         "starts": {name: summary(r) for name, r in runs.items()},
         "autotune": tune,
@@ -1067,6 +1070,7 @@ def field_bench(args, ctx, net, sur_info, log):
         "tr_subproblems": {"interior_cholesky": st["tr_interior"], "boundary_cholesky": st["tr_boundary"],
                            "eigendecomposition": st["tr_eigen"], "jacobi_sweeps": st["tr_sweeps"],
                            "jacobi_sweep_cap": st["tr_sweep_cap"], "newton_steps": st["tr_newton_steps"]},
+        "fit_grid_blocks": st["fit_grid_blocks"],
         "profiled_sweep": {"s": wall_p, "phase_ms": {k[3:]: v for k, v in st_p.items() if k.startswith("ms_")},
                            "kernel_pixel_evals_per_s": st_p["full_px"] / full_s if full_s > 0 else None},
         "roofline": {"kernel": "k_eval_full (value+gradient+Hessian pixel kernel)", "bound": "alu",

@@ -82,11 +82,13 @@ enum {                          /* context options (celeste_ctx_set_option) */
   CELESTE_OPT_BLOCK = 2,        /* threads per pixel-kernel block: 128 or 256 (default 256) */
   CELESTE_OPT_USE_GRAPH = 3,    /* batched fit replays a captured HIP graph per iteration (default 1) */
   CELESTE_OPT_PROFILE = 4,      /* 1: time every kernel phase with HIP events (fits run without a graph) */
-  CELESTE_OPT_VARIANT = 5,      /* pixel-kernel variant 0..7 (default 3): bit 0 = two resident waves per
-                                   SIMD (value+gradient+Hessian kernel), bit 1 = loops unrolled for
-                                   6 exp + 8 dev components (both kernels), bit 2 (with bit 1) = the
-                                   J^T W J part of the Hessian summed on the matrix cores; all
-                                   variants compute the same arithmetic */
+  CELESTE_OPT_VARIANT = 5,      /* pixel-kernel variant 0..7 (default 3): bit 0 = register budget of
+                                   three resident waves per SIMD for the value+gradient+Hessian
+                                   kernel (two with bit 2; otherwise the kernel takes two), bit 1 =
+                                   loops unrolled for 6 exp + 8 dev components (both kernels), bit 2
+                                   (with bit 1) = the J^T W J part of the Hessian summed on the
+                                   matrix cores; all variants compute the same quantities, to FP32
+                                   rounding */
   CELESTE_OPT_TILE_W = 6,       /* width of the 64-pixel tile a wavefront of the value+gradient+Hessian
                                    kernel takes per step: 8, 16, 32 or 64 (default 8) */
   CELESTE_OPT_VALUE_BLOCK = 7,  /* threads per value-kernel block: 128 or 256 (default 256) */
@@ -99,13 +101,15 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    the context's choice (127 where exact, else 160; the default), or
                                    1 to skip nothing: every component, galaxy group and tile is
                                    evaluated (the reference the skips are tested against) */
-  CELESTE_OPT_PERSISTENT = 10,  /* trust-region fits (celeste_newton_fit, celeste_batch_fit): n in
-                                   1..16 = before each value+gradient+Hessian pass the work items of
-                                   the sources still being fitted are compacted into a device list,
-                                   and n blocks per compute unit of a persistent pixel kernel draw
-                                   them in turn (grids do not shrink otherwise: blocks of finished
-                                   sources exit at once; default 2); 0 = one block per work item.
-                                   Results are bitwise the same */
+  CELESTE_OPT_PERSISTENT = 10,  /* trust-region fits (celeste_newton_fit, celeste_batch_fit): before
+                                   each value+gradient+Hessian pass the work items of the sources
+                                   still being fitted are compacted into a device list, and a
+                                   persistent grid of the pixel kernel draws them in turn (grids do
+                                   not shrink otherwise: blocks of finished sources exit at once).
+                                   n in 1..16 = n blocks per compute unit; -1 (default) = as many
+                                   blocks per compute unit as the launched kernel instance keeps
+                                   resident (its register budget, CELESTE_OPT_VARIANT bit 0);
+                                   0 = one block per work item. Results are bitwise the same */
   CELESTE_OPT_TR_CHOLESKY = 11, /* trust-region subproblem (section III-B): 1 = where -H is positive
                                    definite, Cholesky factorisations of -H + lam I give the exact
                                    solution (lam = 0 for a Newton step inside the region, else
@@ -154,6 +158,9 @@ typedef struct celeste_stats {
   /* Jacobi sweeps of the eigendecomposition solves, the solves that reached the 40-sweep cap, and
    * Newton steps on the multiplier of the boundary solves by Cholesky */
   int64_t tr_sweeps, tr_sweep_cap, tr_newton_steps;
+  /* blocks of the last trust-region fit's persistent value+gradient+Hessian grid (0: one block per
+   * work item; CELESTE_OPT_PERSISTENT) */
+  int64_t fit_grid_blocks;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;

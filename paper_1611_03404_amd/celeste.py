@@ -71,7 +71,7 @@ class Stats(ctypes.Structure):
                 ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double),
                 ("tr_interior", ctypes.c_int64), ("tr_boundary", ctypes.c_int64), ("tr_eigen", ctypes.c_int64),
                 ("ms_net", ctypes.c_double), ("tr_sweeps", ctypes.c_int64), ("tr_sweep_cap", ctypes.c_int64),
-                ("tr_newton_steps", ctypes.c_int64)]
+                ("tr_newton_steps", ctypes.c_int64), ("fit_grid_blocks", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):

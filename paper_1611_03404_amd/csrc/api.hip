@@ -91,7 +91,9 @@ struct celeste_ctx {
   DevBuf lfact;                                    // log n! table of the pixel constants
   DevBuf lb_buf;                                   // L-BFGS state beyond the fit state
   DevBuf imgs_s, items_s, srcs_s, partials_s;      // the pixel-subsampled pack of a fit's early phase
-  int persistent = 2;                              // fits: persistent pixel-kernel blocks per CU (0: off)
+  int persistent = -1;                             // fits: persistent pixel-kernel blocks per CU (0: off,
+                                                   // -1: as many as the kernel instance keeps resident)
+  int pgrid = 0;                                   // the current fit's persistent grid (blocks)
   int tr_chol = 1;                                 // fits: subproblem by Cholesky where -H is positive definite
   int fp64_sums = 0;                               // value+gradient+Hessian kernel: FP64 sums per tile step
   int n_cu = 0;                                    // compute units of the device
@@ -768,7 +770,8 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
       c->vblock = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_PERSISTENT:
-      if (value < 0 || value > 16) return fail(CELESTE_E_INVALID, "persistent blocks per compute unit must be 0..16");
+      if (value < -1 || value > 16)
+        return fail(CELESTE_E_INVALID, "persistent blocks per compute unit must be -1..16");
       c->persistent = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_FP64_SUMS:
@@ -1158,8 +1161,19 @@ int check_opts(const celeste_fit_opts* o) {
 
 // Enqueues one trust-region iteration over all sources (each kernel skips sources
 // whose flag is clear).
-// Persistent-grid size of the pixel kernels: the chosen number of resident blocks per compute unit.
-int pgrid_items(const celeste_ctx* ctx) { return ctx->n_cu * ctx->persistent; }
+// Persistent-grid size of the value+gradient+Hessian kernel for a fit over P: the compute units
+// times the chosen blocks per compute unit, or (persistent < 0) times the blocks the launched kernel
+// instance keeps resident on one.
+int fit_grid(celeste_ctx* ctx, const Packed& P) {
+  int bpc = ctx->persistent;
+  if (bpc < 0) {
+    HIPCHK(eval_full_blocks_per_cu(ctx->block, full_variant(ctx), P.prof.n_exp, P.prof.n_dev, &bpc));
+    bpc = std::max(1, bpc);
+  }
+  ctx->pgrid = ctx->n_cu * bpc;
+  ctx->stats.fit_grid_blocks = ctx->pgrid;
+  return CELESTE_OK;
+}
 
 // The device work queue of a fit over P's work items (persistent mode).
 int fit_queue(celeste_ctx* ctx, const Packed& P, WorkQueue* q) {
@@ -1184,7 +1198,7 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, tables, P.tstride, st));
   T->mark(1, st);
   HIPCHK(launch_eval_full(items, P.n_items, imgs, tables, P.tstride, P.prof.n_exp, P.prof.n_dev, F.need_full, parts,
-                          ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, nullptr, Q, pgrid_items(ctx)));
+                          ctx->block, full_variant(ctx), ctx->tile_log2, ctx->e_zero, st, nullptr, Q, ctx->pgrid));
   T->mark(2, st);
   HIPCHK(launch_reduce_full(srcs, P.n_src, imgs, parts, ic, F.theta, P.prior, F.need_full, F.f_full, F.g, F.H,
                             ctr_full(ctx), st));
@@ -1439,7 +1453,11 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   const int poll = (batched && !T.on) ? std::max(1, o->poll_every) : 1;
   const bool graph = batched && ctx->use_graph && !T.on;
   WorkQueue Q;
-  if (ctx->persistent) CHK(fit_queue(ctx, P, &Q));
+  ctx->stats.fit_grid_blocks = 0;
+  if (ctx->persistent) {
+    CHK(fit_queue(ctx, P, &Q));
+    CHK(fit_grid(ctx, P));
+  }
   const WorkQueue* Qp = ctx->persistent ? &Q : nullptr;
   CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
                [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t, Qp); },

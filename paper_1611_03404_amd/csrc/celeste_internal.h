@@ -137,6 +137,9 @@ hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* im
                             int block, int variant, int tw_log2, float e_zero, hipStream_t st,
                             const int* kept = nullptr, const WorkQueue* queue = nullptr,
                             int persistent_grid = 0);
+// Blocks of the value+gradient+Hessian kernel instance for (block, variant, n_exp, n_dev) that one
+// compute unit keeps resident (register and LDS budget of the instance).
+hipError_t eval_full_blocks_per_cu(int block, int variant, int n_exp, int n_dev, int* blocks);
 // Value and z-gradient only: one partial of NGRAD = 1 + NZ doubles per work item (value, 11
 // gradient entries); arguments as launch_eval_full (variant: bit 1 only).
 constexpr int NGRAD = 1 + NZ;

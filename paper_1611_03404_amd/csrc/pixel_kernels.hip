@@ -213,6 +213,68 @@ struct TileMap {
 
 constexpr int tri(int i, int j) { return i * NZ - (i * (i - 1)) / 2 + (j - i); }
 
+// Brightness entries from product sums. The brightness z-derivatives of T and U are per-image
+// constants times the profile values Gs, Gg:
+//   dT/dz_i = ts_i Gs + tg_i Gg,   dU/dz_i = us_i Gs^2 + ug_i Gg^2 + usg_i Gs Gg   (i = 0..4),
+// and so are d2T/dz_i dz_j and d2U/dz_i dz_j. The brightness gradient entries wT dT_i + wU dU_i
+// and the brightness x brightness Hessian entries
+//   wTT dT_i dT_j + wTU (dT_i dU_j + dU_i dT_j) + wT d2T_ij + wU d2U_ij
+// are therefore fixed combinations of NBP per-pixel products
+//   wT Gs, wT Gg, wU Gs^2, wU Gg^2, wU Gs Gg, wTT Gs^2, wTT Gs Gg, wTT Gg^2,
+//   wTU Gs^3, wTU Gs^2 Gg, wTU Gs Gg^2, wTU Gg^3:
+// the pixel loop sums the products (in 12 of the 20 brightness accumulator slots, the other 8
+// stay 0) and the work item's epilogue forms the 20 entries from the sums in FP64.
+constexpr int NBP = 12;
+__device__ __forceinline__ constexpr int bp_slot(int p) {
+  return p < 5 ? p : p < 10 ? NZ + (p - 5) : p == 10 ? NZ + tri(1, 1) : NZ + tri(1, 2);
+}
+
+// Entry e of a partial (1 + e is its index: e < 5 a brightness gradient entry, e = NZ + tri(i, j)
+// with i <= j < 5 a brightness x brightness entry) from the product sums P (indexed by
+// accumulator slot); other entries keep v.
+__device__ double bright_entry(const float* __restrict__ T, int e, const double* P, double v) {
+  const double cs = T[CS], cg = T[CG], Ks = T[KS], Kg = T[KG], Ksg = T[KSG];
+  const double ts[5] = {T[MU_S], cs, 0.5 * cs, 0.0, 0.0};
+  const double tg[5] = {-(double)T[MU_G], 0.0, 0.0, cg, 0.5 * cg};
+  const double us[5] = {T[KA_S], 2.0 * Ks, T[KV_S], 0.0, 0.0};
+  const double ug[5] = {T[KA_G], 0.0, 0.0, 2.0 * Kg, T[KV_G]};
+  const double usg[5] = {T[KA_SG], Ksg, 0.5 * Ksg, Ksg, 0.5 * Ksg};
+  double p[NBP];
+#pragma unroll
+  for (int k = 0; k < NBP; ++k) p[k] = P[bp_slot(k)];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    if (e == i) v = ts[i] * p[0] + tg[i] * p[1] + us[i] * p[2] + ug[i] * p[3] + usg[i] * p[4];
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      if (e != NZ + tri(i, j)) continue;
+      // second-order parts d2T_ij = a Gs + b Gg, d2U_ij = c Gs^2 + d Gg^2 + f Gs Gg
+      double a = 0.0, b = 0.0, c = 0.0, d = 0.0, f = 0.0;
+      if (i == 0 && j == 0) { c = T[KS_AA]; d = T[KG_AA]; f = T[KSG_AA]; }
+      if (i == 0 && j == 1) { a = ts[0]; c = T[KS_AM]; f = T[KSG_AM]; }
+      if (i == 0 && j == 2) { a = 0.5 * ts[0]; c = T[KS_AV]; f = T[KSG_AV]; }
+      if (i == 0 && j == 3) { b = tg[0]; d = T[KG_AM]; f = T[KSG_AM]; }
+      if (i == 0 && j == 4) { b = 0.5 * tg[0]; d = T[KG_AV]; f = T[KSG_AV]; }
+      if (i == 1 && j == 1) { a = cs; c = T[KS_MM]; f = Ksg; }
+      if (i == 1 && j == 2) { a = 0.5 * cs; c = T[KS_MV]; f = 0.5 * Ksg; }
+      if (i == 1 && j == 3) f = Ksg;
+      if (i == 1 && j == 4) f = 0.5 * Ksg;
+      if (i == 2 && j == 2) { a = 0.25 * cs; c = T[KS_VV]; f = 0.25 * Ksg; }
+      if (i == 2 && j == 3) f = 0.5 * Ksg;
+      if (i == 2 && j == 4) f = 0.25 * Ksg;
+      if (i == 3 && j == 3) { b = cg; d = T[KG_MM]; f = Ksg; }
+      if (i == 3 && j == 4) { b = 0.5 * cg; d = T[KG_MV]; f = 0.5 * Ksg; }
+      if (i == 4 && j == 4) { b = 0.25 * cg; d = T[KG_VV]; f = 0.25 * Ksg; }
+      v = a * p[0] + b * p[1] + c * p[2] + d * p[3] + f * p[4] + ts[i] * ts[j] * p[5] +
+          (ts[i] * tg[j] + tg[i] * ts[j]) * p[6] + tg[i] * tg[j] * p[7] + (ts[i] * us[j] + us[i] * ts[j]) * p[8] +
+          (ts[i] * usg[j] + tg[i] * us[j] + usg[i] * ts[j] + us[i] * tg[j]) * p[9] +
+          (ts[i] * ug[j] + tg[i] * usg[j] + ug[i] * ts[j] + usg[i] * tg[j]) * p[10] +
+          (tg[i] * ug[j] + ug[i] * tg[j]) * p[11];
+    }
+  }
+  return v;
+}
+
 // Wavefront sum of 80 lane values by recursive halving (masks 32, 16, 8, 4) and a
 // butterfly over the last 4 lanes: on return the lanes of each quad hold the wavefront
 // sums of the 5 entries starting at quad_base(lane) = 40*b5 + 20*b4 + 10*b3 + 5*b2
@@ -501,74 +563,152 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
       const float lEV = xr3;
       const float wT = io * lE, wU = io2 * lV, wTT = io2 * lEE, wTU = io3 * lEV;
 
-      // ---- sparse second-order part S = wT d2T + wU d2U (upper triangle)
-      float S[NZ * (NZ + 1) / 2];
-      S[tri(0, 0)] = wU * fmaf(T[KS_AA], Gs2, fmaf(T[KG_AA], Gg2, T[KSG_AA] * Gsg));
-      S[tri(0, 1)] = fmaf(wT, mus * Gs, wU * fmaf(T[KS_AM], Gs2, T[KSG_AM] * Gsg));
-      S[tri(0, 2)] = fmaf(wT, 0.5f * mus * Gs, wU * fmaf(T[KS_AV], Gs2, T[KSG_AV] * Gsg));
-      S[tri(0, 3)] = fmaf(wT, -mug * Gg, wU * fmaf(T[KG_AM], Gg2, T[KSG_AM] * Gsg));
-      S[tri(0, 4)] = fmaf(wT, -0.5f * mug * Gg, wU * fmaf(T[KG_AV], Gg2, T[KSG_AV] * Gsg));
-      S[tri(1, 1)] = fmaf(wT, Tz[1], wU * fmaf(T[KS_MM], Gs2, Ksg * Gsg));
-      S[tri(1, 2)] = fmaf(wT, 0.5f * Tz[1], wU * fmaf(T[KS_MV], Gs2, 0.5f * Ksg * Gsg));
-      S[tri(1, 3)] = wU * Ksg * Gsg;
-      S[tri(1, 4)] = 0.5f * wU * Ksg * Gsg;
-      S[tri(2, 2)] = fmaf(wT, 0.25f * Tz[1], wU * fmaf(T[KS_VV], Gs2, 0.25f * Ksg * Gsg));
-      S[tri(2, 3)] = 0.5f * wU * Ksg * Gsg;
-      S[tri(2, 4)] = 0.25f * wU * Ksg * Gsg;
-      S[tri(3, 3)] = fmaf(wT, Tz[3], wU * fmaf(T[KG_MM], Gg2, Ksg * Gsg));
-      S[tri(3, 4)] = fmaf(wT, 0.5f * Tz[3], wU * fmaf(T[KG_MV], Gg2, 0.5f * Ksg * Gsg));
-      S[tri(4, 4)] = fmaf(wT, 0.25f * Tz[3], wU * fmaf(T[KG_VV], Gg2, 0.25f * Ksg * Gsg));
-      {
-        // brightness x geometry block
-        const float dks[5] = {T[KA_S], 2.f * Ks, T[KV_S], 0.f, 0.f};
-        const float dkg[5] = {T[KA_G], 0.f, 0.f, 2.f * Kg, T[KV_G]};
-        const float dksg[5] = {T[KA_SG], Ksg, 0.5f * Ksg, Ksg, 0.5f * Ksg};
-        const float cts[5] = {mus, cs, 0.5f * cs, 0.f, 0.f};
-        const float ctg[5] = {-mug, 0.f, 0.f, cg, 0.5f * cg};
+      // ---- value in FP64 per lane; gradient and second-order part in the per-lane FP32 sums
+      val += (double)lval;
+      const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
+      if constexpr (!MF) {
+        // The geometry derivatives of T and U combine two vectors: a, the star's shape gradient
+        // (zero beyond the position), and b = dG, the galaxy's:
+        //   dT/dy = cs a + cg b,   dU/dy = rhos a + rhog b.
+        // Every geometry entry of the gradient and Hessian terms is therefore a short combination
+        // of a and b; it is formed in that basis, with no products against the zeros of a. Each
+        // entry still reaches its FP32 lane sum by a single addition.
+        const float* a = dGs;
+        const float* b = dG;
+        // brightness gradient and brightness x brightness entries: the product sums (see bp_slot)
+        {
+          const float tS = wTU * Gs2, tG = wTU * Gg2;
+          accf[bp_slot(0)] = fmaf(wT, Gs, accf[bp_slot(0)]);
+          accf[bp_slot(1)] = fmaf(wT, Gg, accf[bp_slot(1)]);
+          accf[bp_slot(2)] = fmaf(wU, Gs2, accf[bp_slot(2)]);
+          accf[bp_slot(3)] = fmaf(wU, Gg2, accf[bp_slot(3)]);
+          accf[bp_slot(4)] = fmaf(wU, Gsg, accf[bp_slot(4)]);
+          accf[bp_slot(5)] = fmaf(wTT, Gs2, accf[bp_slot(5)]);
+          accf[bp_slot(6)] = fmaf(wTT, Gsg, accf[bp_slot(6)]);
+          accf[bp_slot(7)] = fmaf(wTT, Gg2, accf[bp_slot(7)]);
+          accf[bp_slot(8)] = fmaf(tS, Gs, accf[bp_slot(8)]);
+          accf[bp_slot(9)] = fmaf(tS, Gg, accf[bp_slot(9)]);
+          accf[bp_slot(10)] = fmaf(tG, Gs, accf[bp_slot(10)]);
+          accf[bp_slot(11)] = fmaf(tG, Gg, accf[bp_slot(11)]);
+        }
+        // geometry gradient
+#pragma unroll
+        for (int k = 0; k < 2; ++k) accf[5 + k] += fmaf(als, a[k], alg * b[k]);
+#pragma unroll
+        for (int k = 2; k < 6; ++k) accf[5 + k] = fmaf(alg, b[k], accf[5 + k]);
+
+        // brightness x geometry: entry (i, k) = P_i a_k + Q_i b_k. The geometry parts of hT and hU
+        // are hTa a + hTb b and hUa a + hUb b; sa_i and sb_i are the a and b coefficients of the
+        // second-order part.
+        const float hTa = fmaf(wTT, cs, wTU * rhos), hTb = fmaf(wTT, cg, wTU * rhog);
+        const float hUa = wTU * cs, hUb = wTU * cg;
+        const float sa[5] = {fmaf(wT, mus, wU * fmaf(2.f * T[KA_S], Gs, T[KA_SG] * Gg)),
+                             fmaf(wT, cs, wU * fmaf(4.f * Ks, Gs, Ksg * Gg)),
+                             fmaf(wT, 0.5f * cs, wU * fmaf(2.f * T[KV_S], Gs, 0.5f * Ksg * Gg)),
+                             wU * (Ksg * Gg),
+                             wU * (0.5f * Ksg * Gg)};
+        const float sb[5] = {fmaf(wT, -mug, wU * fmaf(2.f * T[KA_G], Gg, T[KA_SG] * Gs)),
+                             wU * (Ksg * Gs),
+                             wU * (0.5f * Ksg * Gs),
+                             fmaf(wT, cg, wU * fmaf(4.f * Kg, Gg, Ksg * Gs)),
+                             fmaf(wT, 0.5f * cg, wU * fmaf(2.f * T[KV_G], Gg, 0.5f * Ksg * Gs))};
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-          const float sgs = fmaf(wT, cts[i], wU * fmaf(2.f * dks[i], Gs, dksg[i] * Gg));
-          const float sgg = fmaf(wT, ctg[i], wU * fmaf(2.f * dkg[i], Gg, dksg[i] * Gs));
+          const float P = fmaf(Tz[i], hTa, fmaf(Uz[i], hUa, sa[i]));
+          const float Q = fmaf(Tz[i], hTb, fmaf(Uz[i], hUb, sb[i]));
 #pragma unroll
-          for (int k = 0; k < 6; ++k) {
-            const float gs = k < 2 ? dGs[k] : 0.f;
-            S[tri(i, 5 + k)] = fmaf(sgs, gs, sgg * dG[k]);
-          }
+          for (int k = 0; k < 2; ++k) accf[NZ + tri(i, 5 + k)] += fmaf(P, a[k], Q * b[k]);
+#pragma unroll
+          for (int k = 2; k < 6; ++k) accf[NZ + tri(i, 5 + k)] = fmaf(Q, b[k], accf[NZ + tri(i, 5 + k)]);
         }
-        // geometry x geometry block
-        const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
+
+        // geometry x geometry: entry (k, l) = m_aa a_k a_l + m_ab (a_k b_l + b_k a_l) + m_bb b_k b_l
+        //   + als d2Gs_kl + alg d2G_kl, written as a_k v_l + b_k u_l + ...
+        const float maa = fmaf(cs, hTa, fmaf(rhos, hUa, 2.f * wU * Ks));
+        const float mab = fmaf(cs, hTb, fmaf(rhos, hUb, wU * Ksg));
+        const float mbb = fmaf(cg, hTb, fmaf(rhog, hUb, 2.f * wU * Kg));
+        float u[6], v[6];
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+          u[l] = l < 2 ? fmaf(mab, a[l], mbb * b[l]) : mbb * b[l];
+          v[l] = l < 2 ? fmaf(maa, a[l], mab * b[l]) : mab * b[l];
+        }
         const float d2Gs[3] = {s2xx, s2xy, s2yy};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
 #pragma unroll
           for (int l = k; l < 6; ++l) {
-            const float gsk = k < 2 ? dGs[k] : 0.f, gsl = l < 2 ? dGs[l] : 0.f;
-            const float hs = (k < 2 && l < 2) ? d2Gs[k + l] : 0.f;
-            float v = fmaf(als, hs, alg * d2G[k][l]);
-            const float q =
-                fmaf(2.f * Ks, gsk * gsl, fmaf(2.f * Kg, dG[k] * dG[l], Ksg * fmaf(gsk, dG[l], gsl * dG[k])));
-            S[tri(5 + k, 5 + l)] = fmaf(wU, q, v);
+            float& h = accf[NZ + tri(5 + k, 5 + l)];
+            if (k == 2 && l == 2) {
+              h = fmaf(u[2], b[2], h);   // d2G[2][2] = 0: e_dev enters G linearly
+            } else {
+              float e = alg * d2G[k][l];
+              if (k < 2 && l < 2) e = fmaf(als, d2Gs[k + l], e);
+              e = fmaf(u[l], b[k], e);
+              if (k < 2) e = fmaf(v[l], a[k], e);
+              h += e;
+            }
           }
         }
-      }
-
-      // ---- value in FP64 per lane; gradient and second-order part in the per-lane FP32 sums
-      val += (double)lval;
-      float hT[NZ], hU[NZ];
-#pragma unroll
-      for (int j = 0; j < NZ; ++j) {
-        accf[j] += fmaf(wT, Tz[j], wU * Uz[j]);
-        hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
-        hU[j] = wTU * Tz[j];
-      }
-      if constexpr (!MF) {
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) {
-#pragma unroll
-          for (int j = i; j < NZ; ++j)
-            accf[NZ + tri(i, j)] += fmaf(Tz[i], hT[j], fmaf(Uz[i], hU[j], S[tri(i, j)]));
-        }
       } else {
+        // the second-order entries, then J^T W J by MFMA
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) accf[j] += fmaf(wT, Tz[j], wU * Uz[j]);
+        // second-order part wT d2T + wU d2U of the brightness x brightness entries (upper triangle)
+        float S[NZ * (NZ + 1) / 2];
+        S[tri(0, 0)] = wU * fmaf(T[KS_AA], Gs2, fmaf(T[KG_AA], Gg2, T[KSG_AA] * Gsg));
+        S[tri(0, 1)] = fmaf(wT, mus * Gs, wU * fmaf(T[KS_AM], Gs2, T[KSG_AM] * Gsg));
+        S[tri(0, 2)] = fmaf(wT, 0.5f * mus * Gs, wU * fmaf(T[KS_AV], Gs2, T[KSG_AV] * Gsg));
+        S[tri(0, 3)] = fmaf(wT, -mug * Gg, wU * fmaf(T[KG_AM], Gg2, T[KSG_AM] * Gsg));
+        S[tri(0, 4)] = fmaf(wT, -0.5f * mug * Gg, wU * fmaf(T[KG_AV], Gg2, T[KSG_AV] * Gsg));
+        S[tri(1, 1)] = fmaf(wT, Tz[1], wU * fmaf(T[KS_MM], Gs2, Ksg * Gsg));
+        S[tri(1, 2)] = fmaf(wT, 0.5f * Tz[1], wU * fmaf(T[KS_MV], Gs2, 0.5f * Ksg * Gsg));
+        S[tri(1, 3)] = wU * Ksg * Gsg;
+        S[tri(1, 4)] = 0.5f * wU * Ksg * Gsg;
+        S[tri(2, 2)] = fmaf(wT, 0.25f * Tz[1], wU * fmaf(T[KS_VV], Gs2, 0.25f * Ksg * Gsg));
+        S[tri(2, 3)] = 0.5f * wU * Ksg * Gsg;
+        S[tri(2, 4)] = 0.25f * wU * Ksg * Gsg;
+        S[tri(3, 3)] = fmaf(wT, Tz[3], wU * fmaf(T[KG_MM], Gg2, Ksg * Gsg));
+        S[tri(3, 4)] = fmaf(wT, 0.5f * Tz[3], wU * fmaf(T[KG_MV], Gg2, 0.5f * Ksg * Gsg));
+        S[tri(4, 4)] = fmaf(wT, 0.25f * Tz[3], wU * fmaf(T[KG_VV], Gg2, 0.25f * Ksg * Gsg));
+        float hT[NZ], hU[NZ];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+          hT[j] = fmaf(wTT, Tz[j], wTU * Uz[j]);
+          hU[j] = wTU * Tz[j];
+        }
+        {
+          // brightness x geometry block
+          const float dks[5] = {T[KA_S], 2.f * Ks, T[KV_S], 0.f, 0.f};
+          const float dkg[5] = {T[KA_G], 0.f, 0.f, 2.f * Kg, T[KV_G]};
+          const float dksg[5] = {T[KA_SG], Ksg, 0.5f * Ksg, Ksg, 0.5f * Ksg};
+          const float cts[5] = {mus, cs, 0.5f * cs, 0.f, 0.f};
+          const float ctg[5] = {-mug, 0.f, 0.f, cg, 0.5f * cg};
+#pragma unroll
+          for (int i = 0; i < 5; ++i) {
+            const float sgs = fmaf(wT, cts[i], wU * fmaf(2.f * dks[i], Gs, dksg[i] * Gg));
+            const float sgg = fmaf(wT, ctg[i], wU * fmaf(2.f * dkg[i], Gg, dksg[i] * Gs));
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              const float gs = k < 2 ? dGs[k] : 0.f;
+              S[tri(i, 5 + k)] = fmaf(sgs, gs, sgg * dG[k]);
+            }
+          }
+          // geometry x geometry block
+          const float d2Gs[3] = {s2xx, s2xy, s2yy};
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+#pragma unroll
+            for (int l = k; l < 6; ++l) {
+              const float gsk = k < 2 ? dGs[k] : 0.f, gsl = l < 2 ? dGs[l] : 0.f;
+              const float hs = (k < 2 && l < 2) ? d2Gs[k + l] : 0.f;
+              float v = fmaf(als, hs, alg * d2G[k][l]);
+              const float q =
+                  fmaf(2.f * Ks, gsk * gsl, fmaf(2.f * Kg, dG[k] * dG[l], Ksg * fmaf(gsk, dG[l], gsl * dG[k])));
+              S[tri(5 + k, 5 + l)] = fmaf(wU, q, v);
+            }
+          }
+        }
 #pragma unroll
         for (int t = 0; t < NZ * (NZ + 1) / 2; ++t) accf[NZ + t] += S[t];
         // ---- J^T W J over the tile: C = sum_k A[:, k] B[k, :], k = 4 m + kq over (pixel, part)
@@ -643,7 +783,17 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_eval_full(const WorkItem* __res
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < BLOCK / 64; ++k) s += red[k][threadIdx.x];
-    partials[(size_t)it * NACC + threadIdx.x] = s;
+    if constexpr (MF)
+      partials[(size_t)it * NACC + threadIdx.x] = s;
+    else
+      red[0][threadIdx.x] = s;   // each thread reads and writes only its own column here
+  }
+  if constexpr (!MF) {
+    // the brightness entries from the product sums (the other entries pass through)
+    __syncthreads();
+    if (threadIdx.x < NACC)
+      partials[(size_t)it * NACC + threadIdx.x] =
+          bright_entry(T, (int)threadIdx.x - 1, red[0] + 1, red[0][threadIdx.x]);
   }
   }   // items
 }
@@ -838,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
     const float Tv = fmaf(cs, Gs, cg * Gg);
     const float Uv = fmaf(Ks, Gs2, fmaf(Kg, Gg2, Ksg * Gsg));
     const float rhos = fmaf(2.f * Ks, Gs, Ksg * Gg), rhog = fmaf(2.f * Kg, Gg, Ksg * Gs);
-    float Tz[NZ], Uz[NZ];
+    float Tz[5], Uz[5];
     Tz[0] = fmaf(mus, Gs, -mug * Gg);
     Tz[1] = cs * Gs;
     Tz[2] = 0.5f * Tz[1];
@@ -850,12 +1000,6 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
     Uz[3] = fmaf(2.f * Kg, Gg2, Ksg * Gsg);
     Uz[4] = fmaf(T[KV_G], Gg2, 0.5f * Ksg * Gsg);
     const float dGs[2] = {s1x, s1y};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float gs = k < 2 ? dGs[k] : 0.f;
-      Tz[5 + k] = fmaf(cs, gs, cg * dG[k]);
-      Uz[5 + k] = fmaf(rhos, gs, rhog * dG[k]);
-    }
     const float E = fmaf(io, Tv, ebg);
     const float V = fmaf(io2, Uv, vbg);
     const float rE = __builtin_amdgcn_rcpf(E);
@@ -864,7 +1008,13 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
     const float wT = io * fmaf(x - E, rE, V * xr3), wU = io2 * (-0.5f * xr2);
     acc[0] += (double)lval;
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) acc[1 + j] += (double)fmaf(wT, Tz[j], wU * Uz[j]);
+    for (int j = 0; j < 5; ++j) acc[1 + j] += (double)fmaf(wT, Tz[j], wU * Uz[j]);
+    // geometry: dT/dy = cs dGs + cg dG and dU/dy = rhos dGs + rhog dG, dGs zero beyond the position
+    const float als = fmaf(wT, cs, wU * rhos), alg = fmaf(wT, cg, wU * rhog);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) acc[6 + k] += (double)fmaf(als, dGs[k], alg * dG[k]);
+#pragma unroll
+    for (int k = 2; k < 6; ++k) acc[6 + k] += (double)(alg * dG[k]);
   }
   // fixed-order reduction: wavefront butterfly, then the waves in index order
 #pragma unroll
@@ -887,53 +1037,54 @@ __global__ __launch_bounds__(BLOCK) void k_eval_grad(const WorkItem* __restrict_
 
 }  // namespace
 
+namespace {
+using FullKernel = decltype(&k_eval_full<256, 1, 6, 8, false, false>);
+
+// The value+gradient+Hessian kernel instance for (block, variant). Variant bits: 0 = the higher
+// occupancy register budget (3 resident waves per SIMD for the vector kernels, 2 with the
+// matrix-core J^T W J; otherwise the compiler's choice, 2 waves per SIMD for this kernel), 1 =
+// mixture loops unrolled for 6 exp + 8 dev components, 2 = J^T W J on the matrix cores, 3 = FP64
+// lane sums.
+FullKernel full_kernel(int block, int variant, int n_exp, int n_dev) {
+  const bool hi = (variant & 1) != 0;
+  const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
+  const bool s64 = (variant & 8) != 0;
+  const bool mf = (variant & 4) != 0 && unroll && !s64;
+  if (block == 128) {
+    if (s64) {
+      if (unroll) return hi ? &k_eval_full<128, 3, 6, 8, false, true> : &k_eval_full<128, 1, 6, 8, false, true>;
+      return hi ? &k_eval_full<128, 3, 0, 0, false, true> : &k_eval_full<128, 1, 0, 0, false, true>;
+    }
+    if (mf) return hi ? &k_eval_full<128, 2, 6, 8, true, false> : &k_eval_full<128, 1, 6, 8, true, false>;
+    if (unroll) return hi ? &k_eval_full<128, 3, 6, 8, false, false> : &k_eval_full<128, 1, 6, 8, false, false>;
+    return hi ? &k_eval_full<128, 3, 0, 0, false, false> : &k_eval_full<128, 1, 0, 0, false, false>;
+  }
+  if (s64) {
+    if (unroll) return hi ? &k_eval_full<256, 3, 6, 8, false, true> : &k_eval_full<256, 1, 6, 8, false, true>;
+    return hi ? &k_eval_full<256, 3, 0, 0, false, true> : &k_eval_full<256, 1, 0, 0, false, true>;
+  }
+  if (mf) return hi ? &k_eval_full<256, 2, 6, 8, true, false> : &k_eval_full<256, 1, 6, 8, true, false>;
+  if (unroll) return hi ? &k_eval_full<256, 3, 6, 8, false, false> : &k_eval_full<256, 1, 6, 8, false, false>;
+  return hi ? &k_eval_full<256, 3, 0, 0, false, false> : &k_eval_full<256, 1, 0, 0, false, false>;
+}
+}  // namespace
+
 hipError_t launch_eval_full(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,
                             int n_exp, int n_dev, const int* src_flag, double* partials, int block, int variant,
                             int tw_log2, float e_zero, hipStream_t st, const int* kept, const WorkQueue* queue,
                             int persistent_grid) {
   if (n_items <= 0) return hipSuccess;
-  const bool occ2 = (variant & 1) != 0;
-  const bool unroll = (variant & 2) != 0 && n_exp == 6 && n_dev == 8;
-  const bool s64 = (variant & 8) != 0;
-  const bool mf = (variant & 4) != 0 && unroll && !s64;
   const WorkQueue q = queue ? *queue : WorkQueue{};
   const dim3 g(queue ? std::min(n_items, persistent_grid) : n_items);
-#define CELESTE_LAUNCH_FULL(B, W, E, D, M, S) \
-  hipLaunchKernelGGL((k_eval_full<B, W, E, D, M, S>), g, dim3(B), 0, st, items, imgs, tables, tstride, n_exp, \
-                     n_dev, src_flag, tw_log2, e_zero, kept, partials, q)
-  if (s64) {
-    if (block == 128) {
-      if (unroll) {
-        if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false, true); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false, true);
-      } else {
-        if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false, true); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false, true);
-      }
-    } else {
-      if (unroll) {
-        if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false, true); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false, true);
-      } else {
-        if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false, true); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false, true);
-      }
-    }
-  } else if (block == 128) {
-    if (mf) {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, true, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, true, false);
-    } else if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 6, 8, false, false); else CELESTE_LAUNCH_FULL(128, 1, 6, 8, false, false);
-    } else {
-      if (occ2) CELESTE_LAUNCH_FULL(128, 2, 0, 0, false, false); else CELESTE_LAUNCH_FULL(128, 1, 0, 0, false, false);
-    }
-  } else {
-    if (mf) {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, true, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, true, false);
-    } else if (unroll) {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 6, 8, false, false); else CELESTE_LAUNCH_FULL(256, 1, 6, 8, false, false);
-    } else {
-      if (occ2) CELESTE_LAUNCH_FULL(256, 2, 0, 0, false, false); else CELESTE_LAUNCH_FULL(256, 1, 0, 0, false, false);
-    }
-  }
-#undef CELESTE_LAUNCH_FULL
+  const FullKernel k = full_kernel(block == 128 ? 128 : 256, variant, n_exp, n_dev);
+  hipLaunchKernelGGL(k, g, dim3(block == 128 ? 128 : 256), 0, st, items, imgs, tables, tstride, n_exp, n_dev,
+                     src_flag, tw_log2, e_zero, kept, partials, q);
   return hipGetLastError();
+}
+
+hipError_t eval_full_blocks_per_cu(int block, int variant, int n_exp, int n_dev, int* blocks) {
+  const int b = block == 128 ? 128 : 256;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, full_kernel(b, variant, n_exp, n_dev), b, 0);
 }
 
 hipError_t launch_eval_grad(const WorkItem* items, int n_items, const ImgDev* imgs, const float* tables, int tstride,

@@ -17,7 +17,7 @@ def test_flop_counts_of_the_roofline():
     sys.path.insert(0, ROOT)
     import bench
     # 3 PSF components, 6 + 8 galaxy prototypes: the figures the design notes quote
-    assert bench.flop_full_per_px(3, 6, 8) == 4729
+    assert bench.flop_full_per_px(3, 6, 8) == 4311
     assert bench.flop_value_per_px(3, 6, 8) == 3 * (13 + 8 * 14) + 30
     # algorithmic figure of the roofline: 170 per galaxy component, 30 per star component, 400 per pixel
     assert bench.flop_full_per_px_algorithmic(3, 6, 8) == 170 * 42 + 90 + 400

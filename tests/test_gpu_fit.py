@@ -139,12 +139,52 @@ def test_persistent_work_queue_equals_one_block_per_item(cb, ctx):
                     assert np.array_equal(rx["iters"], ra["iters"]) and np.array_equal(rx["status"], ra["status"])
             _say("persistent", sb.name, "iterations", ra["iters"].tolist())
     finally:
-        ctx.set_option(cb.OPT_PERSISTENT, 2)   # the library's default
+        ctx.set_option(cb.OPT_PERSISTENT, -1)   # the library's default
         ctx.set_option(cb.OPT_USE_GRAPH, 1)
         ctx.set_option(cb.OPT_CHUNK_PX, 4096)
-    for bad in (-1, 17):
+    for bad in (-2, 17):
         with pytest.raises(cb.CelesteError):
             ctx.set_option(cb.OPT_PERSISTENT, bad)
+
+
+def test_default_persistent_grid_follows_kernel_occupancy(cb, ctx):
+    """The default persistent grid holds as many blocks per compute unit as the launched kernel
+    instance keeps resident: the three-wave register budget (variant bit 0) gives 3 blocks of 256
+    threads (6 of 128) per compute unit, the other budget 2 (4); every grid gives the
+    one-block-per-item results bit for bit."""
+    sb = synth.make_config(1, n_sources=12)
+    b = cb.Batch.from_synth(sb)
+    th0 = np.zeros((sb.n_sources, 27))
+    th0[:, 0:2] = sb.u_cat
+    o = cb.default_opts(init_mode=cb.INIT_PLAIN, max_iter=6)
+
+    def grid():
+        ctx.stats(reset=True)
+        th, r = ctx.batch_fit(b, th0, o)
+        return ctx.stats()["fit_grid_blocks"], th, r
+
+    try:
+        ctx.set_option(cb.OPT_PERSISTENT, 0)
+        n0, th_a, ra = grid()
+        assert n0 == 0
+        ctx.set_option(cb.OPT_PERSISTENT, 1)
+        n_cu, _, _ = grid()
+        assert n_cu > 0
+        ctx.set_option(cb.OPT_PERSISTENT, -1)
+        first = {256: (th_a, ra)}   # the grids of one block size sum in the same order
+        for block, variant, per_cu in ((256, 3, 3), (256, 2, 2), (128, 3, 6), (128, 2, 4)):
+            ctx.set_option(cb.OPT_BLOCK, block)
+            ctx.set_option(cb.OPT_VARIANT, variant)
+            n, th, r = grid()
+            _say("grid", block, variant, n, n_cu)
+            assert n == per_cu * n_cu, (block, variant, n, n_cu)
+            th_f, r_f = first.setdefault(block, (th, r))
+            assert np.array_equal(th, th_f) and np.array_equal(r["elbo"], r_f["elbo"])
+            assert np.array_equal(r["iters"], r_f["iters"])
+    finally:
+        ctx.set_option(cb.OPT_PERSISTENT, -1)
+        ctx.set_option(cb.OPT_BLOCK, 256)
+        ctx.set_option(cb.OPT_VARIANT, 3)
 
 
 def test_interior_cholesky_step_matches_eigendecomposition(cb, ctx):
