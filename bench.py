@@ -135,6 +135,16 @@ def _rel_stats(x):
     return {"max": float(np.max(x)), "median": float(np.median(x))}
 
 
+def oracle_pattern_px(st):
+    """Pixel evaluations (value+gradient+Hessian, value only) of the fits counted in the stats st,
+    as the oracle's own trust-region iteration makes them: the ELBO alone at every trial point and
+    the value, gradient and Hessian at the start and at each accepted point.  The GPU fits make
+    exactly these without trial derivatives; with them, their trial-point passes (trial_full_px)
+    stand for the oracle's value evaluations, and taken_px counts the oracle's evaluations at
+    accepted points."""
+    return (st["full_px"] - st["trial_full_px"] + st["taken_px"], st["value_px"] + st["trial_full_px"])
+
+
 def cpu_baseline(sb, theta_fit, gpu_eval, gpu_full_px_per_step, gpu_value_px_per_step, converged_per_step,
                  budget_s=20.0):
     """Oracle timed on the host cores on a size-stratified sample of the workload: one
@@ -172,7 +182,9 @@ def cpu_baseline(sb, theta_fit, gpu_eval, gpu_full_px_per_step, gpu_value_px_per
         "sample": (f"size-stratified sample of {len(pick)} sources of the same workload (one per equal-count "
                    f"stratum of the pixel-count order, {px} px): one value+gradient+Hessian and one value "
                    f"evaluation each at the GPU fit's final parameters on {cores} processes ({wall:.1f} s wall); "
-                   f"scaled to whole fits with the GPU fits' pixel-evaluation counts per step (extrapolated)"),
+                   f"scaled to whole fits with the pixel evaluations per step of the oracle's own iteration "
+                   f"(the ELBO alone at trial points, value+gradient+Hessian at the start and at accepted points), "
+                   f"counted in the GPU fits (extrapolated)"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
         "gpu_error_at_fitted_theta": {
             "sources": len(pick),
@@ -395,7 +407,9 @@ def field_cpu_baseline(sb, theta, res, nbr, gpu_full_px_per_step, gpu_value_px_p
         "value": sources_per_step / step_s, "unit": "sources/s", "cores": cores, "kind": "oracle",
         "sample": (f"{n_full} random sources ({px_full} px): one value+gradient+Hessian and one value evaluation "
                    f"each at the GPU's final estimates with the last sweep's neighbour arrays, on {cores} processes; "
-                   f"scaled to the step with the GPU's pixel-evaluation counts"),
+                   f"scaled to the step with the pixel evaluations of the oracle's own iteration (the ELBO alone "
+                   f"at trial points, value+gradient+Hessian at the start and at accepted points) counted in the "
+                   f"GPU fits"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
         "elbo_check": {"sources": len(check), "max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
                        "host_copy_s": t_copy, "oracle_wall_s": wall},
@@ -480,6 +494,9 @@ def main():
                     help="trust-region fits: persistent pixel kernels with this many blocks per compute unit "
                          "drawing from the device work list, as many as the kernel keeps resident (-1), or one "
                          "block per work item (0); default: the library's (-1)")
+    ap.add_argument("--trial-derivatives", type=int, choices=(0, 1), default=None,
+                    help="trust-region fits: evaluate the gradient and Hessian at every trial point (1) or only at "
+                         "accepted points (0); default: the library's (1)")
     ap.add_argument("--tr-cholesky", type=int, choices=(0, 1), default=None,
                     help="trust-region subproblem: interior Newton step by Cholesky first (1) or always the "
                          "eigendecomposition (0); default: the library's")
@@ -515,6 +532,8 @@ def main():
     ctx = cb.Context(0)
     if args.persistent is not None:
         ctx.set_option(cb.OPT_PERSISTENT, args.persistent)
+    if args.trial_derivatives is not None:
+        ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, args.trial_derivatives)
     if args.tr_cholesky is not None:
         ctx.set_option(cb.OPT_TR_CHOLESKY, args.tr_cholesky)
     if args.fp64_sums is not None:
@@ -713,8 +732,9 @@ def main():
             # the GPU's ELBO, gradient and Hessian at the fitted parameters of the picked sources
             return ctx.elbo_eval(cb.Batch.from_synth(sb.subset(pick)), th_np[pick])
 
-        out["cpu_baseline"] = cpu_baseline(sb, th_np, gpu_eval, st["full_px"] / args.steps,
-                                           st["value_px"] / args.steps, conv_tol / args.steps)
+        full_o, value_o = oracle_pattern_px(st)
+        out["cpu_baseline"] = cpu_baseline(sb, th_np, gpu_eval, full_o / args.steps, value_o / args.steps,
+                                           conv_tol / args.steps)
     if args.save_fits:
         np.savez(args.save_fits, n_sources=sb.n_sources, host_generated=bool(args.host_generated),
                  plain_elbo=runs["plain"]["res"]["elbo"], plain_status=runs["plain"]["res"]["status"],
@@ -1084,8 +1104,9 @@ def field_bench(args, ctx, net, sur_info, log):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) and ELBO check on a 1% sample ...")
+        full_o, value_o = oracle_pattern_px(st)
         out["cpu_baseline"] = field_cpu_baseline(sb, theta.cpu().numpy(), res, info["nbr"],
-                                                 st["full_px"] / args.steps, st["value_px"] / args.steps,
+                                                 full_o / args.steps, value_o / args.steps,
                                                  sb.n_sources, n_check=max(1, sb.n_sources // 100))
     print(json.dumps(out), flush=True)
     if net is not None:

@@ -116,12 +116,23 @@ enum {                          /* context options (celeste_ctx_set_option) */
                                    Newton's method on lam for the step on the boundary); otherwise,
                                    and always with 0, the eigendecomposition and secular equation
                                    (default 1).  The two differ by rounding */
-  CELESTE_OPT_FP64_SUMS = 12    /* value+gradient+Hessian kernel: 1 = each tile step's FP32 gradient
+  CELESTE_OPT_FP64_SUMS = 12,   /* value+gradient+Hessian kernel: 1 = each tile step's FP32 gradient
                                    and Hessian pixel terms are summed across the wavefront in FP64,
                                    so every pixel sum is FP64 from the first addition (about 10%
                                    slower); 0 = FP32 sums per lane over up to 16 tile steps and an
                                    FP32 wavefront butterfly before FP64 (default).  The ELBO value is
                                    summed in FP64 per lane either way */
+  CELESTE_OPT_TRIAL_DERIVATIVES = 13  /* trust-region fits (celeste_newton_fit, celeste_batch_fit;
+                                   section III-B): 1 = each iteration evaluates the ELBO with its
+                                   gradient and Hessian at the trial point, and an accepted step
+                                   takes them over, so the next iteration needs no evaluation at
+                                   its new point (one value+gradient+Hessian pass before the first
+                                   iteration; default); 0 = the ELBO alone at the trial point and
+                                   the gradient and Hessian at each newly accepted point.  Both run
+                                   the same algorithm; they differ by the rounding of the summed
+                                   ELBO values the ratio test compares.  n_full_evals counts every
+                                   value+gradient+Hessian evaluation of a source (with 1: its
+                                   iterations + 1) */
 };
 
 /* Cumulative work and time counters of a context (since creation or the last reset). */
@@ -161,6 +172,11 @@ typedef struct celeste_stats {
   /* blocks of the last trust-region fit's persistent value+gradient+Hessian grid (0: one block per
    * work item; CELESTE_OPT_PERSISTENT) */
   int64_t fit_grid_blocks;
+  /* with CELESTE_OPT_TRIAL_DERIVATIVES: pixel evaluations of the value+gradient+Hessian passes at
+   * trial points (included in full_px), and the pixels of the sources at each accepted step (the
+   * value+gradient+Hessian evaluations that iterations without trial derivatives make at the new
+   * points); both 0 otherwise */
+  int64_t trial_full_px, taken_px;
 } celeste_stats;
 
 typedef struct celeste_ctx celeste_ctx;
@@ -234,6 +250,8 @@ typedef struct celeste_fit_result {
   int32_t status;               /* CELESTE_CONVERGED, ... */
   int32_t n_full_evals;         /* value+gradient+Hessian evaluations */
   int32_t flags;                /* CELESTE_FLAG_* bits */
+  int32_t n_accepted;           /* steps accepted by the ratio test (L-BFGS: by the line search) */
+  int32_t reserved;             /* 0 */
 } celeste_fit_result;
 
 /* Create a context on HIP device `hip_device` (makes it current).  *out receives the

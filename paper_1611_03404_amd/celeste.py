@@ -28,6 +28,7 @@ FLAG_FALLBACK_USED = 1
 OPT_CHUNK_PX, OPT_BLOCK, OPT_USE_GRAPH, OPT_PROFILE, OPT_VARIANT = 1, 2, 3, 4, 5
 OPT_TILE_W, OPT_VALUE_BLOCK, OPT_VALUE_TILE_W, OPT_EXACT_ZERO, OPT_PERSISTENT, OPT_TR_CHOLESKY = 6, 7, 8, 9, 10, 11
 OPT_FP64_SUMS = 12
+OPT_TRIAL_DERIVATIVES = 13
 
 IMAGE_DT = np.dtype([
     ("band", "<i4"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i4"), ("n_psf", "<i4"), ("nbr_pitch", "<i4"),
@@ -39,7 +40,8 @@ PRIOR_DT = np.dtype([("p_star", "<f8"), ("r_mean", "<f8", (2,)), ("r_var", "<f8"
 PROF_DT = np.dtype([("n_exp", "<i4"), ("n_dev", "<i4"), ("exp_amp", "<f8", (8,)), ("exp_var", "<f8", (8,)),
                     ("dev_amp", "<f8", (8,)), ("dev_var", "<f8", (8,))])
 RESULT_DT = np.dtype([("elbo", "<f8"), ("pred_gain", "<f8"), ("delta", "<f8"), ("iters", "<i4"),
-                      ("status", "<i4"), ("n_full_evals", "<i4"), ("flags", "<i4")])
+                      ("status", "<i4"), ("n_full_evals", "<i4"), ("flags", "<i4"), ("n_accepted", "<i4"),
+                      ("reserved", "<i4")])
 
 
 class CBatch(ctypes.Structure):
@@ -71,7 +73,8 @@ class Stats(ctypes.Structure):
                 ("ms_grad", ctypes.c_double), ("ms_reduce_grad", ctypes.c_double), ("ms_lbfgs", ctypes.c_double),
                 ("tr_interior", ctypes.c_int64), ("tr_boundary", ctypes.c_int64), ("tr_eigen", ctypes.c_int64),
                 ("ms_net", ctypes.c_double), ("tr_sweeps", ctypes.c_int64), ("tr_sweep_cap", ctypes.c_int64),
-                ("tr_newton_steps", ctypes.c_int64), ("fit_grid_blocks", ctypes.c_int64)]
+                ("tr_newton_steps", ctypes.c_int64), ("fit_grid_blocks", ctypes.c_int64),
+                ("trial_full_px", ctypes.c_int64), ("taken_px", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):

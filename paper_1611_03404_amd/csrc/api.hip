@@ -96,6 +96,7 @@ struct celeste_ctx {
   int pgrid = 0;                                   // the current fit's persistent grid (blocks)
   int tr_chol = 1;                                 // fits: subproblem by Cholesky where -H is positive definite
   int fp64_sums = 0;                               // value+gradient+Hessian kernel: FP64 sums per tile step
+  int trial_derivs = 1;                            // fits: gradient and Hessian evaluated at the trial point
   int n_cu = 0;                                    // compute units of the device
   DevBuf qbuf;                                     // the fits' device work queue
   bool lfact_ready = false;
@@ -592,6 +593,10 @@ hipStream_t pick(celeste_ctx* ctx, void* stream) { return stream ? (hipStream_t)
 unsigned long long* ctr_full(celeste_ctx* c) { return as<unsigned long long>(c->ctr); }
 unsigned long long* ctr_value(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 1; }
 unsigned long long* ctr_grad(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 2; }
+// counters [3, 9) belong to the trust-region subproblem (FitParams::tr_ctr)
+unsigned long long* ctr_trial(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 9; }
+unsigned long long* ctr_taken(celeste_ctx* c) { return as<unsigned long long>(c->ctr) + 10; }
+constexpr int N_CTR = 11;
 
 // HIP events between the kernel phases of one iteration (profile mode).
 struct PhaseTimer {
@@ -666,8 +671,8 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
     delete c;
     return fail(CELESTE_E_DEVICE, "stream creation failed");
   }
-  if (ensure(c->ctr, 9 * sizeof(unsigned long long)) != CELESTE_OK ||
-      hipMemset(c->ctr.p, 0, 9 * sizeof(unsigned long long)) != hipSuccess) {
+  if (ensure(c->ctr, N_CTR * sizeof(unsigned long long)) != CELESTE_OK ||
+      hipMemset(c->ctr.p, 0, N_CTR * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipStreamDestroy(c->stream);
     if (c->ctr.p) (void)hipFree(c->ctr.p);
     delete c;
@@ -699,9 +704,11 @@ int celeste_ctx_create(int hip_device, celeste_ctx** out) {
 int celeste_ctx_get_stats(celeste_ctx* c, celeste_stats* out, int reset) {
   if (!c || !out) return fail(CELESTE_E_INVALID, "context and out must not be NULL");
   HIPCHK(hipSetDevice(c->device));
-  unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long h[N_CTR] = {};
   HIPCHK(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
-  c->stats.full_px = (int64_t)h[0];
+  c->stats.full_px = (int64_t)(h[0] + h[9]);
+  c->stats.trial_full_px = (int64_t)h[9];
+  c->stats.taken_px = (int64_t)h[10];
   c->stats.value_px = (int64_t)h[1];
   c->stats.grad_px = (int64_t)h[2];
   c->stats.tr_interior = (int64_t)h[3];
@@ -777,6 +784,10 @@ int celeste_ctx_set_option(celeste_ctx* c, int option, int64_t value) {
     case CELESTE_OPT_FP64_SUMS:
       if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "FP64 sums must be 0 or 1");
       c->fp64_sums = (int)value;
+      return CELESTE_OK;
+    case CELESTE_OPT_TRIAL_DERIVATIVES:
+      if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "trial derivatives must be 0 or 1");
+      c->trial_derivs = (int)value;
       return CELESTE_OK;
     case CELESTE_OPT_TR_CHOLESKY:
       if (value != 0 && value != 1) return fail(CELESTE_E_INVALID, "trust-region Cholesky path must be 0 or 1");
@@ -1108,8 +1119,8 @@ struct FitBufs {
 };
 
 int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
-  const size_t nd = (size_t)S * (NP * 5 + 2 * NP * NP + 2 + 7);
-  const size_t ni = (size_t)S * 10 + 1;
+  const size_t nd = (size_t)S * (NP * 6 + 3 * NP * NP + 2 + 7);
+  const size_t ni = (size_t)S * 11 + 1;
   CHK(ensure(ctx->st_buf, nd * sizeof(double) + ni * sizeof(int) + 256));
   double* d = as<double>(ctx->st_buf);
   auto take = [&](size_t n) {
@@ -1124,6 +1135,8 @@ int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   f->p = take((size_t)S * NP);
   f->H = take((size_t)S * NP * NP);
   f->V = take((size_t)S * NP * NP);
+  f->g_trial = take((size_t)S * NP);
+  f->H_trial = take((size_t)S * NP * NP);
   f->u0 = take((size_t)S * 2);
   f->f = take(S);
   f->f_full = take(S);
@@ -1143,7 +1156,8 @@ int alloc_fit(celeste_ctx* ctx, int S, FitDev* f) {
   f->sw = ip + 7 * S;
   f->fa = ip + 8 * S;
   f->fb = ip + 9 * S;
-  f->n_active = ip + 10 * S;
+  f->n_acc = ip + 10 * S;
+  f->n_active = ip + 11 * S;
   return CELESTE_OK;
 }
 
@@ -1217,6 +1231,63 @@ int enqueue_iteration(celeste_ctx* ctx, const Packed& P, const FitDev& F, const 
   HIPCHK(launch_accept(F, P.n_src, fp, st));
   T->mark(8, st);
   return CELESTE_OK;
+}
+
+// The value+gradient+Hessian pass at the current point of the sources flagged need_full (with
+// trial derivatives: once, before the first iteration).
+int enqueue_current_derivs(celeste_ctx* ctx, const Packed& P, const FitDev& F, hipStream_t st, PhaseTimer* T,
+                           const WorkQueue* Q) {
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  double* parts = as<double>(ctx->partials);
+  T->mark(0, st);
+  if (Q) HIPCHK(launch_build_queue(*Q, P.n_src, F.need_full, st));
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta, F.need_full, P.prof, as<float>(ctx->tables), P.tstride, st));
+  T->mark(1, st);
+  HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                          P.prof.n_exp, P.prof.n_dev, F.need_full, parts, ctx->block, full_variant(ctx),
+                          ctx->tile_log2, ctx->e_zero, st, nullptr, Q, ctx->pgrid));
+  T->mark(2, st);
+  HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, parts, as<double>(ctx->img_const), F.theta,
+                            P.prior, F.need_full, F.f_full, F.g, F.H, ctr_full(ctx), st));
+  T->mark(3, st);
+  return CELESTE_OK;
+}
+
+// One trust-region iteration with trial derivatives (section III-B): the subproblem at the current
+// point, the ELBO with its gradient and Hessian at the trial point, the ratio test, and an accepted
+// step taking over the trial point's gradient and Hessian.
+int enqueue_iteration_td(celeste_ctx* ctx, const Packed& P, const FitDev& F, const FitParams& fp, hipStream_t st,
+                         PhaseTimer* T, const WorkQueue* Q) {
+  const ImgDev* imgs = as<ImgDev>(ctx->imgs);
+  double* parts = as<double>(ctx->partials);
+  T->mark(0, st);
+  HIPCHK(launch_zero_int(F.n_active, 1, st));
+  HIPCHK(launch_tr_step(F, P.n_src, fp, st));
+  T->mark(1, st);
+  if (Q) HIPCHK(launch_build_queue(*Q, P.n_src, F.active, st));
+  HIPCHK(launch_setup(imgs, P.n_img, F.theta_trial, F.active, P.prof, as<float>(ctx->tables), P.tstride, st));
+  T->mark(2, st);
+  HIPCHK(launch_eval_full(as<WorkItem>(ctx->items), P.n_items, imgs, as<float>(ctx->tables), P.tstride,
+                          P.prof.n_exp, P.prof.n_dev, F.active, parts, ctx->block, full_variant(ctx),
+                          ctx->tile_log2, ctx->e_zero, st, nullptr, Q, ctx->pgrid));
+  T->mark(3, st);
+  HIPCHK(launch_reduce_full(as<SrcDev>(ctx->srcs), P.n_src, imgs, parts, as<double>(ctx->img_const),
+                            F.theta_trial, P.prior, F.active, F.f_trial, F.g_trial, F.H_trial, ctr_trial(ctx), st));
+  T->mark(4, st);
+  HIPCHK(launch_accept(F, P.n_src, fp, st));
+  HIPCHK(launch_take_trial(F, P.n_src, st));
+  T->mark(5, st);
+  return CELESTE_OK;
+}
+
+void accumulate_phases_td(celeste_ctx* ctx, PhaseTimer& T) {
+  if (!T.on) return;
+  celeste_stats& s = ctx->stats;
+  s.ms_tr += T.span(0, 1);
+  s.ms_setup += T.span(1, 2);
+  s.ms_full += T.span(2, 3);
+  s.ms_reduce_full += T.span(3, 4);
+  s.ms_accept += T.span(4, 5);
 }
 
 void accumulate_phases(celeste_ctx* ctx, PhaseTimer& T) {
@@ -1327,7 +1398,7 @@ int fit_begin(celeste_ctx* ctx, const celeste_batch* b, const double* theta_inou
 int fit_results(celeste_ctx* ctx, const celeste_batch* b, const FitDev& F, int S, std::vector<double>& th,
                 double* theta_inout, celeste_fit_result* res, hipStream_t st, StageClock& stage) {
   std::vector<double> fv(S), pred(S), delta(S);
-  std::vector<int> iter(S), status(S), nfull(S), flags(S);
+  std::vector<int> iter(S), status(S), nfull(S), flags(S), nacc(S);
   HIPCHK(hipMemcpyAsync(th.data(), F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(fv.data(), F.f, sizeof(double) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(pred.data(), F.pred, sizeof(double) * S, hipMemcpyDeviceToHost, st));
@@ -1336,6 +1407,7 @@ int fit_results(celeste_ctx* ctx, const celeste_batch* b, const FitDev& F, int S
   HIPCHK(hipMemcpyAsync(status.data(), F.status, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(nfull.data(), F.n_full, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(flags.data(), F.flags, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nacc.data(), F.n_acc, sizeof(int) * S, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (b->mem_kind == CELESTE_MEM_HOST)
     std::memcpy(theta_inout, th.data(), sizeof(double) * th.size());
@@ -1351,6 +1423,8 @@ int fit_results(celeste_ctx* ctx, const celeste_batch* b, const FitDev& F, int S
     res[s].iters = iter[s];
     res[s].status = status[s];
     res[s].n_full_evals = nfull[s];
+    res[s].n_accepted = nacc[s];
+    res[s].reserved = 0;
     res[s].flags = flags[s];
   }
   return CELESTE_OK;
@@ -1432,10 +1506,14 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
   fp.eta = o->eta;
   fp.u_box = o->u_box;
   fp.tr_chol = ctx->tr_chol;
+  fp.trial_derivs = ctx->trial_derivs;
   fp.tr_ctr = as<unsigned long long>(ctx->ctr) + 3;
   FitDev F;
   std::vector<double> th;
   CHK(fit_begin(ctx, b, theta_inout, o->init_mode, fp, st, stage, &P, &F, &th));
+  // the batch's per-source metadata exists from here on (fit_begin's upload may reallocate it)
+  fp.srcs = as<SrcDev>(ctx->srcs);
+  fp.taken_px = ctr_taken(ctx);
   if (start_only) {
     if (b->mem_kind == CELESTE_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(theta_inout, F.theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
@@ -1459,13 +1537,28 @@ int run_fit(celeste_ctx* ctx, const celeste_batch* b, double* theta_inout, const
     CHK(fit_grid(ctx, P));
   }
   const WorkQueue* Qp = ctx->persistent ? &Q : nullptr;
-  CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
-               [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t, Qp); },
-               [](celeste_stats& c) {
-                 c.full_launches += 1;
-                 c.value_launches += 1;
-               },
-               accumulate_phases));
+  if (fp.trial_derivs) {
+    // the start's gradient and Hessian, then iterations that evaluate them at every trial point
+    CHK(enqueue_current_derivs(ctx, P, F, st, &T, Qp));
+    ctx->stats.full_launches += 1;
+    if (T.on) {
+      HIPCHK(hipStreamSynchronize(st));
+      ctx->stats.ms_setup += T.span(0, 1);
+      ctx->stats.ms_full += T.span(1, 2);
+      ctx->stats.ms_reduce_full += T.span(2, 3);
+    }
+    CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
+                 [&](PhaseTimer* t) { return enqueue_iteration_td(ctx, P, F, fp, st, t, Qp); },
+                 [](celeste_stats& c) { c.full_launches += 1; }, accumulate_phases_td));
+  } else {
+    CHK(run_loop(ctx, st, o->max_iter + 1, poll, graph, F.n_active, T,
+                 [&](PhaseTimer* t) { return enqueue_iteration(ctx, P, F, fp, st, t, Qp); },
+                 [](celeste_stats& c) {
+                   c.full_launches += 1;
+                   c.value_launches += 1;
+                 },
+                 accumulate_phases));
+  }
   stage(ctx->stats.ms_loop, st);
   return fit_results(ctx, b, F, S, th, theta_inout, res, st, stage);
 }

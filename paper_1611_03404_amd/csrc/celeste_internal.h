@@ -192,6 +192,8 @@ struct FitDev {
   double* g;            // S x 27 natural gradient at current
   double* H;            // S x 729 natural Hessian at current
   double* V;            // S x 729 eigenvectors of the previous trust-region model (warm start)
+  double* g_trial;      // S x 27 natural gradient at the trial point (trial derivatives)
+  double* H_trial;      // S x 729 natural Hessian at the trial point (trial derivatives)
   double* p;            // S x 27 step (psi)
   double* f;            // S current ELBO (value pass)
   double* f_full;       // S ELBO from the full pass
@@ -203,7 +205,8 @@ struct FitDev {
   int* status;          // S
   int* active;          // S  1 while the source is being fitted
   int* need_full;       // S  1 when g/H must be recomputed at theta
-  int* n_full;          // S
+  int* n_full;          // S value+gradient+Hessian evaluations
+  int* n_acc;           // S accepted steps
   int* flags;           // S  CELESTE_FLAG_* bits
   int* samp;            // S  1 while the source fits the pixel-subsampled objective (early phase)
   int* sw;              // S  1 in the iteration that moves the source from the subsampled to the full
@@ -218,6 +221,10 @@ struct FitParams {
   double pred_rtol, curv_tol, delta0, delta_max, delta_min, eta, u_box;
   double switch_rtol;   // subsampled phase: move to the full objective when pred <= switch_rtol max(1, |L|)
   int tr_chol;          // solve the subproblem by Cholesky factorisations where B is positive definite
+  int trial_derivs;     // the gradient and Hessian are evaluated at every trial point (k_accept counts
+                        // each trial evaluation; launch_take_trial moves them to an accepted point)
+  const SrcDev* srcs;   // with trial_derivs: the sources (pixel counts) ...
+  unsigned long long* taken_px;   // ... and the pixels of accepted steps whose trial derivatives are taken
   unsigned long long* tr_ctr;   // subproblems solved: [0] interior step, [1] boundary step by Cholesky,
                                 // [2] by the eigendecomposition; [3] Jacobi sweeps, [4] solves that
                                 // reached the 40-sweep cap, [5] Newton steps on the multiplier
@@ -270,6 +277,9 @@ hipError_t launch_plain_init(const SrcDev* srcs, int n_src, const ImgDev* imgs, 
                              hipStream_t s);
 hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s);
 hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s);
+// Trial derivatives: sources whose step was just accepted take the gradient and Hessian of their
+// trial point (g_trial, H_trial) and clear need_full.
+hipError_t launch_take_trial(FitDev st, int n_src, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int value, hipStream_t s);
 // fa[s] = flag[s] && !samp[s], fb[s] = flag[s] && samp[s] for every source

@@ -170,6 +170,7 @@ __global__ void k_lbfgs_accept(FitDev F, LbfgsDev X, int n_src, LbfgsParams lp) 
       }
       F.f[s] = ft;
       F.iter[s] += 1;
+      F.n_acc[s] += 1;
       F.need_full[s] = 1;
       X.in_ls[s] = 0;
     } else if (X.ls[s] >= lp.max_backtracks) {

@@ -103,10 +103,11 @@ __device__ __forceinline__ bool gal_comp(const float* __restrict__ r, float dx, 
   const float h3xxy = fmaf(by, h2xx, -r[R_2PXY] * bx);
   const float h3xyy = fmaf(bx, h2yy, -r[R_2PXY] * by);
   const float h3yyy = by * u3y;
+  // each FMA reads at most one table value (an FP32 FMA takes one scalar-register operand)
   const float h40 = fmaf(bxx, bxx - r[R_6PXX], r[R_K4A]);
-  const float h41 = fmaf(bxy, u3x, fmaf(-r[R_3PXY], bxx, r[R_K4B]));
-  const float h42 = fmaf(h2xx, h2yy, fmaf(-r[R_4PXY], bxy, r[R_K4C]));
-  const float h43 = fmaf(bxy, u3y, fmaf(-r[R_3PXY], byy, r[R_K4D]));
+  const float h41 = fmaf(-r[R_3PXY], bxx, fmaf(bxy, u3x, r[R_K4B]));
+  const float h42 = fmaf(-r[R_4PXY], bxy, fmaf(h2xx, h2yy, r[R_K4C]));
+  const float h43 = fmaf(-r[R_3PXY], byy, fmaf(bxy, u3y, r[R_K4D]));
   const float h44 = fmaf(byy, byy - r[R_6PYY], r[R_K4E]);
   const float Nn = N * r[R_NU];
   const float Nn2 = Nn * r[R_NU];

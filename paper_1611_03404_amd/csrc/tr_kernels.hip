@@ -44,6 +44,7 @@ __global__ void k_fit_init(FitDev st, int n_src, FitParams fp) {
   st.active[s] = 1;
   st.need_full[s] = 1;
   st.n_full[s] = 0;
+  st.n_acc[s] = 0;
   st.pred[s] = 0.0;
   st.samp[s] = 0;
   st.sw[s] = 0;
@@ -510,6 +511,7 @@ __global__ void k_accept(FitDev st, int n_src, FitParams fp) {
     atomicAdd(st.n_active, 1);
     return;
   }
+  if (fp.trial_derivs) st.n_full[s] += 1;   // the trial point's value+gradient+Hessian evaluation
   const double ft = st.f_trial[s], f = st.f[s], pred = st.pred[s];
   const double rho = isfinite(ft) ? (ft - f) / pred : -INFINITY;
   const double pn = st.pnorm[s];
@@ -530,6 +532,8 @@ __global__ void k_accept(FitDev st, int n_src, FitParams fp) {
     }
     st.f[s] = ft;
     st.need_full[s] = 1;
+    st.n_acc[s] += 1;
+    if (fp.trial_derivs && fp.taken_px) atomicAdd(fp.taken_px, (unsigned long long)fp.srcs[s].npix);
   }
   st.iter[s] += 1;
   if (delta < fp.delta_min) {
@@ -539,6 +543,21 @@ __global__ void k_accept(FitDev st, int n_src, FitParams fp) {
     return;
   }
   atomicAdd(st.n_active, 1);
+}
+
+// Trial derivatives: a source whose step was just accepted (need_full set by k_accept) takes the
+// gradient and Hessian evaluated at its trial point, which is now its current point; one 64-thread
+// block per source.
+__global__ __launch_bounds__(64) void k_take_trial(FitDev st) {
+  const int s = blockIdx.x;
+  if (!st.need_full[s]) return;
+  const int t = threadIdx.x;
+  if (t < NP) st.g[(size_t)s * NP + t] = st.g_trial[(size_t)s * NP + t];
+  double* H = st.H + (size_t)s * NP * NP;
+  const double* Ht = st.H_trial + (size_t)s * NP * NP;
+  for (int k = t; k < NP * NP; k += 64) H[k] = Ht[k];
+  __syncthreads();   // every thread has read the flag before it is cleared
+  if (t == 0) st.need_full[s] = 0;
 }
 
 __global__ void k_fill(int* p, int n, int v) {
@@ -681,6 +700,12 @@ hipError_t launch_tr_step(FitDev st, int n_src, FitParams fp, hipStream_t s) {
 
 hipError_t launch_accept(FitDev st, int n_src, FitParams fp, hipStream_t s) {
   hipLaunchKernelGGL(k_accept, dim3((n_src + 127) / 128), dim3(128), 0, s, st, n_src, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_trial(FitDev st, int n_src, hipStream_t s) {
+  if (n_src <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_take_trial, dim3(n_src), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ def bca(ctx, batch_arrays, fields_meta, sweeps=3, start_mode=cb.INIT_SURROGATE, 
         return v
 
     res = {"elbo": np.zeros(S), "status": np.zeros(S, np.int32), "iters": np.zeros(S, np.int32),
-           "n_full_evals": np.zeros(S, np.int32), "flags": np.zeros(S, np.int32)}
+           "n_full_evals": np.zeros(S, np.int32), "flags": np.zeros(S, np.int32),
+           "n_accepted": np.zeros(S, np.int32)}
     history = []
     t = time.perf_counter()
     ctx.render_fields(base, theta, img_field, n_fields, H, W, out=fields)

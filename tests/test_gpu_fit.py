@@ -187,6 +187,50 @@ def test_default_persistent_grid_follows_kernel_occupancy(cb, ctx):
         ctx.set_option(cb.OPT_VARIANT, 3)
 
 
+def test_trial_derivatives_match_derivatives_at_accepted_points(cb, ctx):
+    """Trust-region fits that evaluate the gradient and Hessian at every trial point (the default)
+    against fits that evaluate them only at accepted points (section III-B runs the same algorithm
+    either way): the same statuses, ELBO values that agree to rounding, the same accepted steps on
+    almost every source, and the evaluation counts each mode implies (with trial derivatives
+    iterations + 1 full evaluations; otherwise accepted steps + 1).  A ragged config-1 subset
+    and config-2 sources, graph replay and eager."""
+    c1 = synth.make_config(1, n_sources=40)
+    side = c1.truth["side"]
+    sets = [c1.subset(list(np.argsort(side)[:6]) + list(np.argsort(side)[-6:])),
+            synth.make_config(2, n_sources=30).subset(list(range(0, 30, 3)))]
+    try:
+        for sb in sets:
+            b = cb.Batch.from_synth(sb)
+            th0 = np.zeros((sb.n_sources, 27))
+            th0[:, 0:2] = sb.u_cat
+            o = cb.default_opts(init_mode=cb.INIT_PLAIN)
+            ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, 0)
+            th_a, ra = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, 1)
+            th_t, rt = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_USE_GRAPH, 0)
+            th_e, re_ = ctx.batch_fit(b, th0, o)
+            ctx.set_option(cb.OPT_USE_GRAPH, 1)
+            assert np.array_equal(th_e, th_t) and np.array_equal(re_["elbo"], rt["elbo"])
+            assert np.array_equal(rt["status"], ra["status"]), (rt["status"], ra["status"])
+            assert np.all(rt["status"] == cb.CONVERGED)
+            rel = np.abs(rt["elbo"] - ra["elbo"]) / np.abs(ra["elbo"])
+            _say("trial derivatives", sb.name, "iters", rt["iters"].tolist(), ra["iters"].tolist(),
+                 "max rel ELBO diff", float(rel.max()))
+            assert rel.max() <= 1e-7
+            same = np.mean(rt["n_accepted"] == ra["n_accepted"])
+            assert same >= 0.9, same
+            assert np.array_equal(rt["n_full_evals"], rt["iters"] + 1)
+            assert np.array_equal(ra["n_full_evals"], ra["n_accepted"] + 1)
+            assert np.all(rt["n_accepted"] <= rt["iters"]) and np.all(rt["reserved"] == 0)
+    finally:
+        ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, 1)
+        ctx.set_option(cb.OPT_USE_GRAPH, 1)
+    for bad in (-1, 2):
+        with pytest.raises(cb.CelesteError):
+            ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, bad)
+
+
 def test_interior_cholesky_step_matches_eigendecomposition(cb, ctx):
     """The Cholesky paths of the subproblem (where -H is positive definite: the interior Newton
     step, or the boundary step by Newton's method on the multiplier) against the
