@@ -195,7 +195,7 @@ struct FitDev {
   double* g_trial;      // S x 27 natural gradient at the trial point (trial derivatives)
   double* H_trial;      // S x 729 natural Hessian at the trial point (trial derivatives)
   double* p;            // S x 27 step (psi)
-  double* f;            // S current ELBO (value pass)
+  double* f;            // S current ELBO (from the evaluation at which the current point was accepted)
   double* f_full;       // S ELBO from the full pass
   double* f_trial;      // S
   double* pred;         // S
@@ -204,7 +204,8 @@ struct FitDev {
   int* iter;            // S
   int* status;          // S
   int* active;          // S  1 while the source is being fitted
-  int* need_full;       // S  1 when g/H must be recomputed at theta
+  int* need_full;       // S  1 when g/H must be computed at theta (with trial derivatives: from an
+                        //    accepted step until k_take_trial hands over the trial point's g/H)
   int* n_full;          // S value+gradient+Hessian evaluations
   int* n_acc;           // S accepted steps
   int* flags;           // S  CELESTE_FLAG_* bits

@@ -102,8 +102,7 @@ __device__ inline void pair_of(int round, int k, int* p, int* q) {
 
 __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __shared__ double B[NPAD][NPAD + 1];
-  __shared__ double V[NPAD][NPAD + 1];
-  __shared__ double W[NPAD][NPAD + 1];
+  __shared__ double V[NPAD][NPAD + 1];   // eigenvectors; the Cholesky paths' factor before that
   __shared__ double g[NPAD], gt[NPAD], lam[NPAD], pt[NPAD], d1s[NP];
   __shared__ double rc[NPAD / 2], rs[NPAD / 2], rt[NPAD / 2], rapq[NPAD / 2], rapp[NPAD / 2], raqq[NPAD / 2];
   __shared__ int rp[NPAD / 2], rq[NPAD / 2];
@@ -136,8 +135,6 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
       if (i == j) b -= d2s[i] * gn[i];
     }
     B[i][j] = b;
-    // warm start: the eigenvectors of the previous model (identity at the first iteration)
-    V[i][j] = (i < NP && j < NP) ? st.V[(size_t)s * NP * NP + i * NP + j] : (i == j ? 1.0 : 0.0);
   }
   if (t < NPAD) g[t] = t < NP ? d1s[t] * gn[t] : 0.0;
   __syncthreads();
@@ -167,36 +164,37 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
     double dmax = t < NP ? B[t][t] : -INFINITY;
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
     dmax = __shfl(dmax, 0);
-    // W <- the Cholesky factor L of B + lam I (lower triangle), pst <- (B + lam I)^{-1} g
+    // V <- the Cholesky factor L of B + lam I (lower triangle), pst <- (B + lam I)^{-1} g (V holds
+    // the eigenvectors only in the eigendecomposition path, which loads them afresh)
     auto factor_solve = [&](double lam) -> bool {
       for (int k = t; k < NP * NP; k += 64) {
         const int i = k / NP, j = k - i * NP;
-        W[i][j] = B[i][j] + (i == j ? lam : 0.0);
+        V[i][j] = B[i][j] + (i == j ? lam : 0.0);
       }
       if (t < NPAD) y[t] = g[t];
       __syncthreads();
       for (int k = 0; k < NP; ++k) {
-        const double piv = W[k][k];   // the same value on every lane: the decision is uniform
+        const double piv = V[k][k];   // the same value on every lane: the decision is uniform
         if (!(piv > 1e-12 * (dmax + lam))) return false;
         const double lkk = sqrt(piv);
-        // (W[k][k] is read above by every lane and written only after the barrier)
-        if (t > k && t < NP) W[t][k] /= lkk;
+        // (V[k][k] is read above by every lane and written only after the barrier)
+        if (t > k && t < NP) V[t][k] /= lkk;
         if (t == k) y[k] /= lkk;
         __syncthreads();
         const int m = NP - 1 - k;
         for (int e = t; e < m * m; e += 64) {
           const int i = k + 1 + e / m, j = k + 1 + e % m;
-          if (j <= i) W[i][j] -= W[i][k] * W[j][k];
+          if (j <= i) V[i][j] -= V[i][k] * V[j][k];
         }
-        if (t > k && t < NP) y[t] -= W[t][k] * y[k];
-        if (t == k) W[k][k] = lkk;
+        if (t > k && t < NP) y[t] -= V[t][k] * y[k];
+        if (t == k) V[k][k] = lkk;
         __syncthreads();
       }
       // back substitution L' p = y, one unknown per step
       for (int k = NP - 1; k >= 0; --k) {
-        const double yk = y[k] / W[k][k];
+        const double yk = y[k] / V[k][k];
         if (t == k) pst[k] = yk;
-        if (t < k) y[t] -= W[k][t] * yk;
+        if (t < k) y[t] -= V[k][t] * yk;
         __syncthreads();
       }
       return true;
@@ -220,9 +218,9 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
           __syncthreads();
           double qk = 0.0;
           for (int k = 0; k < NP; ++k) {
-            const double yk = y[k] / W[k][k];
+            const double yk = y[k] / V[k][k];
             if (t == k) qk = yk;
-            if (t > k && t < NP) y[t] -= W[t][k] * yk;
+            if (t > k && t < NP) y[t] -= V[t][k] * yk;
             __syncthreads();
           }
           const double qn2 = wsum(qk * qk);
@@ -240,20 +238,49 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   }
 
   if (path == 2) {
-  // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
-  // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model
+  // warm start: the eigenvectors of the previous model (identity at the first iteration)
   for (int k = t; k < NPAD * NPAD; k += 64) {
     const int i = k / NPAD, j = k - i * NPAD;
-    double a = 0.0;
-    for (int r = 0; r < NPAD; ++r) a += B[i][r] * V[r][j];
-    W[i][j] = a;
+    V[i][j] = (i < NP && j < NP) ? st.V[(size_t)s * NP * NP + i * NP + j] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int k = t; k < NPAD * NPAD; k += 64) {
-    const int i = k / NPAD, j = k - i * NPAD;
+  // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
+  // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model.
+  // Each lane keeps its entries of B V, then of V^T (B V), in registers between the barriers.
+  constexpr int PER = (NPAD * NPAD + 63) / 64;
+  double acc[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = t + 64 * u;
     double a = 0.0;
-    for (int r = 0; r < NPAD; ++r) a += V[r][i] * W[r][j];
-    B[i][j] = a;
+    if (k < NPAD * NPAD) {
+      const int i = k / NPAD, j = k - i * NPAD;
+      for (int r = 0; r < NPAD; ++r) a += B[i][r] * V[r][j];
+    }
+    acc[u] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = t + 64 * u;
+    if (k < NPAD * NPAD) B[k / NPAD][k % NPAD] = acc[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = t + 64 * u;
+    double a = 0.0;
+    if (k < NPAD * NPAD) {
+      const int i = k / NPAD, j = k - i * NPAD;
+      for (int r = 0; r < NPAD; ++r) a += V[r][i] * B[r][j];
+    }
+    acc[u] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = t + 64 * u;
+    if (k < NPAD * NPAD) B[k / NPAD][k % NPAD] = acc[u];
   }
   __syncthreads();
   // symmetrise (the Hessian is assembled symmetrically; this removes rounding asymmetry)
