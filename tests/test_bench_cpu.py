@@ -13,6 +13,19 @@ def test_more_than_one_gpu_is_refused():
     assert "exactly one GPU" in r.stderr
 
 
+def test_oracle_pattern_counts():
+    """The CPU baseline's pixel-evaluation counts: the stats of fits without trial derivatives are
+    the oracle's own pattern; with them, trial-point passes count as the oracle's value evaluations
+    and the pixels of accepted steps as its value+gradient+Hessian evaluations."""
+    sys.path.insert(0, ROOT)
+    import bench
+    st = {"full_px": 500, "value_px": 300, "trial_full_px": 0, "taken_px": 0}
+    assert bench.oracle_pattern_px(st) == (500, 300)
+    # 100 px per source and 10 sources: start pass 1,000 px, 7 trial passes of 1,000 px, 5 accepted
+    st = {"full_px": 1000 + 7000, "value_px": 2000, "trial_full_px": 7000, "taken_px": 5000}
+    assert bench.oracle_pattern_px(st) == (1000 + 5000, 2000 + 7000)
+
+
 def test_flop_counts_of_the_roofline():
     sys.path.insert(0, ROOT)
     import bench
