@@ -90,6 +90,20 @@ def flop_full_per_px_algorithmic(K, E, D):
     return 170 * K * (E + D) + 30 * K + 400
 
 
+def host_cpu():
+    """The host CPU the oracle ran on: model name and logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def stratified_sample(npx, n, seed):
     """One source drawn at random from each of n equal-count strata of the pixel-count order
     (a size-stratified sample of n sources)."""
@@ -186,6 +200,8 @@ def cpu_baseline(sb, theta_fit, gpu_eval, gpu_full_px_per_step, gpu_value_px_per
                    f"(the ELBO alone at trial points, value+gradient+Hessian at the start and at accepted points), "
                    f"counted in the GPU fits (extrapolated)"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
+        "full_pixel_evals_per_s_per_core": full_rate / cores, "value_pixel_evals_per_s_per_core": val_rate / cores,
+        "host_cpu": host_cpu(),
         "gpu_error_at_fitted_theta": {
             "sources": len(pick),
             "elbo_rel": _rel_stats(e_rel),
@@ -250,7 +266,7 @@ def oracle_fit_baseline(sb, n, gpu_plain_elbo, gpu_head_elbo, log):
         "sample": (f"complete oracle fits from the plain start of a size-stratified sample of {len(pick)} sources "
                    f"(one per equal-count stratum of the pixel-count order) on {cores} processes, {wall:.0f} s wall; "
                    f"the rate scales the sample's measured fit times to the {sb.n_sources}-source workload"),
-        "measured_fits_per_s": len(pick) / wall,
+        "measured_fits_per_s": len(pick) / wall, "host_cpu": host_cpu(),
         "oracle_iterations_mean": float(np.mean([o[2] for o in out])),
         "oracle_converged": int(np.sum(conv)),
         "a22_pass_plain_start": a22(gpu_plain_elbo), "a22_pass_headline_start": a22(gpu_head_elbo),
@@ -321,7 +337,8 @@ def sampled_cpu_baseline(sb, theta, keep_prob, seed, budget_s=20.0):
     return {"value": len(pick) / sum(ts) * cores, "unit": "source evaluations/s", "cores": cores, "kind": "oracle",
             "sample": (f"{len(pick)} random sources of the same workload, one subsampled value+gradient+Hessian "
                        f"estimate each at the plain start, keep_prob {keep_prob}, on {cores} processes "
-                       f"({wall:.1f} s wall)")}
+                       f"({wall:.1f} s wall)"),
+            "host_cpu": host_cpu()}
 
 
 _FIELD_JOB = None   # (subset, per-source neighbour dicts, thetas, n_full): inherited by forked workers
@@ -411,6 +428,8 @@ def field_cpu_baseline(sb, theta, res, nbr, gpu_full_px_per_step, gpu_value_px_p
                    f"at trial points, value+gradient+Hessian at the start and at accepted points) counted in the "
                    f"GPU fits"),
         "full_pixel_evals_per_s": full_rate, "value_pixel_evals_per_s": val_rate,
+        "full_pixel_evals_per_s_per_core": full_rate / cores, "value_pixel_evals_per_s_per_core": val_rate / cores,
+        "host_cpu": host_cpu(),
         "elbo_check": {"sources": len(check), "max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
                        "host_copy_s": t_copy, "oracle_wall_s": wall},
     }
