@@ -207,7 +207,17 @@ def test_trial_derivatives_match_derivatives_at_accepted_points(cb, ctx):
             ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, 0)
             th_a, ra = ctx.batch_fit(b, th0, o)
             ctx.set_option(cb.OPT_TRIAL_DERIVATIVES, 1)
+            ctx.stats(reset=True)
             th_t, rt = ctx.batch_fit(b, th0, o)
+            st = ctx.stats()
+            # the pixel counters: the start pass, one trial pass per iteration, and the pixels of
+            # every accepted step (what the CPU baseline rebuilds the oracle's evaluations from)
+            npix = np.array([int(np.sum(sb.img_h[sb.src_img_off[k]:sb.src_img_off[k + 1]].astype(np.int64)
+                                        * sb.img_w[sb.src_img_off[k]:sb.src_img_off[k + 1]]))
+                             for k in range(sb.n_sources)])
+            assert st["trial_full_px"] == int(np.sum(npix * rt["iters"]))
+            assert st["taken_px"] == int(np.sum(npix * rt["n_accepted"]))
+            assert st["full_px"] - st["trial_full_px"] == int(np.sum(npix))
             ctx.set_option(cb.OPT_USE_GRAPH, 0)
             th_e, re_ = ctx.batch_fit(b, th0, o)
             ctx.set_option(cb.OPT_USE_GRAPH, 1)
