@@ -295,6 +295,37 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __syncthreads();
 
   // ---- cyclic Jacobi, round-robin parallel ordering
+  // A lane updates the same 2x2 blocks of B (by pair index: the diagonal blocks, then the pairs
+  // a < b) and the same entries of V in every round, so their indices are decoded once here.
+  constexpr int NPR = NPAD / 2;                     // disjoint rotations per round
+  constexpr int NBLK = NPR + NPR * (NPR - 1) / 2;   // 2x2 blocks of B touched per round
+  constexpr int BPL = (NBLK + 63) / 64, VPL = (NPR * NPAD + 63) / 64;
+  int blk_a[BPL], blk_b[BPL];   // blk_a < 0: no block; blk_b < 0: the diagonal block of pair blk_a
+#pragma unroll
+  for (int u = 0; u < BPL; ++u) {
+    const int k = t + 64 * u;
+    blk_a[u] = -1;
+    blk_b[u] = -1;
+    if (k >= NBLK) continue;
+    if (k < NPR) {
+      blk_a[u] = k;
+      continue;
+    }
+    int a = 0, idx = k - NPR;
+    while (idx >= NPR - 1 - a) {
+      idx -= NPR - 1 - a;
+      ++a;
+    }
+    blk_a[u] = a;
+    blk_b[u] = a + 1 + idx;
+  }
+  int v_pr[VPL], v_r[VPL];      // rotation and row of the lane's entries of V (v_pr < 0: none)
+#pragma unroll
+  for (int u = 0; u < VPL; ++u) {
+    const int k = t + 64 * u;
+    v_pr[u] = k < NPR * NPAD ? k / NPAD : -1;
+    v_r[u] = k - (k / NPAD) * NPAD;
+  }
   int sweeps = 0;
   for (; sweeps < 40; ++sweeps) {
     double off = 0.0, fro = 0.0;
@@ -310,7 +341,7 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
     }
     if (off <= 1e-30 * fro || fro == 0.0) break;
     for (int round = 0; round < NPAD - 1; ++round) {
-      if (t < NPAD / 2) {
+      if (t < NPR) {
         int p, q;
         pair_of(round, t, &p, &q);
         if (p > q) {
@@ -340,23 +371,20 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
       // each block read and written by one lane, so no entry is touched twice; an off-diagonal
       // block is transformed columns first, then rows, and mirrored; a diagonal block takes the
       // rotated eigenvalue estimates and exact zeros
-      for (int k = t; k < NPAD / 2 + (NPAD / 2) * (NPAD / 2 - 1) / 2; k += 64) {
-        if (k < NPAD / 2) {
-          if (rt[k] != 0.0) {
-            const int p = rp[k], q = rq[k];
-            B[p][p] = rapp[k] - rt[k] * rapq[k];
-            B[q][q] = raqq[k] + rt[k] * rapq[k];
+#pragma unroll
+      for (int u = 0; u < BPL; ++u) {
+        const int a = blk_a[u], b = blk_b[u];
+        if (a < 0) continue;
+        if (b < 0) {
+          if (rt[a] != 0.0) {
+            const int p = rp[a], q = rq[a];
+            B[p][p] = rapp[a] - rt[a] * rapq[a];
+            B[q][q] = raqq[a] + rt[a] * rapq[a];
             B[p][q] = 0.0;
             B[q][p] = 0.0;
           }
           continue;
         }
-        int a = 0, idx = k - NPAD / 2;
-        while (idx >= NPAD / 2 - 1 - a) {
-          idx -= NPAD / 2 - 1 - a;
-          ++a;
-        }
-        const int b = a + 1 + idx;
         const int p1 = rp[a], q1 = rq[a], p2 = rp[b], q2 = rq[b];
         const double c1 = rc[a], s1 = rs[a], c2 = rc[b], s2 = rs[b];
         const double x00 = B[p1][p2], x01 = B[p1][q2], x10 = B[q1][p2], x11 = B[q1][q2];
@@ -373,8 +401,10 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         B[p2][q1] = z10;
         B[q2][q1] = z11;
       }
-      for (int k = t; k < (NPAD / 2) * NPAD; k += 64) {
-        const int pr = k / NPAD, r = k - pr * NPAD;
+#pragma unroll
+      for (int u = 0; u < VPL; ++u) {
+        const int pr = v_pr[u], r = v_r[u];
+        if (pr < 0) continue;
         const int p = rp[pr], q = rq[pr];
         const double c = rc[pr], sn = rs[pr];
         const double vp = V[r][p], vq = V[r][q];
