@@ -104,8 +104,9 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __shared__ double B[NPAD][NPAD + 1];
   __shared__ double V[NPAD][NPAD + 1];   // eigenvectors; the Cholesky paths' factor before that
   __shared__ double g[NPAD], gt[NPAD], lam[NPAD], pt[NPAD], d1s[NP];
-  __shared__ double rc[NPAD / 2], rs[NPAD / 2], rt[NPAD / 2], rapq[NPAD / 2], rapp[NPAD / 2], raqq[NPAD / 2];
-  __shared__ int rp[NPAD / 2], rq[NPAD / 2];
+  // a round's rotations: (p, q) and (cos, sin) side by side so that a reader loads each pair at once
+  __shared__ double2 rcs[NPAD / 2];
+  __shared__ int2 rpq[NPAD / 2];
   __shared__ int done;
   const int s = blockIdx.x;
   if (!st.active[s]) return;
@@ -181,10 +182,14 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
         if (t > k && t < NP) V[t][k] /= lkk;
         if (t == k) y[k] /= lkk;
         __syncthreads();
-        const int m = NP - 1 - k;
-        for (int e = t; e < m * m; e += 64) {
-          const int i = k + 1 + e / m, j = k + 1 + e % m;
-          if (j <= i) V[i][j] -= V[i][k] * V[j][k];
+        // trailing update of the lower triangle: lane (h, j) = (t / 32, t % 32) takes column j,
+        // rows j + h, j + h + 2, ... (each entry updated by one lane)
+        {
+          const int j = t & 31;
+          if (j > k && j < NP) {
+            const double ljk = V[j][k];
+            for (int i = j + (t >> 5); i < NP; i += 2) V[i][j] -= V[i][k] * ljk;
+          }
         }
         if (t > k && t < NP) y[t] -= V[t][k] * y[k];
         if (t == k) V[k][k] = lkk;
@@ -246,43 +251,42 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __syncthreads();
   // B <- V^T B V, nearly diagonal when the model changed little since the previous iteration;
   // the Jacobi rotations below accumulate into V, so V ends as the eigenvectors of the model.
-  // Each lane keeps its entries of B V, then of V^T (B V), in registers between the barriers.
-  constexpr int PER = (NPAD * NPAD + 63) / 64;
-  double acc[PER];
+  // Lane (h, j) = (t / 32, t % 32), j < NPAD, forms column j of each product for the rows
+  // NPAD/2 h .. NPAD/2 h + NPAD/2 - 1 in registers (one LDS read of its own column and broadcast
+  // reads of the other operand per r; every entry summed over r in increasing order) and stores
+  // them after the barrier.
+  {
+    constexpr int HR = NPAD / 2;
+    const int cj = t & 31, r0 = (t >> 5) * HR;
+    const bool cl = cj < NPAD;
+    double acc[HR];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int k = t + 64 * u;
-    double a = 0.0;
-    if (k < NPAD * NPAD) {
-      const int i = k / NPAD, j = k - i * NPAD;
-      for (int r = 0; r < NPAD; ++r) a += B[i][r] * V[r][j];
-    }
-    acc[u] = a;
-  }
-  __syncthreads();
+    for (int i = 0; i < HR; ++i) acc[i] = 0.0;
+    if (cl)
+      for (int r = 0; r < NPAD; ++r) {
+        const double v = V[r][cj];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int k = t + 64 * u;
-    if (k < NPAD * NPAD) B[k / NPAD][k % NPAD] = acc[u];
-  }
-  __syncthreads();
+        for (int i = 0; i < HR; ++i) acc[i] += B[r0 + i][r] * v;
+      }
+    __syncthreads();
+    if (cl)
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int k = t + 64 * u;
-    double a = 0.0;
-    if (k < NPAD * NPAD) {
-      const int i = k / NPAD, j = k - i * NPAD;
-      for (int r = 0; r < NPAD; ++r) a += V[r][i] * B[r][j];
-    }
-    acc[u] = a;
-  }
-  __syncthreads();
+      for (int i = 0; i < HR; ++i) B[r0 + i][cj] = acc[i];
+    __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int k = t + 64 * u;
-    if (k < NPAD * NPAD) B[k / NPAD][k % NPAD] = acc[u];
+    for (int i = 0; i < HR; ++i) acc[i] = 0.0;
+    if (cl)
+      for (int r = 0; r < NPAD; ++r) {
+        const double b = B[r][cj];
+#pragma unroll
+        for (int i = 0; i < HR; ++i) acc[i] += V[r][r0 + i] * b;
+      }
+    __syncthreads();
+    if (cl)
+#pragma unroll
+      for (int i = 0; i < HR; ++i) B[r0 + i][cj] = acc[i];
+    __syncthreads();
   }
-  __syncthreads();
   // symmetrise (the Hessian is assembled symmetrically; this removes rounding asymmetry)
   for (int k = t; k < NPAD * NPAD; k += 64) {
     const int i = k / NPAD, j = k - i * NPAD;
@@ -295,23 +299,19 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
   __syncthreads();
 
   // ---- cyclic Jacobi, round-robin parallel ordering
-  // A lane updates the same 2x2 blocks of B (by pair index: the diagonal blocks, then the pairs
-  // a < b) and the same entries of V in every round, so their indices are decoded once here.
+  // A lane updates the same off-diagonal 2x2 blocks of B (by pair indices a < b) and the same
+  // entries of V in every round, so their indices are decoded once here.
   constexpr int NPR = NPAD / 2;                     // disjoint rotations per round
-  constexpr int NBLK = NPR + NPR * (NPR - 1) / 2;   // 2x2 blocks of B touched per round
+  constexpr int NBLK = NPR * (NPR - 1) / 2;         // off-diagonal 2x2 blocks of B per round
   constexpr int BPL = (NBLK + 63) / 64, VPL = (NPR * NPAD + 63) / 64;
-  int blk_a[BPL], blk_b[BPL];   // blk_a < 0: no block; blk_b < 0: the diagonal block of pair blk_a
+  int blk_a[BPL], blk_b[BPL];   // blk_a < 0: no block
 #pragma unroll
   for (int u = 0; u < BPL; ++u) {
     const int k = t + 64 * u;
     blk_a[u] = -1;
     blk_b[u] = -1;
     if (k >= NBLK) continue;
-    if (k < NPR) {
-      blk_a[u] = k;
-      continue;
-    }
-    int a = 0, idx = k - NPR;
+    int a = 0, idx = k;
     while (idx >= NPR - 1 - a) {
       idx -= NPR - 1 - a;
       ++a;
@@ -357,36 +357,29 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
           c = 1.0 / sqrt(tt * tt + 1.0);
           sn = tt * c;
         }
-        rp[t] = p;
-        rq[t] = q;
-        rc[t] = c;
-        rs[t] = sn;
-        rt[t] = tt;
-        rapq[t] = apq;
-        rapp[t] = app;
-        raqq[t] = aqq;
+        rpq[t] = make_int2(p, q);
+        rcs[t] = make_double2(c, sn);
+        // the pair's own 2x2 block takes the rotated eigenvalue estimates and exact zeros; no other
+        // lane reads these four entries in this round
+        if (tt != 0.0) {
+          B[p][p] = app - tt * apq;
+          B[q][q] = aqq + tt * apq;
+          B[p][q] = 0.0;
+          B[q][p] = 0.0;
+        }
       }
       __syncthreads();
-      // B <- J^T B J and V <- V J in one pass: B by 2x2 blocks (pair a's rows x pair b's columns),
-      // each block read and written by one lane, so no entry is touched twice; an off-diagonal
-      // block is transformed columns first, then rows, and mirrored; a diagonal block takes the
-      // rotated eigenvalue estimates and exact zeros
+      // B <- J^T B J and V <- V J in one pass: the off-diagonal 2x2 blocks of B (pair a's rows x
+      // pair b's columns, a < b), each read and written by one lane, so no entry is touched twice;
+      // a block is transformed columns first, then rows, and mirrored
 #pragma unroll
       for (int u = 0; u < BPL; ++u) {
         const int a = blk_a[u], b = blk_b[u];
         if (a < 0) continue;
-        if (b < 0) {
-          if (rt[a] != 0.0) {
-            const int p = rp[a], q = rq[a];
-            B[p][p] = rapp[a] - rt[a] * rapq[a];
-            B[q][q] = raqq[a] + rt[a] * rapq[a];
-            B[p][q] = 0.0;
-            B[q][p] = 0.0;
-          }
-          continue;
-        }
-        const int p1 = rp[a], q1 = rq[a], p2 = rp[b], q2 = rq[b];
-        const double c1 = rc[a], s1 = rs[a], c2 = rc[b], s2 = rs[b];
+        const int2 pq1 = rpq[a], pq2 = rpq[b];
+        const double2 cs1 = rcs[a], cs2 = rcs[b];
+        const int p1 = pq1.x, q1 = pq1.y, p2 = pq2.x, q2 = pq2.y;
+        const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
         const double x00 = B[p1][p2], x01 = B[p1][q2], x10 = B[q1][p2], x11 = B[q1][q2];
         const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
         const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
@@ -405,8 +398,10 @@ __global__ __launch_bounds__(64) void k_tr(FitDev st, FitParams fp) {
       for (int u = 0; u < VPL; ++u) {
         const int pr = v_pr[u], r = v_r[u];
         if (pr < 0) continue;
-        const int p = rp[pr], q = rq[pr];
-        const double c = rc[pr], sn = rs[pr];
+        const int2 pq = rpq[pr];
+        const double2 cs = rcs[pr];
+        const int p = pq.x, q = pq.y;
+        const double c = cs.x, sn = cs.y;
         const double vp = V[r][p], vq = V[r][q];
         V[r][p] = c * vp - sn * vq;
         V[r][q] = sn * vp + c * vq;
