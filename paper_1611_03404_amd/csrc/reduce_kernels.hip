@@ -108,7 +108,10 @@ __device__ inline double kl_hess(const double* th, const PriorDev& pr, const KL&
   return h;
 }
 
-constexpr int RB = 128;
+constexpr int RB = 256;
+constexpr int RSLOT = 80;              // threads per image slot in k_reduce_full (NACC of them busy)
+constexpr int NSLOT = RB / RSLOT;      // images whose partials are summed at once
+constexpr int ICH = 24;                // images per chunk of per-image sums held in LDS
 
 // Adds one z-space sum (tmp: value, 11 gradient, 66 Hessian entries, in LDS) mapped to the 27
 // natural parameters through the map of (band, WCS matrix) to Ht / gt.  All threads; tmp
@@ -155,6 +158,7 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
                                                     unsigned long long* __restrict__ px_ctr, double px_weight) {
   __shared__ double tmp[NACC];
   __shared__ double grp[5][NACC];
+  __shared__ double isum[ICH][NACC];
   __shared__ double Hz[NZ * NZ];
   __shared__ double Ht[NP * NP];
   __shared__ double gt[NP];
@@ -173,24 +177,33 @@ __global__ __launch_bounds__(RB) void k_reduce_full(const SrcDev* __restrict__ s
   const SrcDev sr = srcs[s];
   const double* wref = imgs[sr.img_begin].wcs;
   unsigned used = 0;   // bands with images in grp (the same on every thread)
-  for (int i = sr.img_begin; i < sr.img_end; ++i) {
-    const ImgDev& im = imgs[i];
-    double acc = 0.0;
-    if (t < NACC) {
-      for (int it = im.item_begin; it < im.item_end; ++it) acc += partials[(size_t)it * NACC + t];
-      acc *= px_weight;
+  const int e = t % RSLOT, slot = t / RSLOT;
+  for (int c0 = sr.img_begin; c0 < sr.img_end; c0 += ICH) {
+    const int c1 = min(sr.img_end, c0 + ICH);
+    // the chunk's per-image sums of the work items' partials (items in order), NSLOT images at a
+    // time, so that the loads of several images are in flight together
+    if (slot < NSLOT && e < NACC)
+      for (int i = c0 + slot; i < c1; i += NSLOT) {
+        const ImgDev& im = imgs[i];
+        double acc = 0.0;
+        for (int it = im.item_begin; it < im.item_end; ++it) acc += partials[(size_t)it * NACC + e];
+        isum[i - c0][e] = acc * px_weight;
+      }
+    __syncthreads();
+    for (int i = c0; i < c1; ++i) {
+      const ImgDev& im = imgs[i];
+      const double* acc = isum[i - c0];
+      if (t == 0) vt += img_const[i];
+      const bool shared = im.wcs[0] == wref[0] && im.wcs[1] == wref[1] && im.wcs[2] == wref[2] && im.wcs[3] == wref[3];
+      if (shared) {
+        if (t < NACC) grp[im.band][t] += acc[t];   // each thread owns its entry: no barrier needed
+        used |= 1u << im.band;
+      } else {
+        if (t == 0) vt += acc[0];
+        project_add(acc, im.band, im.wcs, Hz, Ht, gt);
+      }
     }
-    if (t == 0) vt += img_const[i];
-    const bool shared = im.wcs[0] == wref[0] && im.wcs[1] == wref[1] && im.wcs[2] == wref[2] && im.wcs[3] == wref[3];
-    if (shared) {
-      if (t < NACC) grp[im.band][t] += acc;   // each thread owns its entry: no barrier needed
-      used |= 1u << im.band;
-    } else {
-      if (t < NACC) tmp[t] = acc;
-      __syncthreads();
-      if (t == 0) vt += tmp[0];
-      project_add(tmp, im.band, im.wcs, Hz, Ht, gt);
-    }
+    __syncthreads();   // the chunk's sums are read before the next chunk overwrites them
   }
   for (int b = 0; b < 5; ++b) {
     if (!(used & (1u << b))) continue;
