@@ -87,6 +87,30 @@ __device__ __forceinline__ bf16x8_t row8(const bf16* __restrict__ row, int px, i
   return __builtin_bit_cast(bf16x8_t, o);
 }
 
+// row8 for a shift sh that is the same on every lane: one scalar branch instead of per-lane selects
+// (the same 8 values as row8).
+__device__ __forceinline__ bf16x8_t row8u(const bf16* __restrict__ row, int px, int sh, int wd) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+  const u32x4_t zero = {0u, 0u, 0u, 0u};
+  const u32x4_t mid = *reinterpret_cast<const u32x4_t*>(row + px);
+  if (sh == 0) return __builtin_bit_cast(bf16x8_t, mid);
+  u32x4_t o;
+  if (sh < 0) {
+    const u32x4_t lo = px > 0 ? *reinterpret_cast<const u32x4_t*>(row + px - 8) : zero;
+    o[0] = __builtin_amdgcn_alignbit(mid.x, lo.w, 16u);
+    o[1] = __builtin_amdgcn_alignbit(mid.y, mid.x, 16u);
+    o[2] = __builtin_amdgcn_alignbit(mid.z, mid.y, 16u);
+    o[3] = __builtin_amdgcn_alignbit(mid.w, mid.z, 16u);
+  } else {
+    const u32x4_t hi = px + 8 < wd ? *reinterpret_cast<const u32x4_t*>(row + px + 8) : zero;
+    o[0] = __builtin_amdgcn_alignbit(mid.y, mid.x, 16u);
+    o[1] = __builtin_amdgcn_alignbit(mid.z, mid.y, 16u);
+    o[2] = __builtin_amdgcn_alignbit(mid.w, mid.z, 16u);
+    o[3] = __builtin_amdgcn_alignbit(hi.x, mid.w, 16u);
+  }
+  return __builtin_bit_cast(bf16x8_t, o);
+}
+
 // Per-thread state of an n-run of a convolution operand: the run's image plane 0 and its first
 // pixel (row py, column px, a multiple of 8); fixed over the K loop.
 struct RunState {
@@ -107,7 +131,8 @@ struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img]
     const int img = n >> hwl, p = n & ((1 << hwl) - 1);
     return RunState{X + (((size_t)img * Cin) << hwl), p >> wl, p & ((1 << wl) - 1)};
   }
-  __device__ bf16x8_t b8n(int k, const RunState& r) const {
+  __device__ bf16x8_t b8n(int k0, int kb, const RunState& r) const {
+    const int k = k0 + kb;
     const int ci = k / 9, kk = k - ci * 9;
     const int y = r.py + tap_y(kk) - 1;
     if (y < 0 || y >= (1 << wl)) return zero8();
@@ -115,11 +140,36 @@ struct LdConvFwd {        // Y[co][img*HW+p] = sum_{ci,kk} W[co][ci*9+kk] X[img]
   }
 };
 
+// The same product with K ordered tap-major, k = kk*Cin + ci, for Cin a power of two of at least
+// 32: a 32-deep K step (K splits start at multiples of 32) then lies within one tap, so the tap's
+// row and column shift are the same on every lane.  W is the layer's weights re-laid as
+// W[co][kk*Cin + ci] (k_wf).
+struct LdConvFwdT {
+  static constexpr bool kRunN = true;
+  const bf16* W;
+  const bf16* X;
+  int Cin, cl, hwl, wl;   // Cin = 2^cl
+  __device__ bf16x8_t a8(int m, int k, int kend) const {
+    const size_t o = (size_t)m * Cin * 9 + k;
+    return load8(W + o, kend - k, (o & 7) == 0);
+  }
+  __device__ RunState run(int n) const {
+    const int img = n >> hwl, p = n & ((1 << hwl) - 1);
+    return RunState{X + (((size_t)img * Cin) << hwl), p >> wl, p & ((1 << wl) - 1)};
+  }
+  __device__ bf16x8_t b8n(int k0, int kb, const RunState& r) const {
+    const int kk = k0 >> cl, ci = (k0 & (Cin - 1)) + kb;
+    const int y = r.py + tap_y(kk) - 1;
+    if (y < 0 || y >= (1 << wl)) return zero8();
+    return row8u(r.plane0 + ((size_t)ci << hwl) + ((size_t)y << wl), r.px, tap_x(kk) - 1, 1 << wl);
+  }
+};
+
 struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img][co][p - off(kk)]
   static constexpr bool kRunN = true;
-  const bf16* Wt;         // the layer's weights as Wt[ci][co*9+kk]
+  const bf16* Wt;         // the layer's weights as Wt[ci][kk*Cout+co] (k_wt)
   const bf16* dY;
-  int Cin, Cout, hwl, wl;
+  int Cin, Cout, col, hwl, wl;   // K ordered tap-major, k = kk*Cout + co, Cout = 2^col >= 32 (as LdConvFwdT)
   __device__ bf16x8_t a8(int m, int k, int kend) const {
     const size_t o = (size_t)m * Cout * 9 + k;
     return load8(Wt + o, kend - k, (o & 7) == 0);
@@ -128,11 +178,11 @@ struct LdConvDgrad {      // dX[ci][img*HW+p] = sum_{co,kk} W[co][ci][kk] dY[img
     const int img = n >> hwl, p = n & ((1 << hwl) - 1);
     return RunState{dY + (((size_t)img * Cout) << hwl), p >> wl, p & ((1 << wl) - 1)};
   }
-  __device__ bf16x8_t b8n(int k, const RunState& r) const {
-    const int co = k / 9, kk = k - co * 9;
+  __device__ bf16x8_t b8n(int k0, int kb, const RunState& r) const {
+    const int kk = k0 >> col, co = (k0 & (Cout - 1)) + kb;
     const int y = r.py - tap_y(kk) + 1;
     if (y < 0 || y >= (1 << wl)) return zero8();
-    return row8(r.plane0 + ((size_t)co << hwl) + ((size_t)y << wl), r.px, 1 - tap_x(kk), 1 << wl);
+    return row8u(r.plane0 + ((size_t)co << hwl) + ((size_t)y << wl), r.px, 1 - tap_x(kk), 1 << wl);
   }
 };
 
@@ -266,7 +316,7 @@ __global__ __launch_bounds__(256) void k_gemm(LD ld, int M, int N, int K, int kc
     if constexpr (LD::kRunN) {
       const int k = k0 + kb;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) bn[r] = (rv[r] && k < kend) ? ld.b8n(k, rs[r]) : zero8();
+      for (int r = 0; r < NR; ++r) bn[r] = (rv[r] && k < kend) ? ld.b8n(k0, kb, rs[r]) : zero8();
     } else {
       const int k = k0 + ak;
 #pragma unroll
@@ -525,13 +575,23 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __re
   }
 }
 
-// One convolution layer's weights re-laid for the data-gradient product: Wt[ci][co*9+kk] =
-// W[co][ci*9+kk].
+// One convolution layer's weights re-laid for the data-gradient product, tap-major:
+// Wt[ci][kk*Cout+co] = W[co][ci*9+kk].
 __global__ void k_wt(const bf16* __restrict__ W, int Cin, int Cout, bf16* __restrict__ Wt) {
   const int n = Cin * Cout * 9;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int ci = i / (Cout * 9), r = i - ci * Cout * 9, co = r / 9, kk = r - co * 9;
+    const int ci = i / (Cout * 9), r = i - ci * Cout * 9, kk = r / Cout, co = r - kk * Cout;
     Wt[i] = W[((size_t)co * Cin + ci) * 9 + kk];
+  }
+}
+
+// One convolution layer's weights re-laid for the tap-major forward product:
+// Wf[co][kk*Cin+ci] = W[co][ci*9+kk].
+__global__ void k_wf(const bf16* __restrict__ W, int Cin, int Cout, bf16* __restrict__ Wf) {
+  const int n = Cin * Cout * 9;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int co = i / (Cin * 9), r = i - co * Cin * 9, kk = r / Cin, ci = r - kk * Cin;
+    Wf[i] = W[((size_t)co * Cin + ci) * 9 + kk];
   }
 }
 
@@ -614,6 +674,9 @@ inline int ilog2(int v) {
   return l;
 }
 
+// a convolution product over c channels may order K tap-major: c a power of two of at least 32
+inline bool tap_major(int c) { return c >= 32 && (c & (c - 1)) == 0; }
+
 }  // namespace
 
 // ============================================================ network object (host side)
@@ -652,6 +715,7 @@ struct NetState {
   float* g = nullptr;     // gradient
   bf16* wb = nullptr;     // BF16 weights
   bf16* wt = nullptr;     // convolution weights re-laid for the data-gradient products (conv offsets)
+  bf16* wf = nullptr;     // convolution weights re-laid for the tap-major forward products (conv offsets)
   int step = 0;
   int cap_batch = 0;
   // activations (BF16) and gradients for cap_batch images
@@ -670,6 +734,7 @@ hipError_t net_alloc(NetState* n) {
   if ((e = hipMalloc(&n->g, P * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->wb, P * 2)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->wt, n->L.off[8] * 2)) != hipSuccess) return e;
+  if ((e = hipMalloc(&n->wf, n->L.off[8] * 2)) != hipSuccess) return e;
   if ((e = hipMemset(n->m, 0, P * 4)) != hipSuccess) return e;
   if ((e = hipMemset(n->v, 0, P * 4)) != hipSuccess) return e;
   if ((e = hipMalloc(&n->bpart, sizeof(float) * 128 * BP_PARTS)) != hipSuccess) return e;
@@ -697,6 +762,7 @@ void net_free(NetState* n) {
     if (q) (void)hipFree(q);
   if (n->wb) (void)hipFree(n->wb);
   if (n->wt) (void)hipFree(n->wt);
+  if (n->wf) (void)hipFree(n->wf);
 }
 
 static const int kSplitTarget = 1024;   // aim for about this many GEMM blocks
@@ -751,10 +817,16 @@ hipError_t net_forward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
     const size_t M = L.cout[l], N = (size_t)B * HW, K = (size_t)L.cin[l] * 9;
     int S = splits_for(M, N, K, n->c_cap, tile_n<LdConvFwd>());
     const int wl = ilog2(L.hw[l]);
-    LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], 2 * wl, wl};
-    if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, EpConvFwd{n->w + L.off[2 * l + 1], n->r[l], 2 * wl})) !=
-        hipSuccess)
-      return e;
+    const EpConvFwd ep{n->w + L.off[2 * l + 1], n->r[l], 2 * wl};
+    if (tap_major(L.cin[l])) {
+      hipLaunchKernelGGL(k_wf, dim3(nblk((size_t)L.cin[l] * L.cout[l] * 9)), dim3(256), 0, st, n->wb + L.off[2 * l],
+                         L.cin[l], L.cout[l], n->wf + L.off[2 * l]);
+      LdConvFwdT ld{n->wf + L.off[2 * l], in, L.cin[l], ilog2(L.cin[l]), 2 * wl, wl};
+      if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, ep)) != hipSuccess) return e;
+    } else {
+      LdConvFwd ld{n->wb + L.off[2 * l], in, L.cin[l], 2 * wl, wl};
+      if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st, ep)) != hipSuccess) return e;
+    }
     if (S > 1)   // split products: the epilogue sums the splits
       hipLaunchKernelGGL(k_ep_conv_fwd, dim3(nblk(M * N)), dim3(256), 0, st, n->C, S, L.cout[l], B, HW,
                          n->w + L.off[2 * l + 1], n->r[l]);
@@ -840,7 +912,8 @@ hipError_t net_backward(NetState* n, const bf16* x_in, int B, hipStream_t st) {
       hipLaunchKernelGGL(k_wt, dim3(nblk((size_t)L.cin[l] * L.cout[l] * 9)), dim3(256), 0, st, n->wb + L.off[2 * l],
                          L.cin[l], L.cout[l], n->wt + L.off[2 * l]);
       const int wl = ilog2(L.hw[l]);
-      LdConvDgrad ld{n->wt + L.off[2 * l], n->dzb, L.cin[l], L.cout[l], 2 * wl, wl};
+      if (!tap_major(L.cout[l])) return hipErrorInvalidValue;   // the layout has Cout >= 32 here
+      LdConvDgrad ld{n->wt + L.off[2 * l], n->dzb, L.cin[l], L.cout[l], ilog2(L.cout[l]), 2 * wl, wl};
       if ((e = gemm(ld, (int)M, (int)N, (int)K, n->C, S, st)) != hipSuccess) return e;
       const int Hp = L.hw[l - 1];
       hipLaunchKernelGGL(k_pool_relu_bwd, dim3(nblk((size_t)B * L.cout[l - 1] * Hp * Hp)), dim3(256), 0, st, n->C, S,
