@@ -522,6 +522,9 @@ def main():
     ap.add_argument("--fp64-sums", type=int, choices=(0, 1), default=None,
                     help="value+gradient+Hessian kernel: every pixel term summed in FP64 (1) or FP32 lane sums "
                          "over up to 16 tile steps before FP64 (0); default: the library's")
+    ap.add_argument("--field-chunk-px", type=int, default=4096,
+                    help="crowded field, colour sweeps: pixels per work item after autotuning (0: the "
+                         "autotuner's choice)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: read the launch shapes from it when it has an entry for this "
                          "device and workload, else time them and add one (runs that must share a launch "
@@ -1055,6 +1058,12 @@ def field_bench(args, ctx, net, sur_info, log):
         th0[:, 0:2] = sb.u_cat
         th_start, _ = ctx.start(b0, th0, cb.default_opts(init_mode=cb.INIT_PLAIN))
         tune = ctx.autotune(b0, th_start, cache_path=args.tune_cache)
+        # the sweep's launches hold one colour's few hundred sources (fewer as they converge), where
+        # the tuner's single launch over its whole sample does not reflect the tail of the
+        # persistent grid: keep the library's 4,096-pixel work items (several per block) there
+        if args.schedule == "colour" and args.field_chunk_px > 0:
+            ctx.set_option(cb.OPT_CHUNK_PX, args.field_chunk_px)
+            tune["chunk_px"] = args.field_chunk_px
         log(f"autotune: {tune}")
         del b0
     for w in range(args.warmup):
